@@ -1,0 +1,140 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle.
+
+This module holds no arithmetic of the method: it draws random numbers and
+describes workloads (sizes, boundary types, wall speeds, Reynolds numbers).
+Everything the method computes from these inputs (relaxation times,
+equilibria, steps) is done separately by the HIP library and by the oracle.
+
+Random numbers come from SplitMix64 (Steele, Lea and Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014), used as a counter-based
+generator: value k of stream ``seed`` is mix64(seed + (k + 1) * gamma).  A
+uniform double in [0, 1) takes the top 53 bits.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(seed: int, count: int, offset: int = 0) -> np.ndarray:
+    """``count`` consecutive SplitMix64 outputs of stream ``seed``."""
+    with np.errstate(over="ignore"):
+        k = np.arange(offset + 1, offset + count + 1, dtype=np.uint64)
+        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + k * _GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        return z ^ (z >> np.uint64(31))
+
+
+def uniform(seed: int, count: int, offset: int = 0) -> np.ndarray:
+    """Uniform doubles in [0, 1) from the top 53 bits of SplitMix64."""
+    return (splitmix64(seed, count, offset) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+def velocity_perturbation(n, amplitude: float, seed: int, dims: int = 3) -> np.ndarray:
+    """u of shape (3, nz, ny, nx): each of the first ``dims`` components iid
+    uniform in [-amplitude, amplitude], component a drawn from offset a*cells."""
+    nx, ny, nz = n
+    cells = nx * ny * nz
+    u = np.zeros((3, cells))
+    for a in range(dims):
+        u[a] = amplitude * (2.0 * uniform(seed, cells, offset=a * cells) - 1.0)
+    return u.reshape(3, nz, ny, nx)
+
+
+def random_populations(q: int, n, seed: int, lo: float = 0.01, hi: float = 0.2) -> np.ndarray:
+    """Arbitrary positive populations (q, nz, ny, nx) uniform in [lo, hi): a
+    generic, far-from-equilibrium state for single-step checks."""
+    nx, ny, nz = n
+    cells = nx * ny * nz
+    return (lo + (hi - lo) * uniform(seed, q * cells)).reshape(q, nz, ny, nx)
+
+
+def shear_wave(n, amplitude: float, axis_u: int = 0, axis_k: int = 1, periods: int = 1) -> np.ndarray:
+    """u of shape (3, nz, ny, nx) with u[axis_u] = A sin(2 pi m j / L) along
+    axis_k (node index j, box length L, m periods)."""
+    nx, ny, nz = n
+    L = n[axis_k]
+    j = np.arange(L)
+    prof = amplitude * np.sin(2.0 * np.pi * periods * j / L)
+    shape = [1, 1, 1]
+    shape[2 - axis_k] = L
+    u = np.zeros((3, nz, ny, nx))
+    u[axis_u] = np.broadcast_to(prof.reshape(shape), (nz, ny, nx))
+    return u
+
+
+# ---------------------------------------------------------------------------
+# Workloads.  Face order -x,+x,-y,+y,-z,+z; 0 periodic, 1 wall.
+# ---------------------------------------------------------------------------
+PERIODIC, WALL = 0, 1
+
+
+@dataclass
+class Workload:
+    name: str
+    q: int
+    n: tuple
+    bc: tuple
+    wall_u: tuple = ((0.0, 0.0, 0.0),) * 6
+    reynolds: float = None        # with lid_speed and n_across, fixes tau
+    lid_speed: float = 0.0
+    n_across: int = 0
+    tau: float = None             # given directly when reynolds is None
+    force: tuple = (0.0, 0.0, 0.0)
+    steps: int = 0
+    sensor_every: int = 1
+    theta_refine: float = 1e-3
+    theta_coarsen: float = 5e-4
+    storage: str = "f32"
+    init: str = "rest"            # "rest" or "perturbed"
+    perturb_amp: float = 0.0
+    seed: int = 1
+    block: tuple = None
+    notes: str = ""
+
+    def __post_init__(self):
+        if self.block is None:
+            self.block = (8, 8, 1) if self.q == 9 else (8, 8, 8)
+
+    @property
+    def cells(self):
+        return self.n[0] * self.n[1] * self.n[2]
+
+
+def _lid(speed):
+    wu = [[0.0, 0.0, 0.0] for _ in range(6)]
+    wu[3][0] = speed          # +y face moves in +x
+    return tuple(tuple(v) for v in wu)
+
+
+def cavity2d(n=64, lid=0.1, re=100.0, steps=2000, sensor_every=100):
+    return Workload(name=f"cavity2d_d2q9_{n}x{n}_f64", q=9, n=(n, n, 1),
+                    bc=(WALL, WALL, WALL, WALL, PERIODIC, PERIODIC), wall_u=_lid(lid),
+                    reynolds=re, lid_speed=lid, n_across=n, steps=steps,
+                    sensor_every=sensor_every, storage="f64")
+
+
+def cavity3d(n=128, lid=0.05, re=1000.0, steps=5000, sensor_every=1, storage="f32"):
+    return Workload(name=f"cavity3d_d3q19_{n}^3_{storage}", q=19, n=(n, n, n), bc=(WALL,) * 6,
+                    wall_u=_lid(lid), reynolds=re, lid_speed=lid, n_across=n, steps=steps,
+                    sensor_every=sensor_every, storage=storage)
+
+
+def periodic_box(n=64, amp=0.01, tau=0.8, steps=5000, seed=1, storage="f32"):
+    return Workload(name=f"box_d3q19_{n}^3_{storage}", q=19, n=(n, n, n), bc=(PERIODIC,) * 6,
+                    tau=tau, steps=steps, storage=storage, init="perturbed", perturb_amp=amp,
+                    seed=seed)
+
+
+def channel3d(n=256, g=1e-6, tau=0.8, steps=10000, storage="f32", nx=None, nz=None):
+    nx = n if nx is None else nx
+    nz = n if nz is None else nz
+    return Workload(name=f"channel_d3q19_{nx}x{n}x{nz}_{storage}", q=19, n=(nx, n, nz),
+                    bc=(PERIODIC, PERIODIC, WALL, WALL, PERIODIC, PERIODIC), tau=tau,
+                    force=(g, 0.0, 0.0), steps=steps, storage=storage)

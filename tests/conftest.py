@@ -1,0 +1,25 @@
+"""Shared pytest configuration.
+
+Marker ``gpu``: the test needs an MI355X (gfx950) and the built HIP library;
+everything else runs on the CPU.
+"""
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X GPU and the built HIP library")
+
+
+@pytest.fixture(scope="session")
+def orc():
+    import oracle
+    if not os.path.exists(os.path.join(ROOT, "oracle", "liborc.so")):
+        oracle.build()
+    return oracle
