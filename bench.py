@@ -1,0 +1,165 @@
+"""Throughput of the fused D3Q19 step + kinetic sensor on one MI355X.
+
+Default workload: the 128^3 D3Q19 lid-driven cavity in float32 (lid 0.05,
+Re 1000, halfway bounce-back walls), with the sensor, its 8^3 block maxima
+and the refine/coarsen flags evaluated at every step.  A "step" is one
+launch of the fused kernel over the whole grid.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload cavity128|cavity256|channel256]
+                  [--storage f32|f32s|f64] [--no-cpu-baseline]
+
+MLUPS = cells * K / t / 1e6.  The roofline entry prices the fused kernel at
+its algorithmic traffic, one read and one write of every population per cell
+update (2 * q * bytes per value), against the 8 TB/s HBM3E peak.  The CPU
+baseline is the FP64 oracle timed on the host on a short run of the same
+workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _workload(name, storage):
+    import lbm_inputs
+    if name == "cavity128":
+        return lbm_inputs.cavity3d(n=128, storage=storage)
+    if name == "cavity256":
+        return lbm_inputs.cavity3d(n=256, storage=storage)
+    if name == "channel256":
+        return lbm_inputs.channel3d(n=256, storage=storage)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def _traffic_from_profile(kernel_tag):
+    """HBM bytes per launch measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE,
+    scaled by a copy-kernel calibration), read from the committed summary if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_tag}.txt")
+    if not os.path.exists(path):
+        return None
+    src = os.path.join(ROOT, "paper_1507_06767_amd", "csrc", "step_kernel.hpp")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != digest:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(w, tau, sample_steps):
+    """The FP64 oracle on the same workload, all host threads, a short run."""
+    import oracle
+    G = oracle.Grid(q=w.q, n=w.n, bc=w.bc, wall_u=w.wall_u, tau=tau, force=w.force)
+    S = G.equilibrium_state()
+    S, _ = G.run(S, 0, 1, 1)                   # first touch of the work arrays
+    t0 = time.perf_counter()
+    S, _ = G.run(S, 1, sample_steps, w.sensor_every)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(w.cells * sample_steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{sample_steps} steps of the same {w.n[0]}x{w.n[1]}x{w.n[2]} workload in FP64, "
+                      f"sensor every step, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="cavity128")
+    ap.add_argument("--storage", default="f32", choices=["f32", "f32s", "f64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the domain would shard into z-slabs; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1507_06767_amd as lbm
+
+    storage = {"f32": lbm.LBM_F32, "f32s": lbm.LBM_F32_SHIFTED, "f64": lbm.LBM_F64}[args.storage]
+    w = _workload(args.workload, args.storage)
+    if w.reynolds is not None:
+        st, tau = lbm.lbm_tau_from_reynolds(w.lid_speed, w.n_across, w.reynolds)
+        assert st == 0
+    else:
+        tau = w.tau
+    desc = lbm.make_desc(w.q, w.n, w.bc, tau, storage=storage, wall_u=w.wall_u, force=w.force,
+                         theta_refine=w.theta_refine, theta_coarsen=w.theta_coarsen)
+    torch.cuda.set_device(0)
+    blk = lbm.Blocks(desc, device="cuda:0")
+    stream = blk.stream
+    every = w.sensor_every
+
+    blk.step_n(args.warmup, every)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    start.record(stream)
+    blk.step_n(args.steps, every)
+    end.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms = start.elapsed_time(end)
+    bm, fl, k, nonfinite = blk.sensor_flags()
+
+    elem = 8 if storage == lbm.LBM_F64 else 4
+    bytes_per_update = 2 * w.q * elem
+    sec = ms / 1e3
+    mlups = w.cells * args.steps / sec / 1e6
+    per_launch_s = sec / args.steps
+    achieved = bytes_per_update * w.cells / per_launch_s / 1e9
+    tag = f"{args.workload}_{args.storage}"
+    traffic = _traffic_from_profile(tag)
+
+    result = {
+        "metric": "MLUPS and % HBM roofline for D3Q19 step+sensor; flag agreement vs FP64 oracle",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage,
+        "data": "synthetic",
+        "config": {"workload": w.name, "lattice": f"D{3 if w.q == 19 else 2}Q{w.q}",
+                   "extent": list(w.n), "tau": tau, "sensor": "L2 ratio, 8^3 block max + flags",
+                   "sensor_every": every, "theta_refine": w.theta_refine},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "algorithmic_bytes_per_launch": bytes_per_update * w.cells},
+        "last_sensor_step": k,
+        "refine_blocks": int((fl == 1).sum()),
+        "nonfinite": bool(nonfinite),
+        "wall_s": round(t_wall, 3),
+    }
+    blk.close()
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(w, tau, args.cpu_sample_steps)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,189 @@
+/*
+ * lbm.h -- C interface of the MI355X lattice Boltzmann step with the kinetic
+ * mesh-refinement sensor (Thorimbert et al., "Local mesh refinement sensor for
+ * the lattice Boltzmann method", arXiv:1507.06767).
+ *
+ * One handle owns one uniform grid of cells.  Each step advances the BGK
+ * lattice Boltzmann equation (Sec. 2.2, Eq. bgklb with the equilibrium of
+ * Eq. feq_i and the moments of Eqs. rho and u) by one collide-and-stream
+ * cycle, fused on the GPU with the kinetic sensor of Sec. 3.2 (Eq. sensor /
+ * Eq. kkn, or the L2 ratio ||f^neq||_2 / ||f^eq||_2), its maximum over sensor
+ * blocks and the refine / keep / coarsen decision of Sec. 3.4.
+ *
+ * Conventions that hold for every entry point:
+ *   - Every function returns an lbm_status (0 on success, < 0 on error) and
+ *     never aborts or throws; on error, lbm_last_error() returns a message
+ *     for the calling thread.
+ *   - Device memory is OWNED BY THE CALLER.  The library never allocates
+ *     device memory: the caller sizes the five buffers with
+ *     lbm_required_bytes(), allocates them (for instance as torch tensors)
+ *     and keeps them alive until lbm_destroy().  Host arrays are only read
+ *     or written during the call that receives them.
+ *   - Work is enqueued on the caller's HIP stream (lbm_desc.stream; NULL is
+ *     the null stream).  lbm_step_n() is asynchronous; the calls that return
+ *     host data synchronise that stream.  One handle must not be used from
+ *     two host threads at once.
+ *   - Host population arrays are float64, shape [q][nz][ny][nx] (x fastest),
+ *     in the velocity order below.  Host macroscopic arrays are float64:
+ *     rho [nz][ny][nx], u [3][nz][ny][nx] (u_z = 0 in 2D).
+ *   - The stored state is the set of post-collision populations S_k.  Step k
+ *     (1-based) computes S_k = C(T(S_{k-1})): T streams with the boundary
+ *     conditions, C is the BGK collision with Guo's body-force term.  The
+ *     sensor of step k is evaluated on the pre-collision populations
+ *     T(S_{k-1}).
+ *
+ * Velocity order (opposite of i: i+1 for odd i, i-1 for even i > 0):
+ *   D2Q9 : 0 (0,0) 1 (1,0) 2 (-1,0) 3 (0,1) 4 (0,-1) 5 (1,1) 6 (-1,-1)
+ *          7 (1,-1) 8 (-1,1)
+ *   D3Q19: 0 (0,0,0) 1 (1,0,0) 2 (-1,0,0) 3 (0,1,0) 4 (0,-1,0) 5 (0,0,1)
+ *          6 (0,0,-1) 7 (1,1,0) 8 (-1,-1,0) 9 (1,-1,0) 10 (-1,1,0)
+ *          11 (1,0,1) 12 (-1,0,-1) 13 (1,0,-1) 14 (-1,0,1) 15 (0,1,1)
+ *          16 (0,-1,-1) 17 (0,1,-1) 18 (0,-1,1)
+ *
+ * Boundary faces, in the order -x,+x,-y,+y,-z,+z, are periodic or walls.
+ * Walls use halfway bounce-back: all n cells along an axis are fluid and the
+ * wall lies half a cell beyond the outer ones.  A link pulled from beyond a
+ * wall returns the opposite population of the same cell plus the moving-wall
+ * term 6 w_i rho0 (xi_i . u_w) (the moving bounce-back rule cited in
+ * Sec. 4.1), where u_w is the sum of the wall velocities of every wall face
+ * the link crosses (so a moving lid acts on the links through its edges and
+ * corners too, which keeps mass exactly conserved).
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_ABI_VERSION 1u
+
+typedef int32_t lbm_status;
+enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,      /* bad argument or descriptor; nothing was enqueued */
+    LBM_ENOTSUP = -2,     /* valid but not supported by this build */
+    LBM_EHIP = -3,        /* a HIP call failed; lbm_last_error() has its text */
+    LBM_ESTATE = -4,      /* call not valid in the handle's state */
+    LBM_ENONFINITE = -5   /* a sensor block holds a NaN or Inf (data still written) */
+};
+
+enum { LBM_D2Q9 = 9, LBM_D3Q19 = 19 };                          /* lbm_desc.lattice */
+enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F32_SHIFTED = 2 };         /* lbm_desc.storage */
+enum { LBM_SENSOR_L2 = 0, LBM_SENSOR_KKN = 1 };                 /* lbm_desc.sensor_kind */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_WALL = 1 };                  /* lbm_desc.face_bc[] */
+enum { LBM_BUF_F_A = 0, LBM_BUF_F_B = 1, LBM_BUF_BLOCK_MAX = 2,  /* lbm_desc.buf[] */
+       LBM_BUF_FLAGS = 3, LBM_BUF_SCRATCH = 4, LBM_NBUF = 5 };
+
+/* Refinement decision per sensor block. */
+enum { LBM_FLAG_COARSEN = -1, LBM_FLAG_KEEP = 0, LBM_FLAG_REFINE = 1, LBM_FLAG_NONFINITE = 2 };
+
+typedef struct lbm_blocks lbm_blocks;   /* opaque handle */
+
+typedef struct {
+    uint32_t abi_version;   /* LBM_ABI_VERSION */
+    int32_t lattice;        /* LBM_D2Q9 or LBM_D3Q19 */
+    int32_t storage;        /* LBM_F64: populations and arithmetic in float64.
+                               LBM_F32: float32 populations f_i, float32 arithmetic.
+                               LBM_F32_SHIFTED: float32 stores f_i - w_i rho0,
+                               float32 arithmetic (same bytes, finer rounding). */
+    int32_t sensor_kind;    /* LBM_SENSOR_L2: ||f^neq||_2 / ||f^eq||_2;
+                               LBM_SENSOR_KKN: (1/q) sum_i |f^neq_i / f^eq_i| (Eq. kkn) */
+    int32_t extent[3];      /* cells along x, y, z; extent[2] == 1 for D2Q9;
+                               extent[0]*extent[1]*extent[2] < 2^31 */
+    int32_t block[3];       /* sensor block edge: {8,8,1} for D2Q9, {8,8,8} for
+                               D3Q19 (other sizes: LBM_ENOTSUP).  Blocks start at
+                               the origin; partial blocks at the far faces are
+                               allowed and take the maximum of the cells they hold. */
+    int32_t face_bc[6];     /* -x,+x,-y,+y,-z,+z: LBM_BC_PERIODIC or LBM_BC_WALL; a
+                               periodic face needs a periodic opposite face; the z
+                               faces are periodic for D2Q9 */
+    double wall_u[6][3];    /* wall velocity per face (ignored on periodic faces) */
+    double tau;             /* BGK relaxation time (Eq. bgklb), > 1/2 */
+    double rho0;            /* reference density: initial density, wall density of
+                               the moving-wall term, and shift of LBM_F32_SHIFTED */
+    double force[3];        /* body-force density (Guo scheme); zeros mean none */
+    double theta_refine;    /* flag REFINE iff block max > theta_refine */
+    double theta_coarsen;   /* flag COARSEN iff block max < theta_coarsen
+                               (<= theta_refine) */
+    void *buf[LBM_NBUF];    /* caller-owned device buffers, see lbm_required_bytes();
+                               F_A and F_B must be 256-byte aligned; no two overlap */
+    size_t buf_bytes[LBM_NBUF];  /* their sizes in bytes, >= the required sizes */
+    void *stream;           /* hipStream_t for all work of this handle */
+} lbm_desc;
+
+/* Sizes in bytes of the five device buffers for descriptor d (its buf and
+ * buf_bytes fields are ignored).  Pure host computation, no HIP call.
+ *   F_A, F_B   : two population arrays (ping-pong), q padded planes each;
+ *   BLOCK_MAX  : one float32 (F32 storages) or float64 (F64) per sensor block;
+ *   FLAGS      : one int8 per sensor block;
+ *   SCRATCH    : staging for host transfers and the conservation partial sums.
+ * Returns LBM_EINVAL / LBM_ENOTSUP for a bad descriptor. */
+lbm_status lbm_required_bytes(const lbm_desc *d, size_t bytes[LBM_NBUF]);
+
+/* Validates d (including buffer sizes and alignment), creates a handle and
+ * writes the initial state S_0 into F_A: f0_host (float64 [q][cells]) if not
+ * NULL, otherwise the rest state f_i = w_i rho0.  Synchronises the stream.
+ * The step counter starts at 0.  *out is set only on success. */
+lbm_status lbm_create_blocks(const lbm_desc *d, const double *f0_host, lbm_blocks **out);
+
+/* Enqueues n >= 0 steps k = s+1 .. s+n, s being the current step counter.
+ * Step k also evaluates the sensor, its block maxima and the flags when
+ * sensor_every > 0 and k % sensor_every == 0 (sensor_every == 0: never).
+ * Asynchronous: returns once the launches are enqueued. */
+lbm_status lbm_step_n(lbm_blocks *h, int64_t n, int32_t sensor_every);
+
+/* Synchronises the stream and returns the block maxima (as float64) and the
+ * flags of the latest step that evaluated the sensor, and that step's index.
+ * Any of the host pointers may be NULL.  Blocks are ordered [nbz][nby][nbx].
+ * LBM_ESTATE if no sensor step has run since the state was last set;
+ * LBM_ENONFINITE if some block maximum is NaN or Inf (outputs still written). */
+lbm_status lbm_sensor_flags(lbm_blocks *h, double *block_max_host, int8_t *flags_host,
+                            int64_t *step_index);
+
+/* Synchronises the stream and returns the macroscopic fields of the stored
+ * state computed in float64: rho = sum_i S_i, u = (sum_i xi_i S_i - F/2) / rho
+ * (the velocity of the last collision, Eqs. rho and u).  Either pointer may
+ * be NULL. */
+lbm_status lbm_get_macros(lbm_blocks *h, double *rho_host, double *u_host);
+
+/* Stored populations S_k as float64 [q][cells] (checkpointing, tests). */
+lbm_status lbm_get_populations(lbm_blocks *h, double *f_host);
+
+/* Replaces the stored state by f_host (float64 [q][cells], converted to the
+ * storage type).  Non-finite values are accepted; the next sensor step flags
+ * their blocks LBM_FLAG_NONFINITE.  Synchronises the stream. */
+lbm_status lbm_set_populations(lbm_blocks *h, const double *f_host);
+
+/* Replaces the stored state by the equilibrium f^eq(rho, u) of Eq. feq_i,
+ * computed on the GPU in float64 from rho_host [cells] (NULL: rho0 everywhere)
+ * and u_host [3][cells] (NULL: at rest).  Synchronises the stream. */
+lbm_status lbm_set_equilibrium(lbm_blocks *h, const double *rho_host, const double *u_host);
+
+/* Step counter (number of steps taken since it was last set). */
+lbm_status lbm_get_step(lbm_blocks *h, int64_t *step);
+lbm_status lbm_set_step(lbm_blocks *h, int64_t step);
+
+/* Totals over all cells of the stored state, accumulated in float64 by a
+ * fixed-order two-pass tree (bitwise reproducible): out[0] = sum rho,
+ * out[1..3] = sum_i xi_i S_i summed over cells.  Synchronises the stream. */
+lbm_status lbm_conservation(lbm_blocks *h, double out[4]);
+
+/* tau = nu / c_s^2 + 1/2 with nu = u * n_across / re (Eq. nu_omega, c_s^2 = 1/3). */
+lbm_status lbm_tau_from_reynolds(double u, double n_across, double re, double *tau);
+
+/* Synchronises the stream and releases the handle; caller buffers are left
+ * untouched.  NULL is a no-op. */
+void lbm_destroy(lbm_blocks *h);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -176,7 +176,8 @@ class Grid:
         p.sensor_kind = int(self.sensor_kind)
         p.theta_refine, p.theta_coarsen = float(self.theta_refine), float(self.theta_coarsen)
         self._p = p
-        self._perm = abi_permutation(self.q)
+        self._perm = abi_permutation(self.q)      # interface index -> oracle index
+        self._inv = np.argsort(self._perm)         # oracle index -> interface index
 
     # -- layout -----------------------------------------------------------------
     @property
@@ -194,9 +195,7 @@ class Grid:
     def to_internal(self, f_abi: np.ndarray) -> np.ndarray:
         """(q, nz, ny, nx) interface order -> (cells, q) oracle order."""
         f_abi = np.asarray(f_abi, dtype=np.float64).reshape(self.q, self.cells)
-        out = np.empty((self.cells, self.q))
-        out[:, self._perm] = f_abi.T
-        return np.ascontiguousarray(out)
+        return np.ascontiguousarray(f_abi[self._inv].T)
 
     def to_abi(self, f_int: np.ndarray) -> np.ndarray:
         """(cells, q) oracle order -> (q, nz, ny, nx) interface order."""

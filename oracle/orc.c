@@ -398,15 +398,17 @@ int64_t orc_run(const orc_params *p, double *S, double *work, int64_t k0, int64_
     for (int a = 0; a < 3; ++a) nb[a] = (p->n[a] + p->block[a] - 1) / p->block[a];
     const int64_t NB = (int64_t)nb[0] * nb[1] * nb[2];
     int64_t nsens = 0;
+    double *cur = S, *next = S2;
     for (int64_t k = k0 + 1; k <= k0 + n; ++k) {
         int sense = sensor_every > 0 && (k % sensor_every) == 0;
-        if (orc_step(p, S, S2, f, sense ? s : NULL) != 0) return -1;
-        memcpy(S, S2, sizeof(double) * N * L.q);
+        if (orc_step(p, cur, next, f, sense ? s : NULL) != 0) return -1;
+        double *t = cur; cur = next; next = t;
         if (sense) {
             if (bmax_hist) orc_block_max(p, s, bmax_hist + nsens * NB);
             ++nsens;
         }
     }
+    if (cur != S) memcpy(S, cur, sizeof(double) * N * L.q);
     return nsens;
 }
 

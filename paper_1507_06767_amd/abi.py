@@ -1,0 +1,205 @@
+"""ctypes binding of include/lbm.h: same names, argument marshalling only.
+
+Every function returns the C status code (0 = LBM_OK, < 0 = error), plus any
+output the C function writes through a pointer.  Host arrays are numpy
+arrays; their dtype, contiguity and size are checked here before the call
+so that the C side never writes past a host buffer.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liblbm.so")
+
+LBM_ABI_VERSION = 1
+LBM_OK, LBM_EINVAL, LBM_ENOTSUP, LBM_EHIP, LBM_ESTATE, LBM_ENONFINITE = 0, -1, -2, -3, -4, -5
+LBM_D2Q9, LBM_D3Q19 = 9, 19
+LBM_F64, LBM_F32, LBM_F32_SHIFTED = 0, 1, 2
+LBM_SENSOR_L2, LBM_SENSOR_KKN = 0, 1
+LBM_BC_PERIODIC, LBM_BC_WALL = 0, 1
+LBM_NBUF = 5
+STATUS_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOTSUP", -3: "LBM_EHIP",
+                -4: "LBM_ESTATE", -5: "LBM_ENONFINITE"}
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class lbm_desc(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_uint32),
+        ("lattice", ctypes.c_int32),
+        ("storage", ctypes.c_int32),
+        ("sensor_kind", ctypes.c_int32),
+        ("extent", ctypes.c_int32 * 3),
+        ("block", ctypes.c_int32 * 3),
+        ("face_bc", ctypes.c_int32 * 6),
+        ("wall_u", (ctypes.c_double * 3) * 6),
+        ("tau", ctypes.c_double),
+        ("rho0", ctypes.c_double),
+        ("force", ctypes.c_double * 3),
+        ("theta_refine", ctypes.c_double),
+        ("theta_coarsen", ctypes.c_double),
+        ("buf", ctypes.c_void_p * LBM_NBUF),
+        ("buf_bytes", ctypes.c_size_t * LBM_NBUF),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _load_library():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(
+            f"{_LIB_PATH} is missing: build the HIP library first "
+            "(python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(_LIB_PATH)
+    H = ctypes.c_void_p
+    D = ctypes.POINTER(lbm_desc)
+    dp = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "lbm_required_bytes": [D, ctypes.POINTER(ctypes.c_size_t)],
+        "lbm_create_blocks": [D, dp, ctypes.POINTER(H)],
+        "lbm_step_n": [H, ctypes.c_int64, ctypes.c_int32],
+        "lbm_sensor_flags": [H, dp, ctypes.POINTER(ctypes.c_int8), ctypes.POINTER(ctypes.c_int64)],
+        "lbm_get_macros": [H, dp, dp],
+        "lbm_get_populations": [H, dp],
+        "lbm_set_populations": [H, dp],
+        "lbm_set_equilibrium": [H, dp, dp],
+        "lbm_get_step": [H, ctypes.POINTER(ctypes.c_int64)],
+        "lbm_set_step": [H, ctypes.c_int64],
+        "lbm_conservation": [H, dp],
+        "lbm_tau_from_reynolds": [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int32
+    lib.lbm_destroy.argtypes = [H]
+    lib.lbm_destroy.restype = None
+    lib.lbm_last_error.argtypes = []
+    lib.lbm_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load_library()
+
+
+def _dptr(a, n=None):
+    if a is None:
+        return None
+    if not (isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags.c_contiguous):
+        raise TypeError("host arrays must be C-contiguous float64 numpy arrays")
+    if n is not None and a.size != n:
+        raise ValueError(f"host array has {a.size} values, needs {n}")
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _counts(desc: lbm_desc):
+    cells = desc.extent[0] * desc.extent[1] * desc.extent[2]
+    nb = [(desc.extent[a] + desc.block[a] - 1) // max(desc.block[a], 1) for a in range(3)]
+    dim = 2 if desc.lattice == LBM_D2Q9 else 3
+    return cells, nb[0] * nb[1] * nb[2], dim
+
+
+def make_desc(lattice, extent, face_bc, tau, storage=LBM_F32, sensor_kind=LBM_SENSOR_L2,
+              wall_u=None, rho0=1.0, force=(0.0, 0.0, 0.0), theta_refine=1e-3,
+              theta_coarsen=5e-4, block=None) -> lbm_desc:
+    """A descriptor with the buffers left empty."""
+    d = lbm_desc()
+    d.abi_version = LBM_ABI_VERSION
+    d.lattice, d.storage, d.sensor_kind = lattice, storage, sensor_kind
+    if block is None:
+        block = (8, 8, 1) if lattice == LBM_D2Q9 else (8, 8, 8)
+    for a in range(3):
+        d.extent[a], d.block[a], d.force[a] = int(extent[a]), int(block[a]), float(force[a])
+    for f in range(6):
+        d.face_bc[f] = int(face_bc[f])
+        for a in range(3):
+            d.wall_u[f][a] = float(wall_u[f][a]) if wall_u is not None else 0.0
+    d.tau, d.rho0 = float(tau), float(rho0)
+    d.theta_refine, d.theta_coarsen = float(theta_refine), float(theta_coarsen)
+    return d
+
+
+def lbm_last_error() -> str:
+    return _lib.lbm_last_error().decode()
+
+
+def lbm_required_bytes(desc: lbm_desc):
+    out = (ctypes.c_size_t * LBM_NBUF)()
+    st = _lib.lbm_required_bytes(ctypes.byref(desc), out)
+    return st, list(out)
+
+
+def lbm_create_blocks(desc: lbm_desc, f0=None):
+    cells, _, _ = _counts(desc)
+    h = ctypes.c_void_p()
+    st = _lib.lbm_create_blocks(ctypes.byref(desc), _dptr(f0, desc.lattice * cells), ctypes.byref(h))
+    return st, h
+
+
+def lbm_step_n(h, n: int, sensor_every: int):
+    return _lib.lbm_step_n(h, int(n), int(sensor_every))
+
+
+def lbm_sensor_flags(h, nblocks: int, block_max=None, flags=None):
+    """block_max: float64[nblocks] or None; flags: int8[nblocks] or None."""
+    if flags is not None and not (isinstance(flags, np.ndarray) and flags.dtype == np.int8
+                                  and flags.flags.c_contiguous and flags.size == nblocks):
+        raise TypeError("flags must be a C-contiguous int8 array of nblocks values")
+    step = ctypes.c_int64(-1)
+    fp = flags.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)) if flags is not None else None
+    st = _lib.lbm_sensor_flags(h, _dptr(block_max, nblocks), fp, ctypes.byref(step))
+    return st, step.value
+
+
+def lbm_get_macros(h, cells: int, rho=None, u=None):
+    return _lib.lbm_get_macros(h, _dptr(rho, cells), _dptr(u, 3 * cells))
+
+
+def lbm_get_populations(h, q: int, cells: int, f):
+    return _lib.lbm_get_populations(h, _dptr(f, q * cells))
+
+
+def lbm_set_populations(h, q: int, cells: int, f):
+    return _lib.lbm_set_populations(h, _dptr(f, q * cells))
+
+
+def lbm_set_equilibrium(h, cells: int, dim: int, rho=None, u=None):
+    return _lib.lbm_set_equilibrium(h, _dptr(rho, cells), _dptr(u, dim * cells))
+
+
+def lbm_get_step(h):
+    s = ctypes.c_int64(0)
+    st = _lib.lbm_get_step(h, ctypes.byref(s))
+    return st, s.value
+
+
+def lbm_set_step(h, step: int):
+    return _lib.lbm_set_step(h, int(step))
+
+
+def lbm_conservation(h):
+    out = np.zeros(4)
+    st = _lib.lbm_conservation(h, _dptr(out))
+    return st, out
+
+
+def lbm_tau_from_reynolds(u: float, n_across: float, re: float):
+    t = ctypes.c_double(0.0)
+    st = _lib.lbm_tau_from_reynolds(float(u), float(n_across), float(re), ctypes.byref(t))
+    return st, t.value
+
+
+def lbm_destroy(h):
+    _lib.lbm_destroy(h)

@@ -1,0 +1,146 @@
+// aux_kernels.hpp -- kernels outside the time loop: state initialisation,
+// host-transfer conversion, macroscopic fields and the conservation totals.
+// None of them runs per step; all of them read or write the same SoA planes
+// as the step kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lattice.hpp"
+
+namespace lbm {
+
+template <typename T>
+struct Planes {
+    T *f;              // plane i at f + i*pitch
+    int64_t pitch;
+    int cells;
+    double shift[19];  // storage shift per population (0 for plain storage)
+};
+
+// Rest state: f_i = w_i rho0 (stored as f_i - shift_i).
+template <int Q, typename T>
+__global__ void init_rest_kernel(Planes<T> p, double rho0) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= p.cells) return;
+    static_for<0, Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        p.f[(int64_t)i * p.pitch + c] = static_cast<T>(Vel<Q, i>::w * rho0 - p.shift[i]);
+    });
+}
+
+// One plane from float64 staging: out = (T)(in - shift).
+template <typename T>
+__global__ void import_plane_kernel(const double *in, T *out, int cells, double shift) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < cells) out[c] = static_cast<T>(in[c] - shift);
+}
+
+// One plane to float64 staging: out = (double)in + shift.
+template <typename T>
+__global__ void export_plane_kernel(const T *in, double *out, int cells, double shift) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < cells) out[c] = static_cast<double>(in[c]) + shift;
+}
+
+// f^eq(rho, u) of Eq. feq_i in float64, stored as f^eq_i - shift_i.
+// rho == nullptr: rho0 everywhere; u == nullptr: at rest.  u has 3 planes.
+template <int Q, typename T>
+__global__ void equilibrium_kernel(Planes<T> p, const double *rho, const double *u, double rho0) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= p.cells) return;
+    const double r = rho ? rho[c] : rho0;
+    double uu[3] = {0.0, 0.0, 0.0};
+    if (u) {
+        uu[0] = u[c];
+        uu[1] = u[(int64_t)p.cells + c];
+        uu[2] = (Lattice<Q>::D == 3) ? u[2 * (int64_t)p.cells + c] : 0.0;
+    }
+    const double usq = uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2];
+    static_for<0, Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        using V = Vel<Q, i>;
+        const double cu = V::x * uu[0] + V::y * uu[1] + V::z * uu[2];
+        const double feq = V::w * r * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+        p.f[(int64_t)i * p.pitch + c] = static_cast<T>(feq - p.shift[i]);
+    });
+}
+
+// rho = sum_i S_i and u = (sum_i xi_i S_i - F/2) / rho in float64.
+template <int Q, typename T>
+__global__ void macros_kernel(Planes<T> p, double *rho_out, double *u_out, double Fx, double Fy,
+                              double Fz) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= p.cells) return;
+    double rho = 0.0, m[3] = {0.0, 0.0, 0.0};
+    static_for<0, Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        using V = Vel<Q, i>;
+        const double v = static_cast<double>(p.f[(int64_t)i * p.pitch + c]);
+        rho += v + p.shift[i];
+        if constexpr (V::x != 0) m[0] += V::x * v;   // the shifts cancel in pairs
+        if constexpr (V::y != 0) m[1] += V::y * v;
+        if constexpr (V::z != 0) m[2] += V::z * v;
+    });
+    if (rho_out) rho_out[c] = rho;
+    if (u_out) {
+        u_out[c] = (m[0] - 0.5 * Fx) / rho;
+        u_out[(int64_t)p.cells + c] = (m[1] - 0.5 * Fy) / rho;
+        u_out[2 * (int64_t)p.cells + c] = (m[2] - 0.5 * Fz) / rho;
+    }
+}
+
+constexpr int kReduceThreads = 256;
+
+// Fixed-order tree over the workgroup's 256 slots of 4 doubles.
+__device__ __forceinline__ void tree_reduce4(double (*sh)[4], double acc[4]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sh[t][k] = acc[k];
+    __syncthreads();
+    for (int s = kReduceThreads / 2; s > 0; s >>= 1) {
+        if (t < s) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) sh[t][k] += sh[t + s][k];
+        }
+        __syncthreads();
+    }
+}
+
+// Pass 1: workgroup g sums cells g*256 + t, stepping by the grid size, into
+// partial[g][4] = (mass, momentum x, y, z).
+template <int Q, typename T>
+__global__ __launch_bounds__(kReduceThreads) void conservation_pass1(Planes<T> p, double *partial) {
+    __shared__ double sh[kReduceThreads][4];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int stride = gridDim.x * kReduceThreads;
+    for (int c = blockIdx.x * kReduceThreads + threadIdx.x; c < p.cells; c += stride) {
+        static_for<0, Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            using V = Vel<Q, i>;
+            const double v = static_cast<double>(p.f[(int64_t)i * p.pitch + c]);
+            acc[0] += v + p.shift[i];
+            if constexpr (V::x != 0) acc[1] += V::x * v;
+            if constexpr (V::y != 0) acc[2] += V::y * v;
+            if constexpr (V::z != 0) acc[3] += V::z * v;
+        });
+    }
+    tree_reduce4(sh, acc);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 4; ++k) partial[4 * blockIdx.x + k] = sh[0][k];
+}
+
+// Pass 2: one workgroup folds the partials in a fixed order.
+__global__ __launch_bounds__(kReduceThreads) void conservation_pass2(const double *partial, int n,
+                                                                     double *out) {
+    __shared__ double sh[kReduceThreads][4];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = threadIdx.x; j < n; j += kReduceThreads)
+        for (int k = 0; k < 4; ++k) acc[k] += partial[4 * j + k];
+    tree_reduce4(sh, acc);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 4; ++k) out[k] = sh[0][k];
+}
+
+}  // namespace lbm

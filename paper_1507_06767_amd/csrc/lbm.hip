@@ -1,0 +1,556 @@
+// lbm.hip -- host runtime behind the C interface of include/lbm.h.
+//
+// Validates descriptors, lays out the caller's buffers, selects the kernel
+// variant for (lattice, storage, sensor, force) and enqueues it on the
+// caller's stream.  The library allocates no device memory; the only host
+// allocation is the handle itself.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "aux_kernels.hpp"
+#include "step_kernel.hpp"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_error;
+
+lbm_status fail(lbm_status code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(LBM_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));          \
+    } while (0)
+
+constexpr int kAuxThreads = 256;
+constexpr int kMaxPartials = 1024;
+constexpr size_t kAlign = 256;
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Default tile width and plane padding; both may be overridden for tuning
+// through LBM_TILE_X (32, 64 or 128) and LBM_PLANE_PAD (bytes, multiple of 256).
+int tile_x_setting() {
+    const char *s = std::getenv("LBM_TILE_X");
+    if (s) {
+        int v = std::atoi(s);
+        if (v == 32 || v == 64 || v == 128) return v;
+    }
+    return 64;
+}
+
+size_t plane_pad_setting() {
+    const char *s = std::getenv("LBM_PLANE_PAD");
+    if (s) {
+        long v = std::atol(s);
+        if (v >= 0 && v % 256 == 0 && v <= (1l << 24)) return (size_t)v;
+    }
+    return 512;
+}
+
+struct Layout {
+    int q, dim;
+    int64_t cells;
+    int64_t pitch;        // elements between planes
+    size_t elem;          // bytes per stored population value
+    size_t cbytes;        // bytes per compute-type value (block maxima)
+    int nb[3];
+    int64_t nblocks;
+    size_t bytes[LBM_NBUF];
+    size_t staging_off, partial_off, out_off;
+};
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+lbm_status check_desc(const lbm_desc *d, Layout *L) {
+    if (!d) return fail(LBM_EINVAL, "descriptor is NULL");
+    if (d->abi_version != LBM_ABI_VERSION)
+        return fail(LBM_EINVAL, "abi_version %u, library has %u", d->abi_version, LBM_ABI_VERSION);
+    if (d->lattice != LBM_D2Q9 && d->lattice != LBM_D3Q19)
+        return fail(LBM_ENOTSUP, "lattice %d not supported (9 or 19)", d->lattice);
+    if (d->storage != LBM_F64 && d->storage != LBM_F32 && d->storage != LBM_F32_SHIFTED)
+        return fail(LBM_ENOTSUP, "storage %d not supported", d->storage);
+    if (d->sensor_kind != LBM_SENSOR_L2 && d->sensor_kind != LBM_SENSOR_KKN)
+        return fail(LBM_EINVAL, "sensor_kind %d", d->sensor_kind);
+    const int dim = (d->lattice == LBM_D2Q9) ? 2 : 3;
+    int64_t cells = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (d->extent[a] < 1) return fail(LBM_EINVAL, "extent[%d] = %d < 1", a, d->extent[a]);
+        cells *= d->extent[a];
+    }
+    if (dim == 2 && d->extent[2] != 1) return fail(LBM_EINVAL, "D2Q9 needs extent[2] == 1");
+    if (cells >= (int64_t(1) << 31) - 1024) return fail(LBM_ENOTSUP, "grid of %lld cells exceeds 2^31", (long long)cells);
+    const int want_bz = (dim == 3) ? kBlockEdge : 1;
+    if (d->block[0] != kBlockEdge || d->block[1] != kBlockEdge || d->block[2] != want_bz)
+        return fail(LBM_ENOTSUP, "sensor block {%d,%d,%d}: only {8,8,%d} is supported", d->block[0],
+                    d->block[1], d->block[2], want_bz);
+    for (int f = 0; f < 6; ++f)
+        if (d->face_bc[f] != LBM_BC_PERIODIC && d->face_bc[f] != LBM_BC_WALL)
+            return fail(LBM_EINVAL, "face_bc[%d] = %d", f, d->face_bc[f]);
+    for (int a = 0; a < 3; ++a)
+        if ((d->face_bc[2 * a] == LBM_BC_PERIODIC) != (d->face_bc[2 * a + 1] == LBM_BC_PERIODIC))
+            return fail(LBM_EINVAL, "axis %d: a periodic face needs a periodic opposite face", a);
+    if (dim == 2 && (d->face_bc[4] != LBM_BC_PERIODIC || d->face_bc[5] != LBM_BC_PERIODIC))
+        return fail(LBM_EINVAL, "D2Q9: the z faces must be periodic");
+    if (!is_fin(d->tau) || !(d->tau > 0.5)) return fail(LBM_EINVAL, "tau = %g must be > 1/2", d->tau);
+    if (!is_fin(d->rho0) || !(d->rho0 > 0.0)) return fail(LBM_EINVAL, "rho0 = %g must be > 0", d->rho0);
+    for (int a = 0; a < 3; ++a)
+        if (!is_fin(d->force[a])) return fail(LBM_EINVAL, "force[%d] not finite", a);
+    for (int f = 0; f < 6; ++f)
+        for (int a = 0; a < 3; ++a)
+            if (!is_fin(d->wall_u[f][a])) return fail(LBM_EINVAL, "wall_u[%d][%d] not finite", f, a);
+    if (dim == 2 && (d->force[2] != 0.0)) return fail(LBM_EINVAL, "D2Q9: force[2] must be 0");
+    if (!is_fin(d->theta_refine) || !is_fin(d->theta_coarsen) || d->theta_coarsen > d->theta_refine)
+        return fail(LBM_EINVAL, "thresholds must be finite with theta_coarsen <= theta_refine");
+
+    L->q = d->lattice;
+    L->dim = dim;
+    L->cells = cells;
+    L->elem = (d->storage == LBM_F64) ? 8 : 4;
+    L->cbytes = L->elem;
+    const size_t plane = round_up((size_t)cells * L->elem, kAlign) + plane_pad_setting();
+    L->pitch = (int64_t)(plane / L->elem);
+    L->nblocks = 1;
+    for (int a = 0; a < 3; ++a) {
+        const int e = (a == 2 && dim == 2) ? 1 : kBlockEdge;
+        L->nb[a] = (d->extent[a] + e - 1) / e;
+        L->nblocks *= L->nb[a];
+    }
+    L->bytes[LBM_BUF_F_A] = L->bytes[LBM_BUF_F_B] = plane * L->q;
+    L->bytes[LBM_BUF_BLOCK_MAX] = round_up((size_t)L->nblocks * L->cbytes, kAlign);
+    L->bytes[LBM_BUF_FLAGS] = round_up((size_t)L->nblocks, kAlign);
+    L->staging_off = 0;
+    L->partial_off = round_up((size_t)cells * 8 * 4, kAlign);
+    L->out_off = L->partial_off + round_up((size_t)kMaxPartials * 4 * 8, kAlign);
+    L->bytes[LBM_BUF_SCRATCH] = L->out_off + kAlign;
+    return LBM_OK;
+}
+
+lbm_status check_buffers(const lbm_desc *d, const Layout &L) {
+    static const char *names[LBM_NBUF] = {"F_A", "F_B", "BLOCK_MAX", "FLAGS", "SCRATCH"};
+    for (int b = 0; b < LBM_NBUF; ++b) {
+        if (!d->buf[b]) return fail(LBM_EINVAL, "buffer %s is NULL", names[b]);
+        if (d->buf_bytes[b] < L.bytes[b])
+            return fail(LBM_EINVAL, "buffer %s has %zu bytes, needs %zu", names[b], d->buf_bytes[b],
+                        L.bytes[b]);
+        const size_t align = (b <= LBM_BUF_F_B) ? kAlign : 16;
+        if ((uintptr_t)d->buf[b] % align)
+            return fail(LBM_EINVAL, "buffer %s is not %zu-byte aligned", names[b], align);
+        hipPointerAttribute_t attr;
+        if (hipPointerGetAttributes(&attr, d->buf[b]) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+            (void)hipGetLastError();
+            return fail(LBM_EINVAL, "buffer %s is not device memory", names[b]);
+        }
+    }
+    for (int b = 0; b < LBM_NBUF; ++b)
+        for (int c = b + 1; c < LBM_NBUF; ++c) {
+            const uintptr_t b0 = (uintptr_t)d->buf[b], b1 = b0 + L.bytes[b];
+            const uintptr_t c0 = (uintptr_t)d->buf[c], c1 = c0 + L.bytes[c];
+            if (b0 < c1 && c0 < b1) return fail(LBM_EINVAL, "buffers %s and %s overlap", names[b], names[c]);
+        }
+    return LBM_OK;
+}
+
+}  // namespace
+
+struct lbm_blocks {
+    lbm_desc d;
+    Layout L;
+    hipStream_t stream;
+    int device;
+    int tile_x;
+    int cur;                  // 0: state in F_A, 1: state in F_B
+    int64_t step;
+    int64_t last_sensor_step; // -1: none since the state was set
+    bool has_force;
+    uint32_t wall_mask;
+    std::vector<int8_t> flags_host;
+    std::vector<unsigned char> bmax_host;
+};
+
+namespace {
+
+void *state_ptr(lbm_blocks *h) { return h->d.buf[h->cur ? LBM_BUF_F_B : LBM_BUF_F_A]; }
+
+double *scratch_d(lbm_blocks *h, size_t off) {
+    return reinterpret_cast<double *>(static_cast<char *>(h->d.buf[LBM_BUF_SCRATCH]) + off);
+}
+
+// Storage shift of the auxiliary kernels: w_i rho0 for the shifted storage
+// (exact in float64), 0 for the plain ones.
+template <int Q, typename T>
+Planes<T> planes_of(lbm_blocks *h) {
+    Planes<T> p{};
+    p.f = static_cast<T *>(state_ptr(h));
+    p.pitch = h->L.pitch;
+    p.cells = (int)h->L.cells;
+    const bool shifted = h->d.storage == LBM_F32_SHIFTED;
+    static_for<0, Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        p.shift[i] = shifted ? Vel<Q, i>::w * h->d.rho0 : 0.0;
+    });
+    return p;
+}
+
+template <int Q, typename C>
+StepArgs<C> step_args(lbm_blocks *h, const void *src, void *dst) {
+    StepArgs<C> a{};
+    const lbm_desc &d = h->d;
+    constexpr int D = Lattice<Q>::D;
+    const int BZ = (D == 3) ? kBlockEdge : 1;
+    a.src = src;
+    a.dst = dst;
+    a.pitch = h->L.pitch;
+    a.nx = d.extent[0];
+    a.ny = d.extent[1];
+    a.nz = d.extent[2];
+    a.ntx = (a.nx + h->tile_x - 1) / h->tile_x;
+    a.nty = (a.ny + kTileY - 1) / kTileY;
+    const int ntz = (a.nz + BZ - 1) / BZ;
+    a.ntiles = a.ntx * a.nty * ntz;
+    a.nbx = h->L.nb[0];
+    a.nby = h->L.nb[1];
+    a.wall = h->wall_mask;
+    for (int f = 0; f < 6; ++f)
+        for (int c = 0; c < 3; ++c) a.uw[f][c] = (C)d.wall_u[f][c];
+    static_for<0, Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        a.shift[i] = (C)(Vel<Q, i>::w * d.rho0);
+    });
+    a.omega = (C)(1.0 / d.tau);
+    a.guo = (C)(1.0 - 0.5 / d.tau);
+    a.rho0 = (C)d.rho0;
+    for (int c = 0; c < 3; ++c) a.F[c] = (C)d.force[c];
+    a.theta_r = d.theta_refine;
+    a.theta_c = d.theta_coarsen;
+    a.block_max = static_cast<C *>(d.buf[LBM_BUF_BLOCK_MAX]);
+    a.flags = static_cast<int8_t *>(d.buf[LBM_BUF_FLAGS]);
+    return a;
+}
+
+template <int Q, typename T, typename C, bool SH, int BX>
+void launch_bx(hipStream_t st, const StepArgs<C> &a, bool sens, int sk, bool force) {
+    const dim3 g(a.ntiles), b(BX, kTileY);
+    if (!sens) {
+        if (force) hipLaunchKernelGGL((step_kernel<Q, T, C, SH, false, kSensorL2, true, BX>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((step_kernel<Q, T, C, SH, false, kSensorL2, false, BX>), g, b, 0, st, a);
+    } else if (sk == kSensorL2) {
+        if (force) hipLaunchKernelGGL((step_kernel<Q, T, C, SH, true, kSensorL2, true, BX>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((step_kernel<Q, T, C, SH, true, kSensorL2, false, BX>), g, b, 0, st, a);
+    } else {
+        if (force) hipLaunchKernelGGL((step_kernel<Q, T, C, SH, true, kSensorKKn, true, BX>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((step_kernel<Q, T, C, SH, true, kSensorKKn, false, BX>), g, b, 0, st, a);
+    }
+}
+
+template <int Q, typename T, typename C, bool SH>
+void launch_step(lbm_blocks *h, bool sens) {
+    void *src = state_ptr(h);
+    void *dst = h->d.buf[h->cur ? LBM_BUF_F_A : LBM_BUF_F_B];
+    const StepArgs<C> a = step_args<Q, C>(h, src, dst);
+    const int sk = h->d.sensor_kind;
+    switch (h->tile_x) {
+        case 32: launch_bx<Q, T, C, SH, 32>(h->stream, a, sens, sk, h->has_force); break;
+        case 128: launch_bx<Q, T, C, SH, 128>(h->stream, a, sens, sk, h->has_force); break;
+        default: launch_bx<Q, T, C, SH, 64>(h->stream, a, sens, sk, h->has_force); break;
+    }
+}
+
+void launch_step_any(lbm_blocks *h, bool sens) {
+    const int q = h->d.lattice, s = h->d.storage;
+    if (q == 9) {
+        if (s == LBM_F64) launch_step<9, double, double, false>(h, sens);
+        else if (s == LBM_F32) launch_step<9, float, float, false>(h, sens);
+        else launch_step<9, float, float, true>(h, sens);
+    } else {
+        if (s == LBM_F64) launch_step<19, double, double, false>(h, sens);
+        else if (s == LBM_F32) launch_step<19, float, float, false>(h, sens);
+        else launch_step<19, float, float, true>(h, sens);
+    }
+}
+
+// Calls f.template operator()<Q, T>() for the handle's lattice and storage type.
+template <typename F>
+void with_types(lbm_blocks *h, F &&f) {
+    const int q = h->d.lattice;
+    const bool dbl = h->d.storage == LBM_F64;
+    if (q == 9) {
+        if (dbl) f.template operator()<9, double>();
+        else f.template operator()<9, float>();
+    } else {
+        if (dbl) f.template operator()<19, double>();
+        else f.template operator()<19, float>();
+    }
+}
+
+unsigned grid_for(int64_t n) { return (unsigned)((n + kAuxThreads - 1) / kAuxThreads); }
+
+lbm_status check_handle(lbm_blocks *h) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != h->device)
+        return fail(LBM_EINVAL, "current device %d differs from the handle's device %d", dev, h->device);
+    return LBM_OK;
+}
+
+lbm_status import_state(lbm_blocks *h, const double *f_host) {
+    double *stage = scratch_d(h, h->L.staging_off);
+    const int64_t cells = h->L.cells;
+    lbm_status st = LBM_OK;
+    with_types(h, [&]<int Q, typename T>() {
+        Planes<T> p = planes_of<Q, T>(h);
+        for (int i = 0; i < Q && st == LBM_OK; ++i) {
+            hipError_t e = hipMemcpyAsync(stage, f_host + (int64_t)i * cells, cells * sizeof(double),
+                                          hipMemcpyHostToDevice, h->stream);
+            if (e != hipSuccess) { st = fail(LBM_EHIP, "hipMemcpyAsync: %s", hipGetErrorString(e)); break; }
+            hipLaunchKernelGGL((import_plane_kernel<T>), dim3(grid_for(cells)), dim3(kAuxThreads), 0,
+                               h->stream, stage, p.f + (int64_t)i * p.pitch, (int)cells, p.shift[i]);
+            // the staging plane is reused by the next population: wait for the kernel
+            e = hipStreamSynchronize(h->stream);
+            if (e != hipSuccess) st = fail(LBM_EHIP, "import: %s", hipGetErrorString(e));
+        }
+    });
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_required_bytes(const lbm_desc *d, size_t bytes[LBM_NBUF]) {
+    Layout L;
+    lbm_status st = check_desc(d, &L);
+    if (st != LBM_OK) return st;
+    if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+    for (int b = 0; b < LBM_NBUF; ++b) bytes[b] = L.bytes[b];
+    return LBM_OK;
+}
+
+lbm_status lbm_create_blocks(const lbm_desc *d, const double *f0_host, lbm_blocks **out) {
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    Layout L;
+    lbm_status st = check_desc(d, &L);
+    if (st != LBM_OK) return st;
+    st = check_buffers(d, L);
+    if (st != LBM_OK) return st;
+    lbm_blocks *h = new (std::nothrow) lbm_blocks();
+    if (!h) return fail(LBM_EINVAL, "out of host memory");
+    h->d = *d;
+    h->L = L;
+    h->stream = static_cast<hipStream_t>(d->stream);
+    h->tile_x = tile_x_setting();
+    h->cur = 0;
+    h->step = 0;
+    h->last_sensor_step = -1;
+    h->has_force = d->force[0] != 0.0 || d->force[1] != 0.0 || d->force[2] != 0.0;
+    h->wall_mask = 0;
+    for (int f = 0; f < 6; ++f)
+        if (d->face_bc[f] == LBM_BC_WALL) h->wall_mask |= 1u << f;
+    h->flags_host.resize(L.nblocks);
+    h->bmax_host.resize(L.nblocks * L.cbytes);
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(LBM_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+    }
+    if (f0_host) {
+        st = import_state(h, f0_host);
+    } else {
+        with_types(h, [&]<int Q, typename T>() {
+            hipLaunchKernelGGL((init_rest_kernel<Q, T>), dim3(grid_for(L.cells)), dim3(kAuxThreads), 0,
+                               h->stream, planes_of<Q, T>(h), d->rho0);
+        });
+        e = hipStreamSynchronize(h->stream);
+        if (e == hipSuccess) e = hipGetLastError();
+        if (e != hipSuccess) st = fail(LBM_EHIP, "initial state: %s", hipGetErrorString(e));
+    }
+    if (st != LBM_OK) {
+        delete h;
+        return st;
+    }
+    *out = h;
+    return LBM_OK;
+}
+
+lbm_status lbm_step_n(lbm_blocks *h, int64_t n, int32_t sensor_every) {
+    lbm_status st = check_handle(h);
+    if (st != LBM_OK) return st;
+    if (n < 0) return fail(LBM_EINVAL, "n = %lld < 0", (long long)n);
+    if (sensor_every < 0) return fail(LBM_EINVAL, "sensor_every = %d < 0", sensor_every);
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t step = h->step + 1;
+        const bool sens = sensor_every > 0 && step % sensor_every == 0;
+        launch_step_any(h, sens);
+        h->cur ^= 1;
+        h->step = step;
+        if (sens) h->last_sensor_step = step;
+    }
+    HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
+lbm_status lbm_sensor_flags(lbm_blocks *h, double *block_max_host, int8_t *flags_host,
+                            int64_t *step_index) {
+    lbm_status st = check_handle(h);
+    if (st != LBM_OK) return st;
+    if (h->last_sensor_step < 0) return fail(LBM_ESTATE, "no sensor step has run since the state was set");
+    const int64_t nb = h->L.nblocks;
+    HIP_TRY(hipMemcpyAsync(h->bmax_host.data(), h->d.buf[LBM_BUF_BLOCK_MAX], nb * h->L.cbytes,
+                           hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->flags_host.data(), h->d.buf[LBM_BUF_FLAGS], nb, hipMemcpyDeviceToHost,
+                           h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    bool nonfinite = false;
+    for (int64_t b = 0; b < nb; ++b) {
+        const double v = (h->L.cbytes == 8) ? reinterpret_cast<const double *>(h->bmax_host.data())[b]
+                                            : reinterpret_cast<const float *>(h->bmax_host.data())[b];
+        if (block_max_host) block_max_host[b] = v;
+        if (flags_host) flags_host[b] = h->flags_host[b];
+        if (h->flags_host[b] == LBM_FLAG_NONFINITE) nonfinite = true;
+    }
+    if (step_index) *step_index = h->last_sensor_step;
+    if (nonfinite) return fail(LBM_ENONFINITE, "a sensor block holds a non-finite value");
+    return LBM_OK;
+}
+
+lbm_status lbm_get_macros(lbm_blocks *h, double *rho_host, double *u_host) {
+    lbm_status st = check_handle(h);
+    if (st != LBM_OK) return st;
+    const int64_t cells = h->L.cells;
+    double *rho_d = scratch_d(h, h->L.staging_off);
+    double *u_d = rho_d + cells;
+    with_types(h, [&]<int Q, typename T>() {
+        hipLaunchKernelGGL((macros_kernel<Q, T>), dim3(grid_for(cells)), dim3(kAuxThreads), 0, h->stream,
+                           planes_of<Q, T>(h), rho_d, u_d, h->d.force[0], h->d.force[1], h->d.force[2]);
+    });
+    HIP_TRY(hipGetLastError());
+    if (rho_host) HIP_TRY(hipMemcpyAsync(rho_host, rho_d, cells * 8, hipMemcpyDeviceToHost, h->stream));
+    if (u_host) HIP_TRY(hipMemcpyAsync(u_host, u_d, 3 * cells * 8, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_get_populations(lbm_blocks *h, double *f_host) {
+    lbm_status st = check_handle(h);
+    if (st != LBM_OK) return st;
+    if (!f_host) return fail(LBM_EINVAL, "f_host is NULL");
+    const int64_t cells = h->L.cells;
+    double *stage = scratch_d(h, h->L.staging_off);
+    with_types(h, [&]<int Q, typename T>() {
+        Planes<T> p = planes_of<Q, T>(h);
+        for (int i = 0; i < Q && st == LBM_OK; ++i) {
+            hipLaunchKernelGGL((export_plane_kernel<T>), dim3(grid_for(cells)), dim3(kAuxThreads), 0,
+                               h->stream, p.f + (int64_t)i * p.pitch, stage, (int)cells, p.shift[i]);
+            hipError_t e = hipMemcpyAsync(f_host + (int64_t)i * cells, stage, cells * 8,
+                                          hipMemcpyDeviceToHost, h->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+            if (e != hipSuccess) st = fail(LBM_EHIP, "export: %s", hipGetErrorString(e));
+        }
+    });
+    return st;
+}
+
+lbm_status lbm_set_populations(lbm_blocks *h, const double *f_host) {
+    lbm_status st = check_handle(h);
+    if (st != LBM_OK) return st;
+    if (!f_host) return fail(LBM_EINVAL, "f_host is NULL");
+    st = import_state(h, f_host);
+    if (st == LBM_OK) h->last_sensor_step = -1;
+    return st;
+}
+
+lbm_status lbm_set_equilibrium(lbm_blocks *h, const double *rho_host, const double *u_host) {
+    lbm_status st = check_handle(h);
+    if (st != LBM_OK) return st;
+    const int64_t cells = h->L.cells;
+    double *rho_d = scratch_d(h, h->L.staging_off);
+    double *u_d = rho_d + cells;
+    if (rho_host) HIP_TRY(hipMemcpyAsync(rho_d, rho_host, cells * 8, hipMemcpyHostToDevice, h->stream));
+    if (u_host) {
+        const int planes = h->L.dim;
+        HIP_TRY(hipMemcpyAsync(u_d, u_host, planes * cells * 8, hipMemcpyHostToDevice, h->stream));
+    }
+    with_types(h, [&]<int Q, typename T>() {
+        hipLaunchKernelGGL((equilibrium_kernel<Q, T>), dim3(grid_for(cells)), dim3(kAuxThreads), 0,
+                           h->stream, planes_of<Q, T>(h), rho_host ? rho_d : nullptr,
+                           u_host ? u_d : nullptr, h->d.rho0);
+    });
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->last_sensor_step = -1;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_step(lbm_blocks *h, int64_t *step) {
+    if (!h || !step) return fail(LBM_EINVAL, "NULL argument");
+    *step = h->step;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_step(lbm_blocks *h, int64_t step) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    if (step < 0) return fail(LBM_EINVAL, "step = %lld < 0", (long long)step);
+    h->step = step;
+    h->last_sensor_step = -1;
+    return LBM_OK;
+}
+
+lbm_status lbm_conservation(lbm_blocks *h, double out[4]) {
+    lbm_status st = check_handle(h);
+    if (st != LBM_OK) return st;
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    const int64_t cells = h->L.cells;
+    double *partial = scratch_d(h, h->L.partial_off);
+    double *res = scratch_d(h, h->L.out_off);
+    const int nwg = (int)std::min<int64_t>(kMaxPartials, (cells + kReduceThreads - 1) / kReduceThreads);
+    with_types(h, [&]<int Q, typename T>() {
+        hipLaunchKernelGGL((conservation_pass1<Q, T>), dim3(nwg), dim3(kReduceThreads), 0, h->stream,
+                           planes_of<Q, T>(h), partial);
+    });
+    hipLaunchKernelGGL(conservation_pass2, dim3(1), dim3(kReduceThreads), 0, h->stream, partial, nwg, res);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(out, res, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_tau_from_reynolds(double u, double n_across, double re, double *tau) {
+    if (!tau) return fail(LBM_EINVAL, "tau is NULL");
+    if (!is_fin(u) || !is_fin(n_across) || !is_fin(re) || !(re > 0.0) || !(n_across > 0.0))
+        return fail(LBM_EINVAL, "need finite u, n_across > 0 and re > 0");
+    const double cs2 = 1.0 / 3.0;
+    const double nu = std::fabs(u) * n_across / re;
+    *tau = nu / cs2 + 0.5;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_blocks *h) {
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    delete h;
+}
+
+const char *lbm_last_error(void) { return g_error.c_str(); }
+
+}  // extern "C"
