@@ -60,6 +60,28 @@ def _traffic_from_profile(kernel_tag):
         return None
 
 
+def copy_calibration(nbytes=1 << 30, reps=20):
+    """Device-to-device copy bandwidth of torch's copy kernel on nbytes
+    (read + write counted), the practical ceiling of a streaming kernel; also
+    the reference whose rocprofv3 FETCH_SIZE / WRITE_SIZE scale the counters."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    sec = a.elapsed_time(b) / 1e3 / reps
+    del src, dst
+    return {"bytes_per_copy": nbytes, "gbs": round(2 * nbytes / sec / 1e9, 1), "us": round(sec * 1e6, 2)}
+
+
 def cpu_baseline(w, tau, sample_steps):
     """The FP64 oracle on the same workload, all host threads, a short run."""
     import oracle
@@ -85,6 +107,8 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "f32s", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=20)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also time a 1 GiB device copy (reported as copy_gbs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -156,6 +180,10 @@ def main():
         "wall_s": round(t_wall, 3),
     }
     blk.close()
+    if args.copy_calibration:
+        cal = copy_calibration()
+        result["copy_calibration"] = cal
+        result["roofline"]["frac_of_copy"] = round(achieved / cal["gbs"], 4)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, tau, args.cpu_sample_steps)
     print(json.dumps(result), flush=True)

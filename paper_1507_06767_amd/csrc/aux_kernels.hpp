@@ -30,6 +30,12 @@ __global__ void init_rest_kernel(Planes<T> p, double rho0) {
     });
 }
 
+// Clears n 64-bit words (the per-block accumulators of the step kernel).
+__global__ void zero_words_kernel(unsigned long long *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
 // One plane from float64 staging: out = (T)(in - shift).
 template <typename T>
 __global__ void import_plane_kernel(const double *in, T *out, int cells, double shift) {

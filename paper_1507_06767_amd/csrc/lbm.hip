@@ -48,15 +48,15 @@ constexpr size_t kAlign = 256;
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Default tile width and plane padding; both may be overridden for tuning
-// through LBM_TILE_X (32, 64 or 128) and LBM_PLANE_PAD (bytes, multiple of 256).
-int tile_x_setting() {
+// Tile width: the narrowest of 32, 64, 128 that spans the grid's x extent
+// (128 for wide grids).  LBM_TILE_X (32, 64 or 128) overrides it for tuning.
+int tile_x_setting(int nx) {
     const char *s = std::getenv("LBM_TILE_X");
     if (s) {
         int v = std::atoi(s);
         if (v == 32 || v == 64 || v == 128) return v;
     }
-    return 64;
+    return nx <= 32 ? 32 : (nx <= 64 ? 64 : 128);
 }
 
 size_t plane_pad_setting() {
@@ -77,6 +77,7 @@ struct Layout {
     int nb[3];
     int64_t nblocks;
     size_t bytes[LBM_NBUF];
+    size_t acc_off;       // per-block accumulator words inside BLOCK_MAX
     size_t staging_off, partial_off, out_off;
 };
 
@@ -130,6 +131,9 @@ lbm_status check_desc(const lbm_desc *d, Layout *L) {
     L->cbytes = L->elem;
     const size_t plane = round_up((size_t)cells * L->elem, kAlign) + plane_pad_setting();
     L->pitch = (int64_t)(plane / L->elem);
+    // the kernels address two adjacent planes with a 32-bit byte offset
+    if (2 * plane >= (size_t(1) << 32))
+        return fail(LBM_ENOTSUP, "grid of %lld cells: two population planes exceed 4 GiB", (long long)cells);
     L->nblocks = 1;
     for (int a = 0; a < 3; ++a) {
         const int e = (a == 2 && dim == 2) ? 1 : kBlockEdge;
@@ -137,7 +141,8 @@ lbm_status check_desc(const lbm_desc *d, Layout *L) {
         L->nblocks *= L->nb[a];
     }
     L->bytes[LBM_BUF_F_A] = L->bytes[LBM_BUF_F_B] = plane * L->q;
-    L->bytes[LBM_BUF_BLOCK_MAX] = round_up((size_t)L->nblocks * L->cbytes, kAlign);
+    L->acc_off = round_up((size_t)L->nblocks * L->cbytes, kAlign);
+    L->bytes[LBM_BUF_BLOCK_MAX] = L->acc_off + round_up((size_t)L->nblocks * 8, kAlign);
     L->bytes[LBM_BUF_FLAGS] = round_up((size_t)L->nblocks, kAlign);
     L->staging_off = 0;
     L->partial_off = round_up((size_t)cells * 8 * 4, kAlign);
@@ -213,29 +218,32 @@ Planes<T> planes_of(lbm_blocks *h) {
 }
 
 template <int Q, typename C>
-StepArgs<C> step_args(lbm_blocks *h, const void *src, void *dst) {
+StepArgs<C> step_args(lbm_blocks *h, const void *src, void *dst, bool zmarch, int tile_x) {
     StepArgs<C> a{};
     const lbm_desc &d = h->d;
     constexpr int D = Lattice<Q>::D;
     const int BZ = (D == 3) ? kBlockEdge : 1;
     a.src = src;
     a.dst = dst;
-    a.pitch = h->L.pitch;
+    a.pitch = (uint32_t)h->L.pitch;
     a.nx = d.extent[0];
     a.ny = d.extent[1];
     a.nz = d.extent[2];
-    a.ntx = (a.nx + h->tile_x - 1) / h->tile_x;
+    a.ntx = (a.nx + tile_x - 1) / tile_x;
     a.nty = (a.ny + kTileY - 1) / kTileY;
-    const int ntz = (a.nz + BZ - 1) / BZ;
+    const int ntz = zmarch ? (a.nz + BZ - 1) / BZ : a.nz;
     a.ntiles = a.ntx * a.nty * ntz;
     a.nbx = h->L.nb[0];
     a.nby = h->L.nb[1];
     a.wall = h->wall_mask;
-    for (int f = 0; f < 6; ++f)
-        for (int c = 0; c < 3; ++c) a.uw[f][c] = (C)d.wall_u[f][c];
     static_for<0, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        a.shift[i] = (C)(Vel<Q, i>::w * d.rho0);
+        using V = Vel<Q, i>;
+        a.shift[i] = (C)(V::w * d.rho0);
+        for (int f = 0; f < 6; ++f) {
+            const double cu = V::x * d.wall_u[f][0] + V::y * d.wall_u[f][1] + V::z * d.wall_u[f][2];
+            a.wcorr[i][f] = (C)(6.0 * V::w * d.rho0 * cu);
+        }
     });
     a.omega = (C)(1.0 / d.tau);
     a.guo = (C)(1.0 - 0.5 / d.tau);
@@ -245,34 +253,51 @@ StepArgs<C> step_args(lbm_blocks *h, const void *src, void *dst) {
     a.theta_c = d.theta_coarsen;
     a.block_max = static_cast<C *>(d.buf[LBM_BUF_BLOCK_MAX]);
     a.flags = static_cast<int8_t *>(d.buf[LBM_BUF_FLAGS]);
+    a.acc = reinterpret_cast<unsigned long long *>(static_cast<char *>(d.buf[LBM_BUF_BLOCK_MAX]) +
+                                                   h->L.acc_off);
     return a;
 }
 
-template <int Q, typename T, typename C, bool SH, int BX>
-void launch_bx(hipStream_t st, const StepArgs<C> &a, bool sens, int sk, bool force) {
+template <bool ZM, int Q, typename T, typename C, bool SH, bool SENS, int SK, bool FORCE, int BX>
+void launch_one(hipStream_t st, const StepArgs<C> &a) {
     const dim3 g(a.ntiles), b(BX, kTileY);
+    if constexpr (ZM) hipLaunchKernelGGL((step_zmarch<Q, T, C, SH, SENS, SK, FORCE, BX>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((step_cells<Q, T, C, SH, SENS, SK, FORCE, BX>), g, b, 0, st, a);
+}
+
+template <bool ZM, int Q, typename T, typename C, bool SH, int BX>
+void launch_bx(hipStream_t st, const StepArgs<C> &a, bool sens, int sk, bool force) {
     if (!sens) {
-        if (force) hipLaunchKernelGGL((step_kernel<Q, T, C, SH, false, kSensorL2, true, BX>), g, b, 0, st, a);
-        else hipLaunchKernelGGL((step_kernel<Q, T, C, SH, false, kSensorL2, false, BX>), g, b, 0, st, a);
+        if (force) launch_one<ZM, Q, T, C, SH, false, kSensorL2, true, BX>(st, a);
+        else launch_one<ZM, Q, T, C, SH, false, kSensorL2, false, BX>(st, a);
     } else if (sk == kSensorL2) {
-        if (force) hipLaunchKernelGGL((step_kernel<Q, T, C, SH, true, kSensorL2, true, BX>), g, b, 0, st, a);
-        else hipLaunchKernelGGL((step_kernel<Q, T, C, SH, true, kSensorL2, false, BX>), g, b, 0, st, a);
+        if (force) launch_one<ZM, Q, T, C, SH, true, kSensorL2, true, BX>(st, a);
+        else launch_one<ZM, Q, T, C, SH, true, kSensorL2, false, BX>(st, a);
     } else {
-        if (force) hipLaunchKernelGGL((step_kernel<Q, T, C, SH, true, kSensorKKn, true, BX>), g, b, 0, st, a);
-        else hipLaunchKernelGGL((step_kernel<Q, T, C, SH, true, kSensorKKn, false, BX>), g, b, 0, st, a);
+        if (force) launch_one<ZM, Q, T, C, SH, true, kSensorKKn, true, BX>(st, a);
+        else launch_one<ZM, Q, T, C, SH, true, kSensorKKn, false, BX>(st, a);
     }
 }
 
+// 3D float64 storage marches over z inside a workgroup (its 64-bit block
+// maximum leaves no room for the arrival count of step_cells); every other
+// form runs one cell per thread.
 template <int Q, typename T, typename C, bool SH>
 void launch_step(lbm_blocks *h, bool sens) {
     void *src = state_ptr(h);
     void *dst = h->d.buf[h->cur ? LBM_BUF_F_A : LBM_BUF_F_B];
-    const StepArgs<C> a = step_args<Q, C>(h, src, dst);
     const int sk = h->d.sensor_kind;
-    switch (h->tile_x) {
-        case 32: launch_bx<Q, T, C, SH, 32>(h->stream, a, sens, sk, h->has_force); break;
-        case 128: launch_bx<Q, T, C, SH, 128>(h->stream, a, sens, sk, h->has_force); break;
-        default: launch_bx<Q, T, C, SH, 64>(h->stream, a, sens, sk, h->has_force); break;
+    constexpr bool zm = (Lattice<Q>::D == 3) && (sizeof(C) == 8);
+    if constexpr (zm) {
+        const StepArgs<C> a = step_args<Q, C>(h, src, dst, true, 64);
+        launch_bx<true, Q, T, C, SH, 64>(h->stream, a, sens, sk, h->has_force);
+    } else {
+        const StepArgs<C> a = step_args<Q, C>(h, src, dst, false, h->tile_x);
+        switch (h->tile_x) {
+            case 32: launch_bx<false, Q, T, C, SH, 32>(h->stream, a, sens, sk, h->has_force); break;
+            case 64: launch_bx<false, Q, T, C, SH, 64>(h->stream, a, sens, sk, h->has_force); break;
+            default: launch_bx<false, Q, T, C, SH, 128>(h->stream, a, sens, sk, h->has_force); break;
+        }
     }
 }
 
@@ -305,6 +330,15 @@ void with_types(lbm_blocks *h, F &&f) {
 
 unsigned grid_for(int64_t n) { return (unsigned)((n + kAuxThreads - 1) / kAuxThreads); }
 
+// The step kernel's per-block (count | max) words must read zero before a
+// sensor step; they are cleared whenever a state is installed.
+void reset_accumulators(lbm_blocks *h) {
+    auto *acc = reinterpret_cast<unsigned long long *>(static_cast<char *>(h->d.buf[LBM_BUF_BLOCK_MAX]) +
+                                                       h->L.acc_off);
+    hipLaunchKernelGGL(zero_words_kernel, dim3(grid_for(h->L.nblocks)), dim3(kAuxThreads), 0, h->stream,
+                       acc, (int)h->L.nblocks);
+}
+
 lbm_status check_handle(lbm_blocks *h) {
     if (!h) return fail(LBM_EINVAL, "handle is NULL");
     int dev = -1;
@@ -318,6 +352,7 @@ lbm_status import_state(lbm_blocks *h, const double *f_host) {
     double *stage = scratch_d(h, h->L.staging_off);
     const int64_t cells = h->L.cells;
     lbm_status st = LBM_OK;
+    reset_accumulators(h);
     with_types(h, [&]<int Q, typename T>() {
         Planes<T> p = planes_of<Q, T>(h);
         for (int i = 0; i < Q && st == LBM_OK; ++i) {
@@ -359,7 +394,7 @@ lbm_status lbm_create_blocks(const lbm_desc *d, const double *f0_host, lbm_block
     h->d = *d;
     h->L = L;
     h->stream = static_cast<hipStream_t>(d->stream);
-    h->tile_x = tile_x_setting();
+    h->tile_x = tile_x_setting(d->extent[0]);
     h->cur = 0;
     h->step = 0;
     h->last_sensor_step = -1;
@@ -377,6 +412,7 @@ lbm_status lbm_create_blocks(const lbm_desc *d, const double *f0_host, lbm_block
     if (f0_host) {
         st = import_state(h, f0_host);
     } else {
+        reset_accumulators(h);
         with_types(h, [&]<int Q, typename T>() {
             hipLaunchKernelGGL((init_rest_kernel<Q, T>), dim3(grid_for(L.cells)), dim3(kAuxThreads), 0,
                                h->stream, planes_of<Q, T>(h), d->rho0);
@@ -491,6 +527,7 @@ lbm_status lbm_set_equilibrium(lbm_blocks *h, const double *rho_host, const doub
         const int planes = h->L.dim;
         HIP_TRY(hipMemcpyAsync(u_d, u_host, planes * cells * 8, hipMemcpyHostToDevice, h->stream));
     }
+    reset_accumulators(h);
     with_types(h, [&]<int Q, typename T>() {
         hipLaunchKernelGGL((equilibrium_kernel<Q, T>), dim3(grid_for(cells)), dim3(kAuxThreads), 0,
                            h->stream, planes_of<Q, T>(h), rho_host ? rho_d : nullptr,
