@@ -36,7 +36,14 @@
 // Arithmetic is done on the shifted populations d_i = f_i - w_i rho0, which
 // keeps the float32 variants accurate: every quantity the sensor and the
 // collision need (rho - rho0, rho u, f^neq, f^eq - w_i rho0) is a small
-// number formed without cancellation.
+// number formed without cancellation.  Two more choices keep float32
+// arithmetic from drifting over thousands of steps: the equilibrium's
+// first-order term is formed from the momentum j = sum_i xi_i f_i (+ F/2)
+// itself rather than from rho * u, and its product with the weight w_i uses
+// a two-float weight (w_hi + w_lo, one extra FMA), so that sum_i w_i = 1 and
+// sum_i w_i xi_i xi_i = c_s^2 I hold to rounding instead of being off by the
+// float rounding of 1/3, 1/18, 1/36 -- an error that would otherwise add the
+// same small momentum at every collision.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -96,6 +103,20 @@ __device__ __forceinline__ C dot_c(const C (&u)[3]) {
     if constexpr (V::y != 0) s += C(V::y) * u[1];
     if constexpr (V::z != 0) s += C(V::z) * u[2];
     return s;
+}
+
+// x * w for a lattice weight w known at compile time.  In float the weight
+// is carried as w_hi + w_lo (w_hi = w rounded to float) and the product
+// formed with one FMA, which rounds x * w almost always correctly.
+template <typename C, double W>
+__device__ __forceinline__ C wmul(C x) {
+    if constexpr (sizeof(C) == 4) {
+        constexpr float hi = static_cast<float>(W);
+        constexpr float lo = static_cast<float>(W - static_cast<double>(hi));
+        return __builtin_fmaf(x, hi, x * lo);
+    } else {
+        return x * C(W);
+    }
 }
 
 // Pull-stream with boundary conditions: the q shifted populations of cell
@@ -168,16 +189,13 @@ __device__ __forceinline__ C collide_store(const StepArgs<C> &a, uint32_t cell, 
     });
     const C rho = a.rho0 + drho;
     const C inv_rho = C(1) / rho;
-    C u[3];
+    C j[3] = {mx, my, mz};   // rho u
     if constexpr (FORCE) {
-        u[0] = (mx + C(0.5) * a.F[0]) * inv_rho;
-        u[1] = (my + C(0.5) * a.F[1]) * inv_rho;
-        u[2] = (mz + C(0.5) * a.F[2]) * inv_rho;
-    } else {
-        u[0] = mx * inv_rho;
-        u[1] = my * inv_rho;
-        u[2] = mz * inv_rho;
+        j[0] += C(0.5) * a.F[0];
+        j[1] += C(0.5) * a.F[1];
+        j[2] += C(0.5) * a.F[2];
     }
+    const C u[3] = {j[0] * inv_rho, j[1] * inv_rho, j[2] * inv_rho};
     const C usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     C uF = C(0);
     if constexpr (FORCE) uF = u[0] * a.F[0] + u[1] * a.F[1] + u[2] * a.F[2];
@@ -187,10 +205,13 @@ __device__ __forceinline__ C collide_store(const StepArgs<C> &a, uint32_t cell, 
     static_for<0, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         using V = Vel<Q, i>;
-        constexpr C w = C(V::w);
         const C cu = dot_c<Q, i>(u);
-        // f^eq_i - w_i rho0 = w_i [ (rho - rho0) + rho (3 cu + 9/2 cu^2 - 3/2 u^2) ]
-        const C deq = w * (drho + rho * (cu * (C(3) + C(4.5) * cu) - C(1.5) * usq));
+        const C cj = dot_c<Q, i>(j);
+        // f^eq_i - w_i rho0 = w_i [ (rho - rho0) + 3 xi.(rho u) + rho (9/2 cu^2 - 3/2 u^2) ],
+        // rho (...) taken as rho0 (...) + (rho - rho0) (...)
+        const C p2 = C(4.5) * cu * cu - C(1.5) * usq;
+        const C br = drho + C(3) * cj + (a.rho0 * p2 + drho * p2);
+        const C deq = wmul<C, V::w>(br);
         const C fneq = d[i] - deq;
         if constexpr (SENSOR) {
             const C feq = a.shift[i] + deq;
@@ -207,7 +228,7 @@ __device__ __forceinline__ C collide_store(const StepArgs<C> &a, uint32_t cell, 
             if constexpr (V::x != 0) cF += C(V::x) * a.F[0];
             if constexpr (V::y != 0) cF += C(V::y) * a.F[1];
             if constexpr (V::z != 0) cF += C(V::z) * a.F[2];
-            out += a.guo * w * (C(3) * (cF - uF) + C(9) * cu * cF);
+            out += a.guo * wmul<C, V::w>(C(3) * (cF - uF) + C(9) * cu * cF);
         }
         if constexpr (!SHIFTED) out += a.shift[i];
         // streaming store: the value is read back only in the next launch
