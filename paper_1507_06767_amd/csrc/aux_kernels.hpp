@@ -36,6 +36,18 @@ __global__ void zero_words_kernel(unsigned long long *p, int n) {
     if (i < n) p[i] = 0ull;
 }
 
+// out[opp(i)][c] = in[i][c]: between natural order and the exchanged-slot
+// order of the in-place scheme (an involution).
+template <int Q, typename T>
+__global__ void swap_planes_kernel(const T *in, T *out, int64_t pitch, int cells) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    static_for<0, Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        out[(int64_t)Vel<Q, i>::opp * pitch + c] = in[(int64_t)i * pitch + c];
+    });
+}
+
 // One plane from float64 staging: out = (T)(in - shift).
 template <typename T>
 __global__ void import_plane_kernel(const double *in, T *out, int cells, double shift) {

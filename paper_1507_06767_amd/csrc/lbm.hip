@@ -184,7 +184,10 @@ struct lbm_blocks {
     hipStream_t stream;
     int device;
     int tile_x;
-    int cur;                  // 0: state in F_A, 1: state in F_B
+    bool inplace;             // in-place (single buffer) streaming, else ping-pong
+    int cur;                  // ping-pong: 0 state in F_A, 1 state in F_B
+    int phase;                // in-place: 0 F_A holds S_k with slots i <-> opp(i)
+                              // exchanged; 1 F_A holds T(S_k) in natural order
     int64_t step;
     int64_t last_sensor_step; // -1: none since the state was set
     bool has_force;
@@ -195,7 +198,24 @@ struct lbm_blocks {
 
 namespace {
 
-void *state_ptr(lbm_blocks *h) { return h->d.buf[h->cur ? LBM_BUF_F_B : LBM_BUF_F_A]; }
+// Streaming scheme: in place (one buffer, the AA pattern) when a buffer is at
+// most 512 MiB, so that the working set of a step can stay in the Infinity
+// Cache; ping-pong above, where the two are on par and ping-pong streams its
+// stores non-temporally.  3D float64 always uses ping-pong (its z-march
+// kernel).  LBM_STREAMING=pingpong|inplace overrides the choice for tests.
+bool inplace_setting(const lbm_desc *d, const Layout &L) {
+    if (d->lattice == LBM_D3Q19 && d->storage == LBM_F64) return false;
+    const char *s = std::getenv("LBM_STREAMING");
+    if (s && std::strcmp(s, "pingpong") == 0) return false;
+    if (s && std::strcmp(s, "inplace") == 0) return true;
+    return L.bytes[LBM_BUF_F_A] <= (size_t(512) << 20);
+}
+
+// Buffer the step kernel reads.
+void *state_ptr(lbm_blocks *h) {
+    if (h->inplace) return h->d.buf[LBM_BUF_F_A];
+    return h->d.buf[h->cur ? LBM_BUF_F_B : LBM_BUF_F_A];
+}
 
 double *scratch_d(lbm_blocks *h, size_t off) {
     return reinterpret_cast<double *>(static_cast<char *>(h->d.buf[LBM_BUF_SCRATCH]) + off);
@@ -204,9 +224,9 @@ double *scratch_d(lbm_blocks *h, size_t off) {
 // Storage shift of the auxiliary kernels: w_i rho0 for the shifted storage
 // (exact in float64), 0 for the plain ones.
 template <int Q, typename T>
-Planes<T> planes_of(lbm_blocks *h) {
+Planes<T> planes_of(lbm_blocks *h, void *buf) {
     Planes<T> p{};
-    p.f = static_cast<T *>(state_ptr(h));
+    p.f = static_cast<T *>(buf);
     p.pitch = h->L.pitch;
     p.cells = (int)h->L.cells;
     const bool shifted = h->d.storage == LBM_F32_SHIFTED;
@@ -258,62 +278,6 @@ StepArgs<C> step_args(lbm_blocks *h, const void *src, void *dst, bool zmarch, in
     return a;
 }
 
-template <bool ZM, int Q, typename T, typename C, bool SH, bool SENS, int SK, bool FORCE, int BX>
-void launch_one(hipStream_t st, const StepArgs<C> &a) {
-    const dim3 g(a.ntiles), b(BX, kTileY);
-    if constexpr (ZM) hipLaunchKernelGGL((step_zmarch<Q, T, C, SH, SENS, SK, FORCE, BX>), g, b, 0, st, a);
-    else hipLaunchKernelGGL((step_cells<Q, T, C, SH, SENS, SK, FORCE, BX>), g, b, 0, st, a);
-}
-
-template <bool ZM, int Q, typename T, typename C, bool SH, int BX>
-void launch_bx(hipStream_t st, const StepArgs<C> &a, bool sens, int sk, bool force) {
-    if (!sens) {
-        if (force) launch_one<ZM, Q, T, C, SH, false, kSensorL2, true, BX>(st, a);
-        else launch_one<ZM, Q, T, C, SH, false, kSensorL2, false, BX>(st, a);
-    } else if (sk == kSensorL2) {
-        if (force) launch_one<ZM, Q, T, C, SH, true, kSensorL2, true, BX>(st, a);
-        else launch_one<ZM, Q, T, C, SH, true, kSensorL2, false, BX>(st, a);
-    } else {
-        if (force) launch_one<ZM, Q, T, C, SH, true, kSensorKKn, true, BX>(st, a);
-        else launch_one<ZM, Q, T, C, SH, true, kSensorKKn, false, BX>(st, a);
-    }
-}
-
-// 3D float64 storage marches over z inside a workgroup (its 64-bit block
-// maximum leaves no room for the arrival count of step_cells); every other
-// form runs one cell per thread.
-template <int Q, typename T, typename C, bool SH>
-void launch_step(lbm_blocks *h, bool sens) {
-    void *src = state_ptr(h);
-    void *dst = h->d.buf[h->cur ? LBM_BUF_F_A : LBM_BUF_F_B];
-    const int sk = h->d.sensor_kind;
-    constexpr bool zm = (Lattice<Q>::D == 3) && (sizeof(C) == 8);
-    if constexpr (zm) {
-        const StepArgs<C> a = step_args<Q, C>(h, src, dst, true, 64);
-        launch_bx<true, Q, T, C, SH, 64>(h->stream, a, sens, sk, h->has_force);
-    } else {
-        const StepArgs<C> a = step_args<Q, C>(h, src, dst, false, h->tile_x);
-        switch (h->tile_x) {
-            case 32: launch_bx<false, Q, T, C, SH, 32>(h->stream, a, sens, sk, h->has_force); break;
-            case 64: launch_bx<false, Q, T, C, SH, 64>(h->stream, a, sens, sk, h->has_force); break;
-            default: launch_bx<false, Q, T, C, SH, 128>(h->stream, a, sens, sk, h->has_force); break;
-        }
-    }
-}
-
-void launch_step_any(lbm_blocks *h, bool sens) {
-    const int q = h->d.lattice, s = h->d.storage;
-    if (q == 9) {
-        if (s == LBM_F64) launch_step<9, double, double, false>(h, sens);
-        else if (s == LBM_F32) launch_step<9, float, float, false>(h, sens);
-        else launch_step<9, float, float, true>(h, sens);
-    } else {
-        if (s == LBM_F64) launch_step<19, double, double, false>(h, sens);
-        else if (s == LBM_F32) launch_step<19, float, float, false>(h, sens);
-        else launch_step<19, float, float, true>(h, sens);
-    }
-}
-
 // Calls f.template operator()<Q, T>() for the handle's lattice and storage type.
 template <typename F>
 void with_types(lbm_blocks *h, F &&f) {
@@ -339,6 +303,113 @@ void reset_accumulators(lbm_blocks *h) {
                        acc, (int)h->L.nblocks);
 }
 
+template <bool ZM, int Q, typename T, typename C, bool SH, bool SENS, int SK, bool FORCE, int BX, int SCH>
+void launch_one(hipStream_t st, const StepArgs<C> &a) {
+    const dim3 g(a.ntiles), b(BX, kTileY);
+    if constexpr (ZM) hipLaunchKernelGGL((step_zmarch<Q, T, C, SH, SENS, SK, FORCE, BX>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((step_cells<Q, T, C, SH, SENS, SK, FORCE, BX, SCH>), g, b, 0, st, a);
+}
+
+template <bool ZM, int Q, typename T, typename C, bool SH, int BX, int SCH>
+void launch_sk(hipStream_t st, const StepArgs<C> &a, bool sens, int sk, bool force) {
+    if (!sens) {
+        if (force) launch_one<ZM, Q, T, C, SH, false, kSensorL2, true, BX, SCH>(st, a);
+        else launch_one<ZM, Q, T, C, SH, false, kSensorL2, false, BX, SCH>(st, a);
+    } else if (sk == kSensorL2) {
+        if (force) launch_one<ZM, Q, T, C, SH, true, kSensorL2, true, BX, SCH>(st, a);
+        else launch_one<ZM, Q, T, C, SH, true, kSensorL2, false, BX, SCH>(st, a);
+    } else {
+        if (force) launch_one<ZM, Q, T, C, SH, true, kSensorKKn, true, BX, SCH>(st, a);
+        else launch_one<ZM, Q, T, C, SH, true, kSensorKKn, false, BX, SCH>(st, a);
+    }
+}
+
+template <bool ZM, int Q, typename T, typename C, bool SH, int BX>
+void launch_bx(hipStream_t st, const StepArgs<C> &a, bool sens, int sk, bool force, int scheme) {
+    if constexpr (ZM) {
+        launch_sk<true, Q, T, C, SH, BX, kPingPong>(st, a, sens, sk, force);
+    } else {
+        switch (scheme) {
+            case kStream: launch_sk<false, Q, T, C, SH, BX, kStream>(st, a, sens, sk, force); break;
+            case kLocal: launch_sk<false, Q, T, C, SH, BX, kLocal>(st, a, sens, sk, force); break;
+            default: launch_sk<false, Q, T, C, SH, BX, kPingPong>(st, a, sens, sk, force); break;
+        }
+    }
+}
+
+// 3D float64 storage marches over z inside a workgroup (its 64-bit block
+// maximum leaves no room for the arrival count of step_cells); every other
+// form runs one cell per thread.
+template <int Q, typename T, typename C, bool SH>
+void launch_step(lbm_blocks *h, bool sens) {
+    void *src = state_ptr(h);
+    void *dst = h->inplace ? src : h->d.buf[h->cur ? LBM_BUF_F_A : LBM_BUF_F_B];
+    const int scheme = !h->inplace ? kPingPong : (h->phase == 0 ? kStream : kLocal);
+    const int sk = h->d.sensor_kind;
+    constexpr bool zm = (Lattice<Q>::D == 3) && (sizeof(C) == 8);
+    if constexpr (zm) {
+        const StepArgs<C> a = step_args<Q, C>(h, src, dst, true, 64);
+        launch_bx<true, Q, T, C, SH, 64>(h->stream, a, sens, sk, h->has_force, kPingPong);
+    } else {
+        const StepArgs<C> a = step_args<Q, C>(h, src, dst, false, h->tile_x);
+        switch (h->tile_x) {
+            case 32: launch_bx<false, Q, T, C, SH, 32>(h->stream, a, sens, sk, h->has_force, scheme); break;
+            case 64: launch_bx<false, Q, T, C, SH, 64>(h->stream, a, sens, sk, h->has_force, scheme); break;
+            default: launch_bx<false, Q, T, C, SH, 128>(h->stream, a, sens, sk, h->has_force, scheme); break;
+        }
+    }
+}
+
+// Where host data and initial states are written: the state buffer for
+// ping-pong; F_B as staging for the in-place scheme (then exchanged into F_A
+// by finish_import).
+void *import_target(lbm_blocks *h) { return h->inplace ? h->d.buf[LBM_BUF_F_B] : state_ptr(h); }
+
+void finish_import(lbm_blocks *h) {
+    if (!h->inplace) return;
+    with_types(h, [&]<int Q, typename T>() {
+        hipLaunchKernelGGL((swap_planes_kernel<Q, T>), dim3(grid_for(h->L.cells)), dim3(kAuxThreads), 0,
+                           h->stream, static_cast<const T *>(h->d.buf[LBM_BUF_F_B]),
+                           static_cast<T *>(h->d.buf[LBM_BUF_F_A]), h->L.pitch, (int)h->L.cells);
+    });
+    h->phase = 0;
+}
+
+// A buffer holding S_k in natural order: the state buffer for ping-pong; for
+// the in-place scheme, F_B after undoing the slot exchange or the last
+// scatter of F_A.
+void *canonical_state(lbm_blocks *h) {
+    if (!h->inplace) return state_ptr(h);
+    void *A = h->d.buf[LBM_BUF_F_A];
+    void *B = h->d.buf[LBM_BUF_F_B];
+    with_types(h, [&]<int Q, typename T>() {
+        if (h->phase == 0) {
+            hipLaunchKernelGGL((swap_planes_kernel<Q, T>), dim3(grid_for(h->L.cells)), dim3(kAuxThreads), 0,
+                               h->stream, static_cast<const T *>(A), static_cast<T *>(B), h->L.pitch,
+                               (int)h->L.cells);
+        } else {
+            using C = T;
+            const StepArgs<C> a = step_args<Q, C>(h, A, B, false, h->tile_x);
+            hipLaunchKernelGGL((unstream_kernel<Q, T, C>), dim3(grid_for(h->L.cells)), dim3(kAuxThreads), 0,
+                               h->stream, a, static_cast<T *>(B));
+        }
+    });
+    return B;
+}
+
+void launch_step_any(lbm_blocks *h, bool sens) {
+    const int q = h->d.lattice, s = h->d.storage;
+    if (q == 9) {
+        if (s == LBM_F64) launch_step<9, double, double, false>(h, sens);
+        else if (s == LBM_F32) launch_step<9, float, float, false>(h, sens);
+        else launch_step<9, float, float, true>(h, sens);
+    } else {
+        if (s == LBM_F64) launch_step<19, double, double, false>(h, sens);
+        else if (s == LBM_F32) launch_step<19, float, float, false>(h, sens);
+        else launch_step<19, float, float, true>(h, sens);
+    }
+}
+
 lbm_status check_handle(lbm_blocks *h) {
     if (!h) return fail(LBM_EINVAL, "handle is NULL");
     int dev = -1;
@@ -354,7 +425,7 @@ lbm_status import_state(lbm_blocks *h, const double *f_host) {
     lbm_status st = LBM_OK;
     reset_accumulators(h);
     with_types(h, [&]<int Q, typename T>() {
-        Planes<T> p = planes_of<Q, T>(h);
+        Planes<T> p = planes_of<Q, T>(h, import_target(h));
         for (int i = 0; i < Q && st == LBM_OK; ++i) {
             hipError_t e = hipMemcpyAsync(stage, f_host + (int64_t)i * cells, cells * sizeof(double),
                                           hipMemcpyHostToDevice, h->stream);
@@ -366,7 +437,10 @@ lbm_status import_state(lbm_blocks *h, const double *f_host) {
             if (e != hipSuccess) st = fail(LBM_EHIP, "import: %s", hipGetErrorString(e));
         }
     });
-    return st;
+    if (st != LBM_OK) return st;
+    finish_import(h);
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
 }
 
 }  // namespace
@@ -395,6 +469,8 @@ lbm_status lbm_create_blocks(const lbm_desc *d, const double *f0_host, lbm_block
     h->L = L;
     h->stream = static_cast<hipStream_t>(d->stream);
     h->tile_x = tile_x_setting(d->extent[0]);
+    h->inplace = inplace_setting(d, L);
+    h->phase = 0;
     h->cur = 0;
     h->step = 0;
     h->last_sensor_step = -1;
@@ -415,8 +491,9 @@ lbm_status lbm_create_blocks(const lbm_desc *d, const double *f0_host, lbm_block
         reset_accumulators(h);
         with_types(h, [&]<int Q, typename T>() {
             hipLaunchKernelGGL((init_rest_kernel<Q, T>), dim3(grid_for(L.cells)), dim3(kAuxThreads), 0,
-                               h->stream, planes_of<Q, T>(h), d->rho0);
+                               h->stream, planes_of<Q, T>(h, import_target(h)), d->rho0);
         });
+        finish_import(h);
         e = hipStreamSynchronize(h->stream);
         if (e == hipSuccess) e = hipGetLastError();
         if (e != hipSuccess) st = fail(LBM_EHIP, "initial state: %s", hipGetErrorString(e));
@@ -438,7 +515,8 @@ lbm_status lbm_step_n(lbm_blocks *h, int64_t n, int32_t sensor_every) {
         const int64_t step = h->step + 1;
         const bool sens = sensor_every > 0 && step % sensor_every == 0;
         launch_step_any(h, sens);
-        h->cur ^= 1;
+        if (h->inplace) h->phase ^= 1;
+        else h->cur ^= 1;
         h->step = step;
         if (sens) h->last_sensor_step = step;
     }
@@ -476,9 +554,11 @@ lbm_status lbm_get_macros(lbm_blocks *h, double *rho_host, double *u_host) {
     const int64_t cells = h->L.cells;
     double *rho_d = scratch_d(h, h->L.staging_off);
     double *u_d = rho_d + cells;
+    void *canon = canonical_state(h);
     with_types(h, [&]<int Q, typename T>() {
         hipLaunchKernelGGL((macros_kernel<Q, T>), dim3(grid_for(cells)), dim3(kAuxThreads), 0, h->stream,
-                           planes_of<Q, T>(h), rho_d, u_d, h->d.force[0], h->d.force[1], h->d.force[2]);
+                           planes_of<Q, T>(h, canon), rho_d, u_d, h->d.force[0], h->d.force[1],
+                           h->d.force[2]);
     });
     HIP_TRY(hipGetLastError());
     if (rho_host) HIP_TRY(hipMemcpyAsync(rho_host, rho_d, cells * 8, hipMemcpyDeviceToHost, h->stream));
@@ -493,8 +573,9 @@ lbm_status lbm_get_populations(lbm_blocks *h, double *f_host) {
     if (!f_host) return fail(LBM_EINVAL, "f_host is NULL");
     const int64_t cells = h->L.cells;
     double *stage = scratch_d(h, h->L.staging_off);
+    void *canon = canonical_state(h);
     with_types(h, [&]<int Q, typename T>() {
-        Planes<T> p = planes_of<Q, T>(h);
+        Planes<T> p = planes_of<Q, T>(h, canon);
         for (int i = 0; i < Q && st == LBM_OK; ++i) {
             hipLaunchKernelGGL((export_plane_kernel<T>), dim3(grid_for(cells)), dim3(kAuxThreads), 0,
                                h->stream, p.f + (int64_t)i * p.pitch, stage, (int)cells, p.shift[i]);
@@ -530,9 +611,10 @@ lbm_status lbm_set_equilibrium(lbm_blocks *h, const double *rho_host, const doub
     reset_accumulators(h);
     with_types(h, [&]<int Q, typename T>() {
         hipLaunchKernelGGL((equilibrium_kernel<Q, T>), dim3(grid_for(cells)), dim3(kAuxThreads), 0,
-                           h->stream, planes_of<Q, T>(h), rho_host ? rho_d : nullptr,
+                           h->stream, planes_of<Q, T>(h, import_target(h)), rho_host ? rho_d : nullptr,
                            u_host ? u_d : nullptr, h->d.rho0);
     });
+    finish_import(h);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(h->stream));
     h->last_sensor_step = -1;
@@ -561,9 +643,10 @@ lbm_status lbm_conservation(lbm_blocks *h, double out[4]) {
     double *partial = scratch_d(h, h->L.partial_off);
     double *res = scratch_d(h, h->L.out_off);
     const int nwg = (int)std::min<int64_t>(kMaxPartials, (cells + kReduceThreads - 1) / kReduceThreads);
+    void *canon = canonical_state(h);
     with_types(h, [&]<int Q, typename T>() {
         hipLaunchKernelGGL((conservation_pass1<Q, T>), dim3(nwg), dim3(kReduceThreads), 0, h->stream,
-                           planes_of<Q, T>(h), partial);
+                           planes_of<Q, T>(h, canon), partial);
     });
     hipLaunchKernelGGL(conservation_pass2, dim3(1), dim3(kReduceThreads), 0, h->stream, partial, nwg, res);
     HIP_TRY(hipGetLastError());

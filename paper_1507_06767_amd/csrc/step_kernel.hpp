@@ -17,6 +17,20 @@
 // are a uniform plane base plus a 32-bit lane offset, which keeps the kernel
 // at ~40 VGPRs (8 waves per SIMD) so that enough loads are in flight.
 //
+// Three streaming schemes share the arithmetic:
+//  * kPingPong: read S_{k-1} from one buffer (pull), write S_k to the other.
+//  * In-place ("AA" pattern, one buffer): steps alternate between
+//    kStream, which gathers the pre-collision populations from the
+//    neighbours' opposite slots and scatters the post-collision ones to the
+//    neighbours' own slots, and kLocal, which reads a cell's own slots and
+//    writes its post-collision values back into the opposite slots.  After a
+//    kStream step the buffer holds T(S_k) in natural order; after a kLocal
+//    step it holds S_k with slot i <-> opp(i) exchanged.  A cell reads and
+//    writes the same set of locations, so one buffer suffices, and the
+//    working set of a step is half that of ping-pong: a 128^3 D3Q19 float
+//    state (152 MiB) then stays in the 256 MB Infinity Cache.  Bounce-back
+//    folds into the addressing of both halves of kStream.
+//
 // Two work decompositions:
 //  * step_cells: one cell per thread; a workgroup is BX x 8 cells of one
 //    z-slice, i.e. BX/8 block columns of one 8x8 block row.  The workgroup
@@ -57,11 +71,14 @@ constexpr int kBlockEdge = 8;       // sensor block edge along every active axis
 constexpr int kTileY = 8;           // rows per workgroup (one block row)
 constexpr int kSensorL2 = 0;
 constexpr int kSensorKKn = 1;
+constexpr int kPingPong = 0;   // streaming schemes, see above
+constexpr int kStream = 1;
+constexpr int kLocal = 2;
 
 template <typename C>
 struct StepArgs {
-    const void *src;        // S_{k-1}
-    void *dst;              // S_k
+    const void *src;        // S_{k-1} (in-place schemes: the single buffer)
+    void *dst;              // S_k (in-place schemes: the same buffer)
     uint32_t pitch;         // elements between population planes
     int nx, ny, nz;
     int ntx, nty, ntiles;   // tiles along x, y; total tiles (workgroups)
@@ -119,64 +136,138 @@ __device__ __forceinline__ C wmul(C x) {
     }
 }
 
-// Pull-stream with boundary conditions: the q shifted populations of cell
-// (x, y, z) after streaming, d_i = f_i(x) - w_i rho0.
-template <int Q, typename T, typename C, bool SHIFTED>
-__device__ __forceinline__ void pull(const StepArgs<C> &a, int x, int y, int z, C (&d)[Q]) {
-    constexpr int D = Lattice<Q>::D;
+// Neighbourhood of one cell: the pull source coordinate along each axis for
+// a population moving in +axis ("m", coordinate - 1) and in -axis ("p",
+// coordinate + 1), with periodic wrap, and whether that source lies beyond
+// a wall face.
+struct Geo {
+    int x, y, z;
+    int xm, xp, ym, yp, zm, zp;
+    bool wxm, wxp, wym, wyp, wzm, wzp;
+    uint32_t cell;
+};
+
+template <int D, typename C>
+__device__ __forceinline__ Geo make_geo(const StepArgs<C> &a, int x, int y, int z) {
+    Geo g;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
-    // "m": source of a population moving in +axis (coordinate - 1); "p": in -axis
-    const bool wxm = (x == 0) && (a.wall & 1u);
-    const bool wxp = (x == nx - 1) && (a.wall & 2u);
-    const bool wym = (y == 0) && (a.wall & 4u);
-    const bool wyp = (y == ny - 1) && (a.wall & 8u);
-    const int xm = (x == 0) ? nx - 1 : x - 1;
-    const int xp = (x == nx - 1) ? 0 : x + 1;
-    const int ym = (y == 0) ? ny - 1 : y - 1;
-    const int yp = (y == ny - 1) ? 0 : y + 1;
-    bool wzm = false, wzp = false;
-    int zm = z, zp = z;
+    g.x = x; g.y = y; g.z = z;
+    g.wxm = (x == 0) && (a.wall & 1u);
+    g.wxp = (x == nx - 1) && (a.wall & 2u);
+    g.wym = (y == 0) && (a.wall & 4u);
+    g.wyp = (y == ny - 1) && (a.wall & 8u);
+    g.xm = (x == 0) ? nx - 1 : x - 1;
+    g.xp = (x == nx - 1) ? 0 : x + 1;
+    g.ym = (y == 0) ? ny - 1 : y - 1;
+    g.yp = (y == ny - 1) ? 0 : y + 1;
+    g.wzm = g.wzp = false;
+    g.zm = g.zp = z;
     if constexpr (D == 3) {
-        wzm = (z == 0) && (a.wall & 16u);
-        wzp = (z == nz - 1) && (a.wall & 32u);
-        zm = (z == 0) ? nz - 1 : z - 1;
-        zp = (z == nz - 1) ? 0 : z + 1;
+        g.wzm = (z == 0) && (a.wall & 16u);
+        g.wzp = (z == nz - 1) && (a.wall & 32u);
+        g.zm = (z == 0) ? nz - 1 : z - 1;
+        g.zp = (z == nz - 1) ? 0 : z + 1;
     }
-    const uint32_t cell = (uint32_t)((z * ny + y) * nx + x);
-    const char *base = static_cast<const char *>(a.src);
+    g.cell = (uint32_t)((z * ny + y) * nx + x);
+    return g;
+}
+
+// The pull link of population I at the cell: its source cell x - xi_I (after
+// periodic wrap), whether the source lies beyond a wall (then the link is
+// bounced), and the moving-wall term 6 w_I rho0 (xi_I . u_w) summed over the
+// wall faces crossed (0 off walls).
+template <typename C>
+struct Link {
+    bool wall;
+    uint32_t src;
+    C corr;
+};
+
+template <int Q, int I, typename C>
+__device__ __forceinline__ Link<C> link(const StepArgs<C> &a, const Geo &g) {
+    using V = Vel<Q, I>;
+    const int sx = (V::x > 0) ? g.xm : ((V::x < 0) ? g.xp : g.x);
+    const int sy = (V::y > 0) ? g.ym : ((V::y < 0) ? g.yp : g.y);
+    const int sz = (V::z > 0) ? g.zm : ((V::z < 0) ? g.zp : g.z);
+    Link<C> l;
+    l.wall = false;
+    l.corr = C(0);
+    if constexpr (V::x > 0) { l.wall = l.wall || g.wxm; l.corr += g.wxm ? a.wcorr[I][0] : C(0); }
+    if constexpr (V::x < 0) { l.wall = l.wall || g.wxp; l.corr += g.wxp ? a.wcorr[I][1] : C(0); }
+    if constexpr (V::y > 0) { l.wall = l.wall || g.wym; l.corr += g.wym ? a.wcorr[I][2] : C(0); }
+    if constexpr (V::y < 0) { l.wall = l.wall || g.wyp; l.corr += g.wyp ? a.wcorr[I][3] : C(0); }
+    if constexpr (V::z > 0) { l.wall = l.wall || g.wzm; l.corr += g.wzm ? a.wcorr[I][4] : C(0); }
+    if constexpr (V::z < 0) { l.wall = l.wall || g.wzp; l.corr += g.wzp ? a.wcorr[I][5] : C(0); }
+    l.src = (uint32_t)((sz * a.ny + sy) * a.nx + sx);
+    return l;
+}
+
+// Element address inside planes {I, opp(I)}: both candidates of every access
+// lie in those two planes, so they are addressed from the lower of the two
+// with a non-negative 32-bit offset.
+template <int Q, int I, typename T>
+__device__ __forceinline__ T *pair_addr(void *buf, uint32_t pitch, int plane, uint32_t cell) {
+    constexpr int lo = (Vel<Q, I>::opp < I) ? Vel<Q, I>::opp : I;
+    const uint32_t boff = ((uint32_t)(plane - lo) * pitch + cell) * (uint32_t)sizeof(T);
+    return reinterpret_cast<T *>(static_cast<char *>(buf) + (size_t)lo * pitch * sizeof(T) + boff);
+}
+
+// The q pre-collision populations of the cell as shifted values
+// d_i = f_i - w_i rho0, read according to the streaming scheme:
+//   kPingPong: f_i = S_i(x - xi_i), or S_opp(i)(x) + term on a bounced link;
+//   kStream  : the same values, found in the opposite slots of the single
+//              buffer (S_i(y) is kept in slot opp(i) of y);
+//   kLocal   : f_i is in slot i of the cell itself.
+template <int Q, typename T, typename C, bool SHIFTED, int SCHEME>
+__device__ __forceinline__ void load_cell(const StepArgs<C> &a, const Geo &g, C (&d)[Q]) {
+    void *src = const_cast<void *>(a.src);
     static_for<0, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        using V = Vel<Q, i>;
-        // both candidate sources lie in planes i and opp(i): address them from
-        // the lower of the two so that the lane offset stays non-negative
-        constexpr int lo = (V::opp < i) ? V::opp : i;
-        const int sx = (V::x > 0) ? xm : ((V::x < 0) ? xp : x);
-        const int sy = (V::y > 0) ? ym : ((V::y < 0) ? yp : y);
-        const int sz = (V::z > 0) ? zm : ((V::z < 0) ? zp : z);
-        bool wall = false;
-        C corr = C(0);
-        if constexpr (V::x > 0) { wall = wall || wxm; corr += wxm ? a.wcorr[i][0] : C(0); }
-        if constexpr (V::x < 0) { wall = wall || wxp; corr += wxp ? a.wcorr[i][1] : C(0); }
-        if constexpr (V::y > 0) { wall = wall || wym; corr += wym ? a.wcorr[i][2] : C(0); }
-        if constexpr (V::y < 0) { wall = wall || wyp; corr += wyp ? a.wcorr[i][3] : C(0); }
-        if constexpr (V::z > 0) { wall = wall || wzm; corr += wzm ? a.wcorr[i][4] : C(0); }
-        if constexpr (V::z < 0) { wall = wall || wzp; corr += wzp ? a.wcorr[i][5] : C(0); }
-        const uint32_t nbr = (uint32_t)((sz * ny + sy) * nx + sx);
-        const uint32_t e_pull = (uint32_t)(i - lo) * a.pitch + nbr;
-        const uint32_t e_bounce = (uint32_t)(V::opp - lo) * a.pitch + cell;
-        const uint32_t boff = (wall ? e_bounce : e_pull) * (uint32_t)sizeof(T);
-        const T *p = reinterpret_cast<const T *>(base + (size_t)lo * a.pitch * sizeof(T) + boff);
-        C v = static_cast<C>(*p);
+        constexpr int o = Vel<Q, i>::opp;
+        C v, corr = C(0);
+        if constexpr (SCHEME == kLocal) {
+            v = static_cast<C>(*pair_addr<Q, i, T>(src, a.pitch, i, g.cell));
+        } else {
+            const Link<C> l = link<Q, i>(a, g);
+            const int plane_pull = (SCHEME == kPingPong) ? i : o;
+            const int plane_bounce = (SCHEME == kPingPong) ? o : i;
+            const T *p = l.wall ? pair_addr<Q, i, T>(src, a.pitch, plane_bounce, g.cell)
+                                : pair_addr<Q, i, T>(src, a.pitch, plane_pull, l.src);
+            v = static_cast<C>(*p);
+            corr = l.corr;
+        }
         if constexpr (!SHIFTED) v -= a.shift[i];   // shift[i] == shift[opp(i)]
-        d[i] = v + corr;                             // moving-wall term, 0 off walls
+        d[i] = v + corr;
     });
+}
+
+// Store of the post-collision value of population I of the cell:
+//   kPingPong: slot I of the cell in the other buffer (non-temporal);
+//   kLocal   : slot opp(I) of the cell;
+//   kStream  : slot I of the neighbour x + xi_I, the pre-collision place of
+//              the next step; if x + xi_I lies beyond a wall the value
+//              returns to the cell as opp(I) with the moving-wall term.
+template <int Q, int I, typename T, typename C, int SCHEME>
+__device__ __forceinline__ void store_pop(const StepArgs<C> &a, const Geo &g, C out) {
+    constexpr int o = Vel<Q, I>::opp;
+    if constexpr (SCHEME == kPingPong) {
+        __builtin_nontemporal_store(static_cast<T>(out), pair_addr<Q, I, T>(a.dst, a.pitch, I, g.cell));
+    } else if constexpr (SCHEME == kLocal) {
+        *pair_addr<Q, I, T>(a.dst, a.pitch, o, g.cell) = static_cast<T>(out);
+    } else {
+        // the scatter link of I is the pull link of opp(I) read backwards
+        const Link<C> l = link<Q, o>(a, g);
+        T *p = l.wall ? pair_addr<Q, I, T>(a.dst, a.pitch, o, g.cell)
+                      : pair_addr<Q, I, T>(a.dst, a.pitch, I, l.src);
+        *p = static_cast<T>(out + l.corr);
+    }
 }
 
 // Moments, equilibrium, sensor, BGK + Guo collision and the store of one
 // cell.  Returns the cell's sensor value: ||f^neq||^2 / ||f^eq||^2 (L2; the
 // square root is taken once per block) or K_Kn.
-template <int Q, typename T, typename C, bool SHIFTED, bool SENSOR, int SKIND, bool FORCE>
-__device__ __forceinline__ C collide_store(const StepArgs<C> &a, uint32_t cell, const C (&d)[Q]) {
+template <int Q, typename T, typename C, bool SHIFTED, bool SENSOR, int SKIND, bool FORCE, int SCHEME>
+__device__ __forceinline__ C collide_store(const StepArgs<C> &a, const Geo &g, const C (&d)[Q]) {
     // moments (Eqs. rho and u), Guo's half-force shift
     C drho = C(0), mx = C(0), my = C(0), mz = C(0);
     static_for<0, Q>([&](auto ic) {
@@ -201,7 +292,6 @@ __device__ __forceinline__ C collide_store(const StepArgs<C> &a, uint32_t cell, 
     if constexpr (FORCE) uF = u[0] * a.F[0] + u[1] * a.F[1] + u[2] * a.F[2];
 
     C num = C(0), den = C(0), kkn = C(0);
-    T *__restrict__ dst = static_cast<T *>(a.dst);
     static_for<0, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         using V = Vel<Q, i>;
@@ -231,8 +321,7 @@ __device__ __forceinline__ C collide_store(const StepArgs<C> &a, uint32_t cell, 
             out += a.guo * wmul<C, V::w>(C(3) * (cF - uF) + C(9) * cu * cF);
         }
         if constexpr (!SHIFTED) out += a.shift[i];
-        // streaming store: the value is read back only in the next launch
-        __builtin_nontemporal_store(static_cast<T>(out), dst + (size_t)i * a.pitch + cell);
+        store_pop<Q, i, T, C, SCHEME>(a, g, out);
     });
     if constexpr (SENSOR) {
         if constexpr (SKIND == kSensorL2) return num / den;
@@ -279,7 +368,7 @@ __device__ __forceinline__ C finish(C M) {
     else return M;
 }
 
-template <int Q, typename T, typename C, bool SHIFTED, bool SENSOR, int SKIND, bool FORCE, int BX>
+template <int Q, typename T, typename C, bool SHIFTED, bool SENSOR, int SKIND, bool FORCE, int BX, int SCHEME>
 __global__ __launch_bounds__(BX *kTileY) void step_cells(const StepArgs<C> a) {
     constexpr int D = Lattice<Q>::D;
     static_assert(BX % kBlockEdge == 0, "tile width must hold whole blocks");
@@ -295,9 +384,10 @@ __global__ __launch_bounds__(BX *kTileY) void step_cells(const StepArgs<C> a) {
 
     C s = C(0);
     if (x < a.nx && y < a.ny) {
+        const Geo g = make_geo<D>(a, x, y, z);
         C d[Q];
-        pull<Q, T, C, SHIFTED>(a, x, y, z, d);
-        s = collide_store<Q, T, C, SHIFTED, SENSOR, SKIND, FORCE>(a, (uint32_t)((z * a.ny + y) * a.nx + x), d);
+        load_cell<Q, T, C, SHIFTED, SCHEME>(a, g, d);
+        s = collide_store<Q, T, C, SHIFTED, SENSOR, SKIND, FORCE, SCHEME>(a, g, d);
     }
     if constexpr (SENSOR) {
         const C M = tile_block_max<BX>(s);
@@ -347,10 +437,10 @@ __global__ __launch_bounds__(BX *kTileY) void step_zmarch(const StepArgs<C> a) {
         const int zend = min(z0 + kBlockEdge, a.nz);
 #pragma unroll 1
         for (int z = z0; z < zend; ++z) {
+            const Geo g = make_geo<3>(a, x, y, z);
             C d[Q];
-            pull<Q, T, C, SHIFTED>(a, x, y, z, d);
-            const C s = collide_store<Q, T, C, SHIFTED, SENSOR, SKIND, FORCE>(
-                a, (uint32_t)((z * a.ny + y) * a.nx + x), d);
+            load_cell<Q, T, C, SHIFTED, kPingPong>(a, g, d);
+            const C s = collide_store<Q, T, C, SHIFTED, SENSOR, SKIND, FORCE, kPingPong>(a, g, d);
             if constexpr (SENSOR) m = nan_max(m, s);
         }
     }
@@ -361,6 +451,32 @@ __global__ __launch_bounds__(BX *kTileY) void step_zmarch(const StepArgs<C> a) {
             if (bx < a.nbx) write_block(a, (tiz * a.nby + tiy) * a.nbx + bx, finish<SKIND>(M));
         }
     }
+}
+
+// Inverse of one in-place kStream step's scatter: from a buffer that holds
+// T(S_k) in natural order (after kStream), writes S_k in natural order to
+// `out` (same pitch).  S_i(x) sits in slot i of x + xi_i, or, when that
+// neighbour lies beyond a wall, in slot opp(i) of x with the moving-wall term
+// added.  One thread per cell.
+template <int Q, typename T, typename C>
+__global__ void unstream_kernel(const StepArgs<C> a, T *out) {
+    constexpr int D = Lattice<Q>::D;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.nx * a.ny * a.nz) return;
+    const int x = c % a.nx;
+    const int y = (c / a.nx) % a.ny;
+    const int z = c / (a.nx * a.ny);
+    const Geo g = make_geo<D>(a, x, y, z);
+    void *src = const_cast<void *>(a.src);
+    static_for<0, Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int o = Vel<Q, i>::opp;
+        const Link<C> l = link<Q, o>(a, g);
+        const T *p = l.wall ? pair_addr<Q, i, T>(src, a.pitch, o, g.cell)
+                            : pair_addr<Q, i, T>(src, a.pitch, i, l.src);
+        const C v = static_cast<C>(*p) - l.corr;
+        out[(size_t)i * a.pitch + g.cell] = static_cast<T>(v);
+    });
 }
 
 }  // namespace lbm

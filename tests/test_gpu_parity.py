@@ -34,6 +34,13 @@ def lbm():
     return lbm
 
 
+@pytest.fixture(params=["inplace", "pingpong"])
+def scheme(request, monkeypatch):
+    """Streaming scheme of the handles a test creates (read at creation)."""
+    monkeypatch.setenv("LBM_STREAMING", request.param)
+    return request.param
+
+
 def _wall(lid=0.0, face=3, comp=0):
     w = [[0.0] * 3 for _ in range(6)]
     w[face][comp] = lid
@@ -92,9 +99,9 @@ _SMALL = [
 @pytest.mark.parametrize("storage", [0, 1, 2], ids=["f64", "f32", "f32s"])
 @pytest.mark.parametrize("kind", [0, 1], ids=["l2", "kkn"])
 @pytest.mark.parametrize("case", _SMALL, ids=[c[0] for c in _SMALL])
-def test_small_grids(lbm, orc, case, kind, storage):
+def test_small_grids(lbm, orc, case, kind, storage, scheme):
     name, q, n, bc, wall_u, tau, force, init = case
-    print(f"\n[case] {name} q={q} n={n} storage={storage} kind={kind}", flush=True)
+    print(f"\n[case] {name} q={q} n={n} storage={storage} kind={kind} {scheme}", flush=True)
     desc, G = _pair(lbm, orc, q, n, bc, wall_u, tau, storage, kind, force)
     u0 = None
     if init == "perturbed":
@@ -142,8 +149,51 @@ def test_config0_cavity2d_full(lbm, orc):
     blk.close()
 
 
+_PHASE_CASES = [
+    ("cav3d_lid", 19, (19, 10, 11), (WALL,) * 6, _wall(0.05), (0, 0, 0)),
+    ("mixed3d_force", 19, (16, 9, 12), (WALL, WALL, PERIODIC, PERIODIC, WALL, WALL), _wall(0.03, 5, 1),
+     (0, 1e-4, 0)),
+    ("cav2d_lid", 9, (21, 13, 1), (WALL, WALL, WALL, WALL, PERIODIC, PERIODIC), _wall(0.1), (0, 0, 0)),
+]
+
+
+@pytest.mark.parametrize("case", _PHASE_CASES, ids=[c[0] for c in _PHASE_CASES])
+@pytest.mark.parametrize("storage", [0, 2], ids=["f64", "f32s"])
+def test_state_readback_every_step(lbm, orc, case, storage, scheme):
+    """Populations, macroscopic fields and totals read back after 1, 2, 3, 4,
+    5 and 8 steps: the in-place scheme holds its state in two different
+    arrangements on odd and even steps, and every read must undo them."""
+    name, q, n, bc, wall_u, F = case
+    print(f"\n[case] readback {name} storage={storage} {scheme}", flush=True)
+    desc, G = _pair(lbm, orc, q, n, bc, wall_u, 0.7, storage, 0, F)
+    u0 = lbm_inputs.velocity_perturbation(n, 0.02, seed=4, dims=2 if q == 9 else 3)
+    blk = lbm.Blocks(desc)
+    blk.set_equilibrium(u=u0)
+    S = G.equilibrium_state(u=u0)
+    k = 0
+    tol = 1e-13 if storage == 0 else 2e-7
+    for target in (1, 2, 3, 4, 5, 8):
+        S, _ = G.run(S, k, target - k, 0)
+        blk.step_n(target - k, 1)
+        k = target
+        assert blk.step == k
+        assert np.abs(blk.populations() - S).max() < tol, f"populations after {k} steps"
+        rho, u = blk.macros()
+        rho_r, u_r = G.macros(S)
+        assert np.abs(u - u_r).max() < tol * 10 and np.abs(rho - rho_r).max() < tol * 10
+        assert np.abs(blk.conservation() - G.conservation(S)).max() < tol * G.cells
+        # a read does not disturb the run: the next sensor step still matches
+    bm, fl, kk, _ = blk.sensor_flags()
+    _, hist = G.run(S, k, 1, 1)
+    blk.step_n(1, 1)
+    bm, fl, kk, _ = blk.sensor_flags()
+    assert kk == k + 1
+    _compare_bmax(bm, hist[0][1], storage)
+    blk.close()
+
+
 @pytest.mark.parametrize("q", [9, 19])
-def test_generic_state_single_step(lbm, orc, q):
+def test_generic_state_single_step(lbm, orc, q, scheme):
     """One step from arbitrary positive populations (far from equilibrium):
     every arithmetic path of the kernel on generic inputs, FP64."""
     n = (37, 11, 1) if q == 9 else (19, 10, 9)
@@ -164,7 +214,7 @@ def test_generic_state_single_step(lbm, orc, q):
         blk.close()
 
 
-def test_nonfinite_population_is_flagged(lbm, orc):
+def test_nonfinite_population_is_flagged(lbm, orc, scheme):
     """A NaN written through set_populations gives flag 2 in its block and
     LBM_ENONFINITE, while the other blocks keep their flags."""
     n = (32, 16, 16)
@@ -184,7 +234,7 @@ def test_nonfinite_population_is_flagged(lbm, orc):
     blk.close()
 
 
-def test_determinism_and_checkpoint_resume(lbm, orc):
+def test_determinism_and_checkpoint_resume(lbm, orc, scheme):
     """Two runs are bitwise equal; stopping, saving the populations and the
     step counter, and resuming in a fresh handle is bitwise equal too."""
     n = (40, 24, 16)
@@ -213,7 +263,7 @@ def test_determinism_and_checkpoint_resume(lbm, orc):
 
 
 @pytest.mark.parametrize("storage", [0, 1, 2], ids=["f64", "f32", "f32s"])
-def test_conservation_totals(lbm, orc, storage):
+def test_conservation_totals(lbm, orc, storage, scheme):
     """FP64 totals of the stored state against the oracle's, and their
     invariance in a periodic box; with a body force the momentum grows by F
     per cell and step."""
