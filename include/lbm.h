@@ -117,8 +117,12 @@ typedef struct {
 
 /* Sizes in bytes of the five device buffers for descriptor d (its buf and
  * buf_bytes fields are ignored).  Pure host computation, no HIP call.
- *   F_A, F_B   : two population arrays (ping-pong), q padded planes each;
- *   BLOCK_MAX  : one float32 (F32 storages) or float64 (F64) per sensor block;
+ *   F_A, F_B   : two population arrays of q padded planes each.  Ping-pong
+ *                streaming alternates between them; the in-place scheme
+ *                (chosen for arrays up to 512 MiB) steps F_A only and uses F_B
+ *                as staging when states are read or written;
+ *   BLOCK_MAX  : one float32 (F32 storages) or float64 (F64) per sensor block,
+ *                followed by one 64-bit accumulator word per block;
  *   FLAGS      : one int8 per sensor block;
  *   SCRATCH    : staging for host transfers and the conservation partial sums.
  * Returns LBM_EINVAL / LBM_ENOTSUP for a bad descriptor. */
@@ -162,6 +166,13 @@ lbm_status lbm_set_populations(lbm_blocks *h, const double *f_host);
  * computed on the GPU in float64 from rho_host [cells] (NULL: rho0 everywhere)
  * and u_host [3][cells] (NULL: at rest).  Synchronises the stream. */
 lbm_status lbm_set_equilibrium(lbm_blocks *h, const double *rho_host, const double *u_host);
+
+/* How the handle streams: *inplace = 1 for the single-buffer scheme (steps
+ * alternate between a gather-scatter launch and a local launch; the step
+ * counter's parity says which comes next via *next_is_gather), 0 for
+ * ping-pong; *tile_x = workgroup tile width in cells.  Any pointer may be
+ * NULL.  Pure host query. */
+lbm_status lbm_get_scheme(lbm_blocks *h, int32_t *inplace, int32_t *next_is_gather, int32_t *tile_x);
 
 /* Step counter (number of steps taken since it was last set). */
 lbm_status lbm_get_step(lbm_blocks *h, int64_t *step);

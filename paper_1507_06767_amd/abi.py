@@ -76,6 +76,8 @@ def _load_library():
         "lbm_set_populations": [H, dp],
         "lbm_set_equilibrium": [H, dp, dp],
         "lbm_get_step": [H, ctypes.POINTER(ctypes.c_int64)],
+        "lbm_get_scheme": [H, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                           ctypes.POINTER(ctypes.c_int32)],
         "lbm_set_step": [H, ctypes.c_int64],
         "lbm_conservation": [H, dp],
         "lbm_tau_from_reynolds": [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp],
@@ -183,6 +185,13 @@ def lbm_get_step(h):
     s = ctypes.c_int64(0)
     st = _lib.lbm_get_step(h, ctypes.byref(s))
     return st, s.value
+
+
+def lbm_get_scheme(h):
+    """(status, inplace, next_is_gather, tile_x)."""
+    a, b, c = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+    st = _lib.lbm_get_scheme(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    return st, a.value, b.value, c.value
 
 
 def lbm_set_step(h, step: int):

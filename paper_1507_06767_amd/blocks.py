@@ -99,6 +99,12 @@ class Blocks:
     def step(self, value: int):
         _check(abi.lbm_set_step(self.h, value))
 
+    def scheme(self):
+        """dict(inplace, next_is_gather, tile_x) of the handle."""
+        st, ip, nxt, tx = abi.lbm_get_scheme(self.h)
+        _check(st)
+        return {"inplace": bool(ip), "next_is_gather": bool(nxt), "tile_x": tx}
+
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value is not None:
             abi.lbm_destroy(self.h)

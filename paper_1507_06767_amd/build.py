@@ -1,6 +1,7 @@
 """Build liblbm.so for gfx950 with hipcc (in-tree, next to this file).
 
-Run as ``python -m paper_1507_06767_amd.build``.  Flags: -O3, C++20, no
+Run as ``python paper_1507_06767_amd/build.py`` (by path: importing the
+package would load the library being rebuilt).  Flags: -O3, C++20, no
 fast-math (division and square root stay correctly rounded), and the packed
 FP32 instructions disabled for the device code.
 """

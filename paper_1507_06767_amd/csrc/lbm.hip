@@ -48,15 +48,19 @@ constexpr size_t kAlign = 256;
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Tile width: the narrowest of 32, 64, 128 that spans the grid's x extent
-// (128 for wide grids).  LBM_TILE_X (32, 64 or 128) overrides it for tuning.
-int tile_x_setting(int nx) {
+// Tile width: the narrowest of 32, 64, 128 that spans the grid's x extent,
+// capped at 64 for the in-place scheme and 128 for ping-pong (measured best:
+// 64 for the in-place 128^3 cavity, 128 for the ping-pong 256^3 one).
+// LBM_TILE_X (32, 64 or 128) overrides it for tuning.
+int tile_x_setting(int nx, bool inplace) {
     const char *s = std::getenv("LBM_TILE_X");
     if (s) {
         int v = std::atoi(s);
         if (v == 32 || v == 64 || v == 128) return v;
     }
-    return nx <= 32 ? 32 : (nx <= 64 ? 64 : 128);
+    const int cap = inplace ? 64 : 128;
+    const int fit = nx <= 32 ? 32 : (nx <= 64 ? 64 : 128);
+    return fit < cap ? fit : cap;
 }
 
 size_t plane_pad_setting() {
@@ -468,8 +472,8 @@ lbm_status lbm_create_blocks(const lbm_desc *d, const double *f0_host, lbm_block
     h->d = *d;
     h->L = L;
     h->stream = static_cast<hipStream_t>(d->stream);
-    h->tile_x = tile_x_setting(d->extent[0]);
     h->inplace = inplace_setting(d, L);
+    h->tile_x = tile_x_setting(d->extent[0], h->inplace);
     h->phase = 0;
     h->cur = 0;
     h->step = 0;
@@ -618,6 +622,14 @@ lbm_status lbm_set_equilibrium(lbm_blocks *h, const double *rho_host, const doub
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(h->stream));
     h->last_sensor_step = -1;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_scheme(lbm_blocks *h, int32_t *inplace, int32_t *next_is_gather, int32_t *tile_x) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    if (inplace) *inplace = h->inplace ? 1 : 0;
+    if (next_is_gather) *next_is_gather = (h->inplace && h->phase == 0) ? 1 : 0;
+    if (tile_x) *tile_x = h->tile_x;
     return LBM_OK;
 }
 
