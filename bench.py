@@ -6,7 +6,7 @@ and the refine/coarsen flags evaluated at every step.  A "step" is one
 launch of the fused kernel over the whole grid.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--workload cavity128|cavity256|channel256]
-                  [--storage f32|f32s|f64] [--no-cpu-baseline]
+                  [--storage f32|f32s|f64|f16s|bf16s|f16sr|bf16sr] [--no-cpu-baseline]
 
 MLUPS = cells * K / t / 1e6 over K back-to-back steps (HIP events on the
 library's stream).  The roofline entry prices the dominant kernel at its
@@ -110,7 +110,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="cavity128")
-    ap.add_argument("--storage", default="f32", choices=["f32", "f32s", "f64"])
+    ap.add_argument("--storage", default="f32", choices=["f32", "f32s", "f64", "f16s", "bf16s", "f16sr", "bf16sr"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=20)
     ap.add_argument("--kernel-samples", type=int, default=200,
@@ -126,7 +126,9 @@ def main():
     import torch
     import paper_1507_06767_amd as lbm
 
-    storage = {"f32": lbm.LBM_F32, "f32s": lbm.LBM_F32_SHIFTED, "f64": lbm.LBM_F64}[args.storage]
+    storage = {"f32": lbm.LBM_F32, "f32s": lbm.LBM_F32_SHIFTED, "f64": lbm.LBM_F64,
+               "f16s": lbm.LBM_F16_SHIFTED, "bf16s": lbm.LBM_BF16_SHIFTED,
+               "f16sr": lbm.LBM_F16_SHIFTED_SR, "bf16sr": lbm.LBM_BF16_SHIFTED_SR}[args.storage]
     w = _workload(args.workload, args.storage)
     if w.reynolds is not None:
         st, tau = lbm.lbm_tau_from_reynolds(w.lid_speed, w.n_across, w.reynolds)
@@ -173,7 +175,7 @@ def main():
     per = {kind: sum(v) / len(v) for kind, v in per.items() if v}
     dominant = max(per, key=per.get)
 
-    elem = 8 if storage == lbm.LBM_F64 else 4
+    elem = 8 if storage == lbm.LBM_F64 else (2 if storage >= lbm.LBM_F16_SHIFTED else 4)
     bytes_per_update = 2 * w.q * elem
     sec = ms / 1e3
     mlups = w.cells * args.steps / sec / 1e6

@@ -72,7 +72,9 @@ enum {
 };
 
 enum { LBM_D2Q9 = 9, LBM_D3Q19 = 19 };                          /* lbm_desc.lattice */
-enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F32_SHIFTED = 2 };         /* lbm_desc.storage */
+enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F32_SHIFTED = 2,          /* lbm_desc.storage */
+       LBM_F16_SHIFTED = 3, LBM_BF16_SHIFTED = 4,
+       LBM_F16_SHIFTED_SR = 5, LBM_BF16_SHIFTED_SR = 6 };
 enum { LBM_SENSOR_L2 = 0, LBM_SENSOR_KKN = 1 };                 /* lbm_desc.sensor_kind */
 enum { LBM_BC_PERIODIC = 0, LBM_BC_WALL = 1 };                  /* lbm_desc.face_bc[] */
 enum { LBM_BUF_F_A = 0, LBM_BUF_F_B = 1, LBM_BUF_BLOCK_MAX = 2,  /* lbm_desc.buf[] */
@@ -89,7 +91,14 @@ typedef struct {
     int32_t storage;        /* LBM_F64: populations and arithmetic in float64.
                                LBM_F32: float32 populations f_i, float32 arithmetic.
                                LBM_F32_SHIFTED: float32 stores f_i - w_i rho0,
-                               float32 arithmetic (same bytes, finer rounding). */
+                               float32 arithmetic (same bytes, finer rounding).
+                               LBM_F16_SHIFTED / LBM_BF16_SHIFTED: IEEE half / bfloat16
+                               store f_i - w_i rho0 (half the bytes), float32
+                               arithmetic, rounding to nearest even on store.
+                               LBM_F16_SHIFTED_SR / LBM_BF16_SHIFTED_SR: the same with
+                               stochastic rounding on store (unbiased; the random
+                               bits hash (cell, population, step), so runs are
+                               reproducible bit for bit). */
     int32_t sensor_kind;    /* LBM_SENSOR_L2: ||f^neq||_2 / ||f^eq||_2;
                                LBM_SENSOR_KKN: (1/q) sum_i |f^neq_i / f^eq_i| (Eq. kkn) */
     int32_t extent[3];      /* cells along x, y, z; extent[2] == 1 for D2Q9;
@@ -121,7 +130,7 @@ typedef struct {
  *                streaming alternates between them; the in-place scheme
  *                (chosen for arrays up to 512 MiB) steps F_A only and uses F_B
  *                as staging when states are read or written;
- *   BLOCK_MAX  : one float32 (F32 storages) or float64 (F64) per sensor block,
+ *   BLOCK_MAX  : one float32 (float32/16-bit storages) or float64 (F64) per block,
  *                followed by one 64-bit accumulator word per block;
  *   FLAGS      : one int8 per sensor block;
  *   SCRATCH    : staging for host transfers and the conservation partial sums.

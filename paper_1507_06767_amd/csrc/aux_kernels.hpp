@@ -11,6 +11,20 @@
 
 namespace lbm {
 
+// Conversions between the storage type and float64 (16-bit types go
+// through float32).
+template <typename T>
+__device__ __forceinline__ T to_store(double v) {
+    if constexpr (sizeof(T) == 2) return static_cast<T>(static_cast<float>(v));
+    else return static_cast<T>(v);
+}
+
+template <typename T>
+__device__ __forceinline__ double from_store(T v) {
+    if constexpr (sizeof(T) == 2) return static_cast<double>(static_cast<float>(v));
+    else return static_cast<double>(v);
+}
+
 template <typename T>
 struct Planes {
     T *f;              // plane i at f + i*pitch
@@ -26,7 +40,7 @@ __global__ void init_rest_kernel(Planes<T> p, double rho0) {
     if (c >= p.cells) return;
     static_for<0, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        p.f[(int64_t)i * p.pitch + c] = static_cast<T>(Vel<Q, i>::w * rho0 - p.shift[i]);
+        p.f[(int64_t)i * p.pitch + c] = to_store<T>(Vel<Q, i>::w * rho0 - p.shift[i]);
     });
 }
 
@@ -52,14 +66,14 @@ __global__ void swap_planes_kernel(const T *in, T *out, int64_t pitch, int cells
 template <typename T>
 __global__ void import_plane_kernel(const double *in, T *out, int cells, double shift) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < cells) out[c] = static_cast<T>(in[c] - shift);
+    if (c < cells) out[c] = to_store<T>(in[c] - shift);
 }
 
 // One plane to float64 staging: out = (double)in + shift.
 template <typename T>
 __global__ void export_plane_kernel(const T *in, double *out, int cells, double shift) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < cells) out[c] = static_cast<double>(in[c]) + shift;
+    if (c < cells) out[c] = from_store<T>(in[c]) + shift;
 }
 
 // f^eq(rho, u) of Eq. feq_i in float64, stored as f^eq_i - shift_i.
@@ -81,7 +95,7 @@ __global__ void equilibrium_kernel(Planes<T> p, const double *rho, const double 
         using V = Vel<Q, i>;
         const double cu = V::x * uu[0] + V::y * uu[1] + V::z * uu[2];
         const double feq = V::w * r * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
-        p.f[(int64_t)i * p.pitch + c] = static_cast<T>(feq - p.shift[i]);
+        p.f[(int64_t)i * p.pitch + c] = to_store<T>(feq - p.shift[i]);
     });
 }
 
@@ -95,7 +109,7 @@ __global__ void macros_kernel(Planes<T> p, double *rho_out, double *u_out, doubl
     static_for<0, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         using V = Vel<Q, i>;
-        const double v = static_cast<double>(p.f[(int64_t)i * p.pitch + c]);
+        const double v = from_store<T>(p.f[(int64_t)i * p.pitch + c]);
         rho += v + p.shift[i];
         if constexpr (V::x != 0) m[0] += V::x * v;   // the shifts cancel in pairs
         if constexpr (V::y != 0) m[1] += V::y * v;
@@ -137,7 +151,7 @@ __global__ __launch_bounds__(kReduceThreads) void conservation_pass1(Planes<T> p
         static_for<0, Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             using V = Vel<Q, i>;
-            const double v = static_cast<double>(p.f[(int64_t)i * p.pitch + c]);
+            const double v = from_store<T>(p.f[(int64_t)i * p.pitch + c]);
             acc[0] += v + p.shift[i];
             if constexpr (V::x != 0) acc[1] += V::x * v;
             if constexpr (V::y != 0) acc[2] += V::y * v;

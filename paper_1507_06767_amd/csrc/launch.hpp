@@ -1,0 +1,81 @@
+// launch.hpp -- host-side launch of the step kernels.
+//
+// The kernel variants (lattice x storage x sensor kind x force x tile width x
+// streaming scheme) are instantiated in one translation unit per storage
+// family (step_f64.hip, step_f32.hip, step_f16.hip, step_bf16.hip) so that
+// they compile in parallel; lbm.hip only sees the declaration.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "step_kernel.hpp"
+
+namespace lbm {
+
+struct LaunchCfg {
+    hipStream_t stream;
+    int tile_x;        // 32, 64 or 128 (step_zmarch: 64)
+    int scheme;        // kPingPong, kStream or kLocal
+    bool sensor;       // evaluate sensor, block maxima and flags in this step
+    int sensor_kind;   // kSensorL2 or kSensorKKn
+    bool force;        // body force present
+};
+
+// 3D float64 marches over z inside a workgroup (a 64-bit block maximum
+// leaves no room for the arrival count of step_cells); every other form runs
+// one cell per thread.
+template <int Q, typename C>
+constexpr bool uses_zmarch() {
+    return Lattice<Q>::D == 3 && sizeof(C) == 8;
+}
+
+// Enqueues one step of lattice Q, storage policy T and arithmetic C.
+template <int Q, typename T, typename C, bool SH>
+void launch_step_kernel(const StepArgs<C> &a, const LaunchCfg &c);
+
+#ifdef LBM_LAUNCH_DEFINITIONS
+template <bool ZM, int Q, typename T, typename C, bool SH, bool SENS, int SK, bool FORCE, int BX, int SCH>
+void launch_one(hipStream_t st, const StepArgs<C> &a) {
+    const dim3 g(a.ntiles), b(BX, kTileY);
+    if constexpr (ZM) hipLaunchKernelGGL((step_zmarch<Q, T, C, SH, SENS, SK, FORCE, BX>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((step_cells<Q, T, C, SH, SENS, SK, FORCE, BX, SCH>), g, b, 0, st, a);
+}
+
+template <bool ZM, int Q, typename T, typename C, bool SH, int BX, int SCH>
+void launch_sk(const StepArgs<C> &a, const LaunchCfg &c) {
+    if (!c.sensor) {
+        if (c.force) launch_one<ZM, Q, T, C, SH, false, kSensorL2, true, BX, SCH>(c.stream, a);
+        else launch_one<ZM, Q, T, C, SH, false, kSensorL2, false, BX, SCH>(c.stream, a);
+    } else if (c.sensor_kind == kSensorL2) {
+        if (c.force) launch_one<ZM, Q, T, C, SH, true, kSensorL2, true, BX, SCH>(c.stream, a);
+        else launch_one<ZM, Q, T, C, SH, true, kSensorL2, false, BX, SCH>(c.stream, a);
+    } else {
+        if (c.force) launch_one<ZM, Q, T, C, SH, true, kSensorKKn, true, BX, SCH>(c.stream, a);
+        else launch_one<ZM, Q, T, C, SH, true, kSensorKKn, false, BX, SCH>(c.stream, a);
+    }
+}
+
+template <int Q, typename T, typename C, bool SH, int BX>
+void launch_scheme(const StepArgs<C> &a, const LaunchCfg &c) {
+    switch (c.scheme) {
+        case kStream: launch_sk<false, Q, T, C, SH, BX, kStream>(a, c); break;
+        case kLocal: launch_sk<false, Q, T, C, SH, BX, kLocal>(a, c); break;
+        default: launch_sk<false, Q, T, C, SH, BX, kPingPong>(a, c); break;
+    }
+}
+
+template <int Q, typename T, typename C, bool SH>
+void launch_step_kernel(const StepArgs<C> &a, const LaunchCfg &c) {
+    if constexpr (uses_zmarch<Q, C>()) {
+        launch_sk<true, Q, T, C, SH, 64, kPingPong>(a, c);
+    } else {
+        switch (c.tile_x) {
+            case 32: launch_scheme<Q, T, C, SH, 32>(a, c); break;
+            case 64: launch_scheme<Q, T, C, SH, 64>(a, c); break;
+            default: launch_scheme<Q, T, C, SH, 128>(a, c); break;
+        }
+    }
+}
+#endif
+
+}  // namespace lbm

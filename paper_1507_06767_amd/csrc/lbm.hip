@@ -13,10 +13,12 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "lbm.h"
 #include "aux_kernels.hpp"
+#include "launch.hpp"
 #include "step_kernel.hpp"
 
 using namespace lbm;
@@ -93,7 +95,7 @@ lbm_status check_desc(const lbm_desc *d, Layout *L) {
         return fail(LBM_EINVAL, "abi_version %u, library has %u", d->abi_version, LBM_ABI_VERSION);
     if (d->lattice != LBM_D2Q9 && d->lattice != LBM_D3Q19)
         return fail(LBM_ENOTSUP, "lattice %d not supported (9 or 19)", d->lattice);
-    if (d->storage != LBM_F64 && d->storage != LBM_F32 && d->storage != LBM_F32_SHIFTED)
+    if (d->storage < LBM_F64 || d->storage > LBM_BF16_SHIFTED_SR)
         return fail(LBM_ENOTSUP, "storage %d not supported", d->storage);
     if (d->sensor_kind != LBM_SENSOR_L2 && d->sensor_kind != LBM_SENSOR_KKN)
         return fail(LBM_EINVAL, "sensor_kind %d", d->sensor_kind);
@@ -131,8 +133,8 @@ lbm_status check_desc(const lbm_desc *d, Layout *L) {
     L->q = d->lattice;
     L->dim = dim;
     L->cells = cells;
-    L->elem = (d->storage == LBM_F64) ? 8 : 4;
-    L->cbytes = L->elem;
+    L->elem = (d->storage == LBM_F64) ? 8 : (d->storage <= LBM_F32_SHIFTED ? 4 : 2);
+    L->cbytes = (d->storage == LBM_F64) ? 8 : 4;   // block maxima in the arithmetic type
     const size_t plane = round_up((size_t)cells * L->elem, kAlign) + plane_pad_setting();
     L->pitch = (int64_t)(plane / L->elem);
     // the kernels address two adjacent planes with a 32-bit byte offset
@@ -233,7 +235,7 @@ Planes<T> planes_of(lbm_blocks *h, void *buf) {
     p.f = static_cast<T *>(buf);
     p.pitch = h->L.pitch;
     p.cells = (int)h->L.cells;
-    const bool shifted = h->d.storage == LBM_F32_SHIFTED;
+    const bool shifted = h->d.storage >= LBM_F32_SHIFTED;
     static_for<0, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         p.shift[i] = shifted ? Vel<Q, i>::w * h->d.rho0 : 0.0;
@@ -275,6 +277,7 @@ StepArgs<C> step_args(lbm_blocks *h, const void *src, void *dst, bool zmarch, in
     for (int c = 0; c < 3; ++c) a.F[c] = (C)d.force[c];
     a.theta_r = d.theta_refine;
     a.theta_c = d.theta_coarsen;
+    a.step = (uint32_t)(h->step + 1);
     a.block_max = static_cast<C *>(d.buf[LBM_BUF_BLOCK_MAX]);
     a.flags = static_cast<int8_t *>(d.buf[LBM_BUF_FLAGS]);
     a.acc = reinterpret_cast<unsigned long long *>(static_cast<char *>(d.buf[LBM_BUF_BLOCK_MAX]) +
@@ -283,17 +286,22 @@ StepArgs<C> step_args(lbm_blocks *h, const void *src, void *dst, bool zmarch, in
 }
 
 // Calls f.template operator()<Q, T>() for the handle's lattice and storage type.
+template <int Q, typename F>
+void with_storage_type(lbm_blocks *h, F &&f) {
+    switch (h->d.storage) {
+        case LBM_F64: f.template operator()<Q, double>(); break;
+        case LBM_F16_SHIFTED:
+        case LBM_F16_SHIFTED_SR: f.template operator()<Q, _Float16>(); break;
+        case LBM_BF16_SHIFTED:
+        case LBM_BF16_SHIFTED_SR: f.template operator()<Q, __bf16>(); break;
+        default: f.template operator()<Q, float>(); break;
+    }
+}
+
 template <typename F>
 void with_types(lbm_blocks *h, F &&f) {
-    const int q = h->d.lattice;
-    const bool dbl = h->d.storage == LBM_F64;
-    if (q == 9) {
-        if (dbl) f.template operator()<9, double>();
-        else f.template operator()<9, float>();
-    } else {
-        if (dbl) f.template operator()<19, double>();
-        else f.template operator()<19, float>();
-    }
+    if (h->d.lattice == 9) with_storage_type<9>(h, f);
+    else with_storage_type<19>(h, f);
 }
 
 unsigned grid_for(int64_t n) { return (unsigned)((n + kAuxThreads - 1) / kAuxThreads); }
@@ -307,61 +315,20 @@ void reset_accumulators(lbm_blocks *h) {
                        acc, (int)h->L.nblocks);
 }
 
-template <bool ZM, int Q, typename T, typename C, bool SH, bool SENS, int SK, bool FORCE, int BX, int SCH>
-void launch_one(hipStream_t st, const StepArgs<C> &a) {
-    const dim3 g(a.ntiles), b(BX, kTileY);
-    if constexpr (ZM) hipLaunchKernelGGL((step_zmarch<Q, T, C, SH, SENS, SK, FORCE, BX>), g, b, 0, st, a);
-    else hipLaunchKernelGGL((step_cells<Q, T, C, SH, SENS, SK, FORCE, BX, SCH>), g, b, 0, st, a);
-}
-
-template <bool ZM, int Q, typename T, typename C, bool SH, int BX, int SCH>
-void launch_sk(hipStream_t st, const StepArgs<C> &a, bool sens, int sk, bool force) {
-    if (!sens) {
-        if (force) launch_one<ZM, Q, T, C, SH, false, kSensorL2, true, BX, SCH>(st, a);
-        else launch_one<ZM, Q, T, C, SH, false, kSensorL2, false, BX, SCH>(st, a);
-    } else if (sk == kSensorL2) {
-        if (force) launch_one<ZM, Q, T, C, SH, true, kSensorL2, true, BX, SCH>(st, a);
-        else launch_one<ZM, Q, T, C, SH, true, kSensorL2, false, BX, SCH>(st, a);
-    } else {
-        if (force) launch_one<ZM, Q, T, C, SH, true, kSensorKKn, true, BX, SCH>(st, a);
-        else launch_one<ZM, Q, T, C, SH, true, kSensorKKn, false, BX, SCH>(st, a);
-    }
-}
-
-template <bool ZM, int Q, typename T, typename C, bool SH, int BX>
-void launch_bx(hipStream_t st, const StepArgs<C> &a, bool sens, int sk, bool force, int scheme) {
-    if constexpr (ZM) {
-        launch_sk<true, Q, T, C, SH, BX, kPingPong>(st, a, sens, sk, force);
-    } else {
-        switch (scheme) {
-            case kStream: launch_sk<false, Q, T, C, SH, BX, kStream>(st, a, sens, sk, force); break;
-            case kLocal: launch_sk<false, Q, T, C, SH, BX, kLocal>(st, a, sens, sk, force); break;
-            default: launch_sk<false, Q, T, C, SH, BX, kPingPong>(st, a, sens, sk, force); break;
-        }
-    }
-}
-
-// 3D float64 storage marches over z inside a workgroup (its 64-bit block
-// maximum leaves no room for the arrival count of step_cells); every other
-// form runs one cell per thread.
 template <int Q, typename T, typename C, bool SH>
 void launch_step(lbm_blocks *h, bool sens) {
     void *src = state_ptr(h);
     void *dst = h->inplace ? src : h->d.buf[h->cur ? LBM_BUF_F_A : LBM_BUF_F_B];
-    const int scheme = !h->inplace ? kPingPong : (h->phase == 0 ? kStream : kLocal);
-    const int sk = h->d.sensor_kind;
-    constexpr bool zm = (Lattice<Q>::D == 3) && (sizeof(C) == 8);
-    if constexpr (zm) {
-        const StepArgs<C> a = step_args<Q, C>(h, src, dst, true, 64);
-        launch_bx<true, Q, T, C, SH, 64>(h->stream, a, sens, sk, h->has_force, kPingPong);
-    } else {
-        const StepArgs<C> a = step_args<Q, C>(h, src, dst, false, h->tile_x);
-        switch (h->tile_x) {
-            case 32: launch_bx<false, Q, T, C, SH, 32>(h->stream, a, sens, sk, h->has_force, scheme); break;
-            case 64: launch_bx<false, Q, T, C, SH, 64>(h->stream, a, sens, sk, h->has_force, scheme); break;
-            default: launch_bx<false, Q, T, C, SH, 128>(h->stream, a, sens, sk, h->has_force, scheme); break;
-        }
-    }
+    LaunchCfg c;
+    c.stream = h->stream;
+    c.scheme = !h->inplace ? kPingPong : (h->phase == 0 ? kStream : kLocal);
+    c.sensor = sens;
+    c.sensor_kind = h->d.sensor_kind;
+    c.force = h->has_force;
+    constexpr bool zm = uses_zmarch<Q, C>();
+    c.tile_x = zm ? 64 : h->tile_x;
+    const StepArgs<C> a = step_args<Q, C>(h, src, dst, zm, c.tile_x);
+    launch_step_kernel<Q, T, C, SH>(a, c);
 }
 
 // Where host data and initial states are written: the state buffer for
@@ -392,7 +359,7 @@ void *canonical_state(lbm_blocks *h) {
                                h->stream, static_cast<const T *>(A), static_cast<T *>(B), h->L.pitch,
                                (int)h->L.cells);
         } else {
-            using C = T;
+            using C = std::conditional_t<sizeof(T) == 8, double, float>;
             const StepArgs<C> a = step_args<Q, C>(h, A, B, false, h->tile_x);
             hipLaunchKernelGGL((unstream_kernel<Q, T, C>), dim3(grid_for(h->L.cells)), dim3(kAuxThreads), 0,
                                h->stream, a, static_cast<T *>(B));
@@ -406,11 +373,19 @@ void launch_step_any(lbm_blocks *h, bool sens) {
     if (q == 9) {
         if (s == LBM_F64) launch_step<9, double, double, false>(h, sens);
         else if (s == LBM_F32) launch_step<9, float, float, false>(h, sens);
-        else launch_step<9, float, float, true>(h, sens);
+        else if (s == LBM_F32_SHIFTED) launch_step<9, float, float, true>(h, sens);
+        else if (s == LBM_F16_SHIFTED) launch_step<9, _Float16, float, true>(h, sens);
+        else if (s == LBM_BF16_SHIFTED) launch_step<9, __bf16, float, true>(h, sens);
+        else if (s == LBM_F16_SHIFTED_SR) launch_step<9, half_sr, float, true>(h, sens);
+        else launch_step<9, bf16_sr, float, true>(h, sens);
     } else {
         if (s == LBM_F64) launch_step<19, double, double, false>(h, sens);
         else if (s == LBM_F32) launch_step<19, float, float, false>(h, sens);
-        else launch_step<19, float, float, true>(h, sens);
+        else if (s == LBM_F32_SHIFTED) launch_step<19, float, float, true>(h, sens);
+        else if (s == LBM_F16_SHIFTED) launch_step<19, _Float16, float, true>(h, sens);
+        else if (s == LBM_BF16_SHIFTED) launch_step<19, __bf16, float, true>(h, sens);
+        else if (s == LBM_F16_SHIFTED_SR) launch_step<19, half_sr, float, true>(h, sens);
+        else launch_step<19, bf16_sr, float, true>(h, sens);
     }
 }
 

@@ -63,6 +63,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "lattice.hpp"
 
 namespace lbm {
@@ -91,6 +93,7 @@ struct StepArgs {
     C rho0;
     C F[3];                 // body-force density
     double theta_r, theta_c;
+    uint32_t step;          // index of the step this launch computes (stochastic rounding key)
     C *block_max;           // [nbz][nby][nbx]
     int8_t *flags;          // [nbz][nby][nbx]
     unsigned long long *acc;  // per block (count << 32 | max bits), zero between sensor steps
@@ -202,14 +205,90 @@ __device__ __forceinline__ Link<C> link(const StepArgs<C> &a, const Geo &g) {
     return l;
 }
 
+// Storage policies.  A plain type (double, float, _Float16, __bf16) is stored
+// with its conversion's rounding, to nearest even.  half_sr / bf16_sr store
+// IEEE half / bfloat16 with stochastic rounding: a value between two
+// representable neighbours goes to the upper one with probability equal to
+// its distance from the lower one, in units of their spacing.  Rounding is
+// then unbiased, so per-step increments smaller than half a unit in the last
+// place are not lost (round-to-nearest would return the same stored value
+// step after step).  The random bits come from a hash of (cell, population,
+// step), so a run is reproducible bit for bit.
+struct half_sr {};
+struct bf16_sr {};
+
+template <typename T>
+struct Storage {
+    using raw = T;
+    static constexpr bool sr = false;
+};
+template <>
+struct Storage<half_sr> {
+    using raw = _Float16;
+    static constexpr bool sr = true;
+};
+template <>
+struct Storage<bf16_sr> {
+    using raw = __bf16;
+    static constexpr bool sr = true;
+};
+
+// MurmurHash3's 32-bit finaliser (Appleby), a bijective avalanche mix.
+__device__ __forceinline__ uint32_t mix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+// Random bits for population `pop` of a cell: one full mix per (cell, step)
+// (cell_key), then a cheap multiply-xorshift per population, whose upper bits
+// are the ones the rounding uses.
+__device__ __forceinline__ uint32_t cell_key(uint32_t cell, uint32_t step) {
+    return mix32(cell * 0x9E3779B1u + step * 0x7FEB352Du + 0x2545F491u);
+}
+
+__device__ __forceinline__ uint32_t round_key(uint32_t ckey, int pop) {
+    uint32_t h = (ckey ^ ((uint32_t)pop * 0x9E3779B9u)) * 0x85EBCA6Bu;
+    return h ^ (h >> 15);
+}
+
+// x converted to the stored representation of policy T.
+template <typename T, typename C>
+__device__ __forceinline__ typename Storage<T>::raw to_storage(C x, uint32_t key) {
+    if constexpr (std::is_same_v<T, bf16_sr>) {
+        // bfloat16 keeps the upper 16 bits of a float: add a uniform 16-bit
+        // dither to the dropped bits and truncate (finite values only)
+        uint32_t b = __float_as_uint(static_cast<float>(x));
+        if ((b & 0x7F800000u) != 0x7F800000u) b += key >> 16;
+        return __builtin_bit_cast(__bf16, static_cast<uint16_t>(b >> 16));
+    } else if constexpr (std::is_same_v<T, half_sr>) {
+        // add uniform noise of one half-precision spacing, centred, then
+        // round to nearest: the upper neighbour wins with the right probability
+        const float xf = static_cast<float>(x);
+        int e = (int)((__float_as_uint(xf) >> 23) & 0xFFu) - 127;
+        e = e < -14 ? -14 : e;                                   // subnormal spacing 2^-24
+        const float ulp = __uint_as_float((uint32_t)(e - 10 + 127) << 23);
+        const float u = static_cast<float>(key >> 8) * 0x1p-24f;  // [0, 1)
+        return static_cast<_Float16>(xf + (u - 0.5f) * ulp);
+    } else {
+        (void)key;
+        return static_cast<T>(x);
+    }
+}
+
 // Element address inside planes {I, opp(I)}: both candidates of every access
 // lie in those two planes, so they are addressed from the lower of the two
 // with a non-negative 32-bit offset.
 template <int Q, int I, typename T>
-__device__ __forceinline__ T *pair_addr(void *buf, uint32_t pitch, int plane, uint32_t cell) {
+__device__ __forceinline__ typename Storage<T>::raw *pair_addr(void *buf, uint32_t pitch, int plane,
+                                                                uint32_t cell) {
+    using R = typename Storage<T>::raw;
     constexpr int lo = (Vel<Q, I>::opp < I) ? Vel<Q, I>::opp : I;
-    const uint32_t boff = ((uint32_t)(plane - lo) * pitch + cell) * (uint32_t)sizeof(T);
-    return reinterpret_cast<T *>(static_cast<char *>(buf) + (size_t)lo * pitch * sizeof(T) + boff);
+    const uint32_t boff = ((uint32_t)(plane - lo) * pitch + cell) * (uint32_t)sizeof(R);
+    return reinterpret_cast<R *>(static_cast<char *>(buf) + (size_t)lo * pitch * sizeof(R) + boff);
 }
 
 // The q pre-collision populations of the cell as shifted values
@@ -231,8 +310,8 @@ __device__ __forceinline__ void load_cell(const StepArgs<C> &a, const Geo &g, C 
             const Link<C> l = link<Q, i>(a, g);
             const int plane_pull = (SCHEME == kPingPong) ? i : o;
             const int plane_bounce = (SCHEME == kPingPong) ? o : i;
-            const T *p = l.wall ? pair_addr<Q, i, T>(src, a.pitch, plane_bounce, g.cell)
-                                : pair_addr<Q, i, T>(src, a.pitch, plane_pull, l.src);
+            const auto *p = l.wall ? pair_addr<Q, i, T>(src, a.pitch, plane_bounce, g.cell)
+                                   : pair_addr<Q, i, T>(src, a.pitch, plane_pull, l.src);
             v = static_cast<C>(*p);
             corr = l.corr;
         }
@@ -248,18 +327,19 @@ __device__ __forceinline__ void load_cell(const StepArgs<C> &a, const Geo &g, C 
 //              the next step; if x + xi_I lies beyond a wall the value
 //              returns to the cell as opp(I) with the moving-wall term.
 template <int Q, int I, typename T, typename C, int SCHEME>
-__device__ __forceinline__ void store_pop(const StepArgs<C> &a, const Geo &g, C out) {
+__device__ __forceinline__ void store_pop(const StepArgs<C> &a, const Geo &g, C out, uint32_t ckey) {
     constexpr int o = Vel<Q, I>::opp;
+    const uint32_t key = Storage<T>::sr ? round_key(ckey, I) : 0u;
     if constexpr (SCHEME == kPingPong) {
-        __builtin_nontemporal_store(static_cast<T>(out), pair_addr<Q, I, T>(a.dst, a.pitch, I, g.cell));
+        __builtin_nontemporal_store(to_storage<T>(out, key), pair_addr<Q, I, T>(a.dst, a.pitch, I, g.cell));
     } else if constexpr (SCHEME == kLocal) {
-        *pair_addr<Q, I, T>(a.dst, a.pitch, o, g.cell) = static_cast<T>(out);
+        *pair_addr<Q, I, T>(a.dst, a.pitch, o, g.cell) = to_storage<T>(out, key);
     } else {
         // the scatter link of I is the pull link of opp(I) read backwards
         const Link<C> l = link<Q, o>(a, g);
-        T *p = l.wall ? pair_addr<Q, I, T>(a.dst, a.pitch, o, g.cell)
-                      : pair_addr<Q, I, T>(a.dst, a.pitch, I, l.src);
-        *p = static_cast<T>(out + l.corr);
+        auto *p = l.wall ? pair_addr<Q, I, T>(a.dst, a.pitch, o, g.cell)
+                         : pair_addr<Q, I, T>(a.dst, a.pitch, I, l.src);
+        *p = to_storage<T>(out + l.corr, key);
     }
 }
 
@@ -292,6 +372,7 @@ __device__ __forceinline__ C collide_store(const StepArgs<C> &a, const Geo &g, c
     if constexpr (FORCE) uF = u[0] * a.F[0] + u[1] * a.F[1] + u[2] * a.F[2];
 
     C num = C(0), den = C(0), kkn = C(0);
+    const uint32_t ckey = Storage<T>::sr ? cell_key(g.cell, a.step) : 0u;
     static_for<0, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         using V = Vel<Q, i>;
@@ -321,7 +402,7 @@ __device__ __forceinline__ C collide_store(const StepArgs<C> &a, const Geo &g, c
             out += a.guo * wmul<C, V::w>(C(3) * (cF - uF) + C(9) * cu * cF);
         }
         if constexpr (!SHIFTED) out += a.shift[i];
-        store_pop<Q, i, T, C, SCHEME>(a, g, out);
+        store_pop<Q, i, T, C, SCHEME>(a, g, out, ckey);
     });
     if constexpr (SENSOR) {
         if constexpr (SKIND == kSensorL2) return num / den;
