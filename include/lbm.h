@@ -133,7 +133,8 @@ typedef struct {
  *   BLOCK_MAX  : one float32 (float32/16-bit storages) or float64 (F64) per block,
  *                followed by one 64-bit accumulator word per block;
  *   FLAGS      : one int8 per sensor block;
- *   SCRATCH    : staging for host transfers and the conservation partial sums.
+ *   SCRATCH    : staging for host transfers, the conservation partial sums, the
+ *                per-cell sums of the time-averaged sensor and the level maps.
  * Returns LBM_EINVAL / LBM_ENOTSUP for a bad descriptor. */
 lbm_status lbm_required_bytes(const lbm_desc *d, size_t bytes[LBM_NBUF]);
 
@@ -156,6 +157,28 @@ lbm_status lbm_step_n(lbm_blocks *h, int64_t n, int32_t sensor_every);
  * LBM_ENONFINITE if some block maximum is NaN or Inf (outputs still written). */
 lbm_status lbm_sensor_flags(lbm_blocks *h, double *block_max_host, int8_t *flags_host,
                             int64_t *step_index);
+
+/* Refinement level of every sensor block from the block maxima M of the
+ * latest sensor step (Sec. 3.4): phi = log2 M, l = clamp(floor(a phi + b),
+ * lmin, lmax); a non-finite M gives lmax and M = 0 gives lmin.  The offset b
+ * is this library's addition: with a alone, sensor values near 1e-3
+ * (phi ~ -10) cannot be placed on levels >= 0.  Then the buffer layer of
+ * Sec. 5.2: each block takes the largest level within `buffer` blocks
+ * (Chebyshev distance, 0..8).  levels_host: int8 [nbz][nby][nbx].
+ * Synchronises the stream; LBM_ESTATE if no sensor step has run. */
+lbm_status lbm_sensor_levels(lbm_blocks *h, double a, double b, int32_t lmin, int32_t lmax,
+                             int32_t buffer, int8_t *levels_host);
+
+/* Time-averaged sensor (Sec. 5.1 averages the sensor over a period before
+ * building its mesh).  _begin clears per-cell running sums; from then on
+ * every sensor step adds each cell's sensor value.  lbm_sensor_average
+ * returns, per block, the largest time-averaged cell value (float64,
+ * [nbz][nby][nbx]; NULL allowed) and the number of sensor steps summed.
+ * _end stops accumulating (the sums stay readable).  The sums live in the
+ * scratch buffer; lbm_sensor_average synchronises the stream. */
+lbm_status lbm_sensor_average_begin(lbm_blocks *h);
+lbm_status lbm_sensor_average(lbm_blocks *h, double *block_max_host, int64_t *samples);
+lbm_status lbm_sensor_average_end(lbm_blocks *h);
 
 /* Synchronises the stream and returns the macroscopic fields of the stored
  * state computed in float64: rho = sum_i S_i, u = (sum_i xi_i S_i - F/2) / rho

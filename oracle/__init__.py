@@ -102,6 +102,8 @@ def _load():
         lib.orc_run.restype = ctypes.c_int64
         lib.orc_conservation.argtypes = [P, dp, dp]
         lib.orc_equilibrium_field.argtypes = [P, dp, dp, dp]
+        lib.orc_levels.argtypes = [P, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                   ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int8)]
         _lib = lib
     return _lib
 
@@ -249,6 +251,31 @@ class Grid:
         _load().orc_flags(ctypes.byref(self._p), _dp(bmax), bmax.size,
                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)))
         return out.reshape(self.nblocks[::-1])
+
+    def levels(self, bmax, a, b, lmin, lmax, buffer=0):
+        """Refinement level per block from block maxima (Sec. 3.4), dilated by
+        `buffer` blocks (the buffer layer of Sec. 5.2)."""
+        bmax = np.ascontiguousarray(np.asarray(bmax, dtype=np.float64).ravel())
+        out = np.empty(bmax.size, dtype=np.int8)
+        assert _load().orc_levels(ctypes.byref(self._p), _dp(bmax), float(a), float(b), int(lmin),
+                                  int(lmax), int(buffer),
+                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))) == 0
+        return out.reshape(self.nblocks[::-1])
+
+    def sensor_history(self, S_abi, k0, n, every, start):
+        """Runs n steps from S_{k0}; returns (S, mean cell sensor over the
+        sensor steps k > start, number of samples): the time average of the
+        sensor that Sec. 5.1 builds its mesh from."""
+        S = S_abi
+        acc, cnt = None, 0
+        for k in range(k0 + 1, k0 + n + 1):
+            f = self.stream(S)
+            if every > 0 and k % every == 0 and k > start:
+                s = self.sensor(f)
+                acc = s if acc is None else acc + s
+                cnt += 1
+            S = self.collide(f)
+        return S, (acc / cnt if cnt else None), cnt
 
     def macros(self, f_abi, post_collision=True):
         """(rho (nz,ny,nx), u (3,nz,ny,nx)); u of the stored post-collision

@@ -429,3 +429,52 @@ int orc_conservation(const orc_params *p, const double *S, double *out)
     for (int a = 0; a < 4; ++a) out[a] = (double)acc[a];
     return 0;
 }
+
+/* ---------------------------------------------------------------------------
+ * Refinement level map (Sec. 3.4): phi = log2 K and
+ *   l = l_min if [a phi] < l_min, l_max if [a phi] > l_max, [a phi] otherwise,
+ * with [x] the integral part.  Reading taken here: an offset b is added
+ * (l from [a phi + b]) because with a alone the sensor values met in practice
+ * (K ~ 1e-3, phi ~ -10) cannot be mapped onto levels >= 0; "integral part" is
+ * read as floor.  A non-finite K gives l_max (refine where the sensor is
+ * broken); K = 0 gives l_min.  Then the buffer layer of Sec. 5.2: every block
+ * takes the maximum level found within `buffer` blocks of it (Chebyshev
+ * distance), so refinement spreads one layer (or more) around tagged blocks.
+ * ------------------------------------------------------------------------- */
+int orc_levels(const orc_params *p, const double *bmax, double a, double b, int lmin, int lmax,
+               int buffer, int8_t *levels)
+{
+    int nb[3];
+    for (int k = 0; k < 3; ++k) nb[k] = (p->n[k] + p->block[k] - 1) / p->block[k];
+    const int64_t NB = (int64_t)nb[0] * nb[1] * nb[2];
+    int8_t *raw = (int8_t *)malloc((size_t)NB);
+    if (!raw) return -1;
+    for (int64_t i = 0; i < NB; ++i) {
+        double K = bmax[i];
+        int l;
+        if (!isfinite(K)) l = lmax;
+        else if (K <= 0.0) l = lmin;
+        else {
+            double x = floor(a * log2(K) + b);
+            l = (x < lmin) ? lmin : (x > lmax) ? lmax : (int)x;
+        }
+        raw[i] = (int8_t)l;
+    }
+    for (int z = 0; z < nb[2]; ++z)
+        for (int y = 0; y < nb[1]; ++y)
+            for (int x = 0; x < nb[0]; ++x) {
+                int best = -128;
+                for (int dz = -buffer; dz <= buffer; ++dz)
+                    for (int dy = -buffer; dy <= buffer; ++dy)
+                        for (int dx = -buffer; dx <= buffer; ++dx) {
+                            int xx = x + dx, yy = y + dy, zz = z + dz;
+                            if (xx < 0 || yy < 0 || zz < 0 || xx >= nb[0] || yy >= nb[1] || zz >= nb[2])
+                                continue;
+                            int v = raw[((int64_t)zz * nb[1] + yy) * nb[0] + xx];
+                            if (v > best) best = v;
+                        }
+                levels[((int64_t)z * nb[1] + y) * nb[0] + x] = (int8_t)best;
+            }
+    free(raw);
+    return 0;
+}

@@ -80,6 +80,11 @@ def _load_library():
         "lbm_get_scheme": [H, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                            ctypes.POINTER(ctypes.c_int32)],
         "lbm_set_step": [H, ctypes.c_int64],
+        "lbm_sensor_levels": [H, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                              ctypes.c_int32, ctypes.POINTER(ctypes.c_int8)],
+        "lbm_sensor_average_begin": [H],
+        "lbm_sensor_average": [H, dp, ctypes.POINTER(ctypes.c_int64)],
+        "lbm_sensor_average_end": [H],
         "lbm_conservation": [H, dp],
         "lbm_tau_from_reynolds": [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp],
     }
@@ -193,6 +198,28 @@ def lbm_get_scheme(h):
     a, b, c = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
     st = _lib.lbm_get_scheme(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
     return st, a.value, b.value, c.value
+
+
+def lbm_sensor_levels(h, nblocks: int, a: float, b: float, lmin: int, lmax: int, buffer: int, levels):
+    if not (isinstance(levels, np.ndarray) and levels.dtype == np.int8 and levels.flags.c_contiguous
+            and levels.size == nblocks):
+        raise TypeError("levels must be a C-contiguous int8 array of nblocks values")
+    return _lib.lbm_sensor_levels(h, float(a), float(b), int(lmin), int(lmax), int(buffer),
+                                  levels.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)))
+
+
+def lbm_sensor_average_begin(h):
+    return _lib.lbm_sensor_average_begin(h)
+
+
+def lbm_sensor_average(h, nblocks: int, block_max=None):
+    n = ctypes.c_int64(0)
+    st = _lib.lbm_sensor_average(h, _dptr(block_max, nblocks), ctypes.byref(n))
+    return st, n.value
+
+
+def lbm_sensor_average_end(h):
+    return _lib.lbm_sensor_average_end(h)
 
 
 def lbm_set_step(h, step: int):

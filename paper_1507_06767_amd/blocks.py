@@ -62,6 +62,25 @@ class Blocks:
         shp = (self.nb[2], self.nb[1], self.nb[0])
         return bm.reshape(shp), fl.reshape(shp), step, st == abi.LBM_ENONFINITE
 
+    def levels(self, a, b, lmin, lmax, buffer=0):
+        """Refinement levels [nbz,nby,nbx] from the latest sensor step."""
+        lev = np.empty(self.nblocks, dtype=np.int8)
+        _check(abi.lbm_sensor_levels(self.h, self.nblocks, a, b, lmin, lmax, buffer, lev))
+        return lev.reshape(self.nb[2], self.nb[1], self.nb[0])
+
+    def average_begin(self):
+        _check(abi.lbm_sensor_average_begin(self.h))
+
+    def average(self):
+        """(per-block max of the time-averaged cell sensor, samples)."""
+        bm = np.empty(self.nblocks)
+        st, n = abi.lbm_sensor_average(self.h, self.nblocks, bm)
+        _check(st)
+        return bm.reshape(self.nb[2], self.nb[1], self.nb[0]), n
+
+    def average_end(self):
+        _check(abi.lbm_sensor_average_end(self.h))
+
     def macros(self):
         rho = np.empty(self.cells)
         u = np.empty(3 * self.cells)

@@ -123,6 +123,61 @@ __global__ void macros_kernel(Planes<T> p, double *rho_out, double *u_out, doubl
     }
 }
 
+// Refinement level of every block from its sensor maximum (Sec. 3.4):
+// l = clamp(floor(a log2 M + b), lmin, lmax); non-finite M -> lmax, M <= 0 -> lmin.
+template <typename C>
+__global__ void levels_kernel(const C *bmax, int8_t *lev, int nblocks, double a, double b, int lmin,
+                              int lmax) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nblocks) return;
+    const double K = static_cast<double>(bmax[i]);
+    int l;
+    if (!(K == K) || K == HUGE_VAL) l = lmax;
+    else if (K <= 0.0) l = lmin;
+    else {
+        const double x = floor(a * log2(K) + b);
+        l = (x < lmin) ? lmin : (x > lmax) ? lmax : (int)x;
+    }
+    lev[i] = (int8_t)l;
+}
+
+// Buffer layer (Sec. 5.2): every block takes the largest level within `r`
+// blocks of it (Chebyshev distance).
+__global__ void dilate_kernel(const int8_t *in, int8_t *out, int nbx, int nby, int nbz, int r) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nbx * nby * nbz) return;
+    const int x = i % nbx, y = (i / nbx) % nby, z = i / (nbx * nby);
+    int best = -128;
+    for (int dz = -r; dz <= r; ++dz)
+        for (int dy = -r; dy <= r; ++dy)
+            for (int dx = -r; dx <= r; ++dx) {
+                const int xx = x + dx, yy = y + dy, zz = z + dz;
+                if (xx < 0 || yy < 0 || zz < 0 || xx >= nbx || yy >= nby || zz >= nbz) continue;
+                const int v = in[(zz * nby + yy) * nbx + xx];
+                best = v > best ? v : best;
+            }
+    out[i] = (int8_t)best;
+}
+
+// Per block: the largest time-averaged cell sensor, sum / samples, NaN-propagating.
+template <typename C>
+__global__ void average_block_max_kernel(const C *sum, double *out, int nx, int ny, int nz, int bx, int by,
+                                         int bz, int nbx, int nby, int nbz, double inv_samples) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nbx * nby * nbz) return;
+    const int x0 = (i % nbx) * bx, y0 = ((i / nbx) % nby) * by, z0 = (i / (nbx * nby)) * bz;
+    double m = 0.0;
+    bool nan = false;
+    for (int z = z0; z < min(z0 + bz, nz); ++z)
+        for (int y = y0; y < min(y0 + by, ny); ++y)
+            for (int x = x0; x < min(x0 + bx, nx); ++x) {
+                const double v = static_cast<double>(sum[((int64_t)z * ny + y) * nx + x]) * inv_samples;
+                if (!(v == v)) nan = true;
+                else if (v > m) m = v;
+            }
+    out[i] = nan ? __longlong_as_double(0x7ff8000000000000ll) : m;
+}
+
 constexpr int kReduceThreads = 256;
 
 // Fixed-order tree over the workgroup's 256 slots of 4 doubles.

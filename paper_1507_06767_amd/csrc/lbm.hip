@@ -85,6 +85,9 @@ struct Layout {
     size_t bytes[LBM_NBUF];
     size_t acc_off;       // per-block accumulator words inside BLOCK_MAX
     size_t staging_off, partial_off, out_off;
+    size_t avg_off;       // per-cell running sensor sums (time average)
+    size_t lev_off;       // two per-block int8 level arrays
+    size_t avgmax_off;    // per-block float64 maxima of the averaged sensor
 };
 
 bool is_fin(double v) { return std::isfinite(v); }
@@ -153,7 +156,10 @@ lbm_status check_desc(const lbm_desc *d, Layout *L) {
     L->staging_off = 0;
     L->partial_off = round_up((size_t)cells * 8 * 4, kAlign);
     L->out_off = L->partial_off + round_up((size_t)kMaxPartials * 4 * 8, kAlign);
-    L->bytes[LBM_BUF_SCRATCH] = L->out_off + kAlign;
+    L->avg_off = L->out_off + kAlign;
+    L->lev_off = L->avg_off + round_up((size_t)cells * L->cbytes, kAlign);
+    L->avgmax_off = L->lev_off + round_up((size_t)L->nblocks * 2, kAlign);
+    L->bytes[LBM_BUF_SCRATCH] = L->avgmax_off + round_up((size_t)L->nblocks * 8, kAlign);
     return LBM_OK;
 }
 
@@ -197,6 +203,9 @@ struct lbm_blocks {
     int64_t step;
     int64_t last_sensor_step; // -1: none since the state was set
     bool has_force;
+    bool averaging;           // sensor steps add the cell sensor to running sums
+    bool avg_started;         // the sums were cleared by lbm_sensor_average_begin
+    int64_t avg_samples;      // sensor steps summed since averaging began
     uint32_t wall_mask;
     std::vector<int8_t> flags_host;
     std::vector<unsigned char> bmax_host;
@@ -278,6 +287,8 @@ StepArgs<C> step_args(lbm_blocks *h, const void *src, void *dst, bool zmarch, in
     a.theta_r = d.theta_refine;
     a.theta_c = d.theta_coarsen;
     a.step = (uint32_t)(h->step + 1);
+    a.avg = h->averaging ? reinterpret_cast<C *>(static_cast<char *>(d.buf[LBM_BUF_SCRATCH]) + h->L.avg_off)
+                         : nullptr;
     a.block_max = static_cast<C *>(d.buf[LBM_BUF_BLOCK_MAX]);
     a.flags = static_cast<int8_t *>(d.buf[LBM_BUF_FLAGS]);
     a.acc = reinterpret_cast<unsigned long long *>(static_cast<char *>(d.buf[LBM_BUF_BLOCK_MAX]) +
@@ -453,6 +464,9 @@ lbm_status lbm_create_blocks(const lbm_desc *d, const double *f0_host, lbm_block
     h->cur = 0;
     h->step = 0;
     h->last_sensor_step = -1;
+    h->averaging = false;
+    h->avg_started = false;
+    h->avg_samples = 0;
     h->has_force = d->force[0] != 0.0 || d->force[1] != 0.0 || d->force[2] != 0.0;
     h->wall_mask = 0;
     for (int f = 0; f < 6; ++f)
@@ -498,6 +512,7 @@ lbm_status lbm_step_n(lbm_blocks *h, int64_t n, int32_t sensor_every) {
         else h->cur ^= 1;
         h->step = step;
         if (sens) h->last_sensor_step = step;
+        if (sens && h->averaging) ++h->avg_samples;
     }
     HIP_TRY(hipGetLastError());
     return LBM_OK;
@@ -524,6 +539,79 @@ lbm_status lbm_sensor_flags(lbm_blocks *h, double *block_max_host, int8_t *flags
     }
     if (step_index) *step_index = h->last_sensor_step;
     if (nonfinite) return fail(LBM_ENONFINITE, "a sensor block holds a non-finite value");
+    return LBM_OK;
+}
+
+lbm_status lbm_sensor_levels(lbm_blocks *h, double a, double b, int32_t lmin, int32_t lmax,
+                             int32_t buffer, int8_t *levels_host) {
+    lbm_status st = check_handle(h);
+    if (st != LBM_OK) return st;
+    if (!levels_host) return fail(LBM_EINVAL, "levels_host is NULL");
+    if (!is_fin(a) || !is_fin(b) || lmin > lmax || lmin < -127 || lmax > 127 || buffer < 0 || buffer > 8)
+        return fail(LBM_EINVAL, "need finite a, b, -127 <= lmin <= lmax <= 127 and 0 <= buffer <= 8");
+    if (h->last_sensor_step < 0) return fail(LBM_ESTATE, "no sensor step has run since the state was set");
+    const int nb = (int)h->L.nblocks;
+    int8_t *lev = reinterpret_cast<int8_t *>(static_cast<char *>(h->d.buf[LBM_BUF_SCRATCH]) + h->L.lev_off);
+    const unsigned g = grid_for(nb);
+    if (h->L.cbytes == 8)
+        hipLaunchKernelGGL(levels_kernel<double>, dim3(g), dim3(kAuxThreads), 0, h->stream,
+                           static_cast<const double *>(h->d.buf[LBM_BUF_BLOCK_MAX]), lev, nb, a, b, lmin, lmax);
+    else
+        hipLaunchKernelGGL(levels_kernel<float>, dim3(g), dim3(kAuxThreads), 0, h->stream,
+                           static_cast<const float *>(h->d.buf[LBM_BUF_BLOCK_MAX]), lev, nb, a, b, lmin, lmax);
+    hipLaunchKernelGGL(dilate_kernel, dim3(g), dim3(kAuxThreads), 0, h->stream, lev, lev + nb, h->L.nb[0],
+                       h->L.nb[1], h->L.nb[2], buffer);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(levels_host, lev + nb, nb, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_sensor_average_begin(lbm_blocks *h) {
+    lbm_status st = check_handle(h);
+    if (st != LBM_OK) return st;
+    const size_t bytes = (size_t)h->L.cells * h->L.cbytes;
+    char *p = static_cast<char *>(h->d.buf[LBM_BUF_SCRATCH]) + h->L.avg_off;
+    // cleared with a kernel (no memset node if the caller captures the stream)
+    hipLaunchKernelGGL(zero_words_kernel, dim3(grid_for((int64_t)(bytes / 8))), dim3(kAuxThreads), 0,
+                       h->stream, reinterpret_cast<unsigned long long *>(p), (int)(bytes / 8));
+    HIP_TRY(hipGetLastError());
+    h->averaging = true;
+    h->avg_started = true;
+    h->avg_samples = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_sensor_average(lbm_blocks *h, double *block_max_host, int64_t *samples) {
+    lbm_status st = check_handle(h);
+    if (st != LBM_OK) return st;
+    if (!h->avg_started) return fail(LBM_ESTATE, "averaging has not been started");
+    if (samples) *samples = h->avg_samples;
+    if (!block_max_host) return LBM_OK;
+    if (h->avg_samples == 0) return fail(LBM_ESTATE, "no sensor step since averaging began");
+    const int nb = (int)h->L.nblocks;
+    const int bz = (h->L.dim == 3) ? kBlockEdge : 1;
+    const char *scr = static_cast<const char *>(h->d.buf[LBM_BUF_SCRATCH]);
+    double *out = reinterpret_cast<double *>(static_cast<char *>(h->d.buf[LBM_BUF_SCRATCH]) + h->L.avgmax_off);
+    const double inv = 1.0 / (double)h->avg_samples;
+    const lbm_desc &d = h->d;
+    if (h->L.cbytes == 8)
+        hipLaunchKernelGGL(average_block_max_kernel<double>, dim3(grid_for(nb)), dim3(kAuxThreads), 0, h->stream,
+                           reinterpret_cast<const double *>(scr + h->L.avg_off), out, d.extent[0], d.extent[1],
+                           d.extent[2], kBlockEdge, kBlockEdge, bz, h->L.nb[0], h->L.nb[1], h->L.nb[2], inv);
+    else
+        hipLaunchKernelGGL(average_block_max_kernel<float>, dim3(grid_for(nb)), dim3(kAuxThreads), 0, h->stream,
+                           reinterpret_cast<const float *>(scr + h->L.avg_off), out, d.extent[0], d.extent[1],
+                           d.extent[2], kBlockEdge, kBlockEdge, bz, h->L.nb[0], h->L.nb[1], h->L.nb[2], inv);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(block_max_host, out, nb * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_sensor_average_end(lbm_blocks *h) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    h->averaging = false;
     return LBM_OK;
 }
 

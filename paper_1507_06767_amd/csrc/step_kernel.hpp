@@ -94,6 +94,7 @@ struct StepArgs {
     C F[3];                 // body-force density
     double theta_r, theta_c;
     uint32_t step;          // index of the step this launch computes (stochastic rounding key)
+    C *avg;                 // per-cell running sums of the sensor (time average); nullptr: off
     C *block_max;           // [nbz][nby][nbx]
     int8_t *flags;          // [nbz][nby][nbx]
     unsigned long long *acc;  // per block (count << 32 | max bits), zero between sensor steps
@@ -449,6 +450,13 @@ __device__ __forceinline__ C finish(C M) {
     else return M;
 }
 
+// Time average of the cell sensor (the averaged sensor of Sec. 5.1): adds the
+// cell's sensor value to its running sum when averaging is switched on.
+template <int SKIND, typename C>
+__device__ __forceinline__ void accumulate(const StepArgs<C> &a, uint32_t cell, C s) {
+    if (a.avg) a.avg[cell] += finish<SKIND>(s);
+}
+
 template <int Q, typename T, typename C, bool SHIFTED, bool SENSOR, int SKIND, bool FORCE, int BX, int SCHEME>
 __global__ __launch_bounds__(BX *kTileY) void step_cells(const StepArgs<C> a) {
     constexpr int D = Lattice<Q>::D;
@@ -469,6 +477,7 @@ __global__ __launch_bounds__(BX *kTileY) void step_cells(const StepArgs<C> a) {
         C d[Q];
         load_cell<Q, T, C, SHIFTED, SCHEME>(a, g, d);
         s = collide_store<Q, T, C, SHIFTED, SENSOR, SKIND, FORCE, SCHEME>(a, g, d);
+        if constexpr (SENSOR) accumulate<SKIND>(a, g.cell, s);
     }
     if constexpr (SENSOR) {
         const C M = tile_block_max<BX>(s);
@@ -522,7 +531,10 @@ __global__ __launch_bounds__(BX *kTileY) void step_zmarch(const StepArgs<C> a) {
             C d[Q];
             load_cell<Q, T, C, SHIFTED, kPingPong>(a, g, d);
             const C s = collide_store<Q, T, C, SHIFTED, SENSOR, SKIND, FORCE, kPingPong>(a, g, d);
-            if constexpr (SENSOR) m = nan_max(m, s);
+            if constexpr (SENSOR) {
+                m = nan_max(m, s);
+                accumulate<SKIND>(a, g.cell, s);
+            }
         }
     }
     if constexpr (SENSOR) {

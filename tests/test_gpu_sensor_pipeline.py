@@ -1,0 +1,125 @@
+"""The paper's refinement pipeline on top of the block maxima, on the GPU
+against the FP64 oracle: the level map of Sec. 3.4, the buffer layer of
+Sec. 5.2 and the time-averaged sensor of Sec. 5.1.
+
+Levels are integers decided by floating point (floor of a log2 M + b): GPU
+and oracle must agree exactly except on blocks whose oracle value of
+a log2 M + b lies within the sensor tolerance of an integer, and, after the
+buffer layer, blocks next to such a block; these are counted and printed.
+"""
+import numpy as np
+import pytest
+
+import lbm_inputs
+from lbm_inputs import PERIODIC, WALL
+
+pytestmark = pytest.mark.gpu
+
+EPS_S = {0: 1e-11, 2: 2e-5}
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1507_06767_amd as lbm
+    return lbm
+
+
+@pytest.fixture(params=["inplace", "pingpong"])
+def scheme(request, monkeypatch):
+    monkeypatch.setenv("LBM_STREAMING", request.param)
+    return request.param
+
+
+def _wall(lid):
+    w = [[0.0] * 3 for _ in range(6)]
+    w[3][0] = lid
+    return w
+
+
+_CASES = [
+    ("cav3d", 19, (40, 24, 20), (WALL,) * 6),
+    ("cav2d", 9, (72, 40, 1), (WALL, WALL, WALL, WALL, PERIODIC, PERIODIC)),
+]
+
+
+def _near_integer(bm_ref, a, b, eps):
+    """Blocks whose a log2 M + b is within the sensor tolerance of an integer."""
+    with np.errstate(divide="ignore"):
+        x = a * np.log2(np.maximum(bm_ref, 1e-300)) + b
+    dx = abs(a) * eps / np.log(2.0) + 1e-12
+    return np.abs(x - np.round(x)) <= dx
+
+
+def _dilate(mask, r):
+    out = mask.copy()
+    nz, ny, nx = mask.shape
+    for z, y, x in zip(*np.nonzero(mask)):
+        out[max(0, z - r):z + r + 1, max(0, y - r):y + r + 1, max(0, x - r):x + r + 1] = True
+    return out
+
+
+@pytest.mark.parametrize("storage", [0, 2], ids=["f64", "f32s"])
+@pytest.mark.parametrize("case", _CASES, ids=[c[0] for c in _CASES])
+def test_levels_and_buffer_layer(lbm, orc, case, storage, scheme):
+    name, q, n, bc = case
+    print(f"\n[case] levels {name} storage={storage} {scheme}", flush=True)
+    wall_u = _wall(0.08)
+    desc = lbm.make_desc(q, n, bc, 0.6, storage=storage, wall_u=wall_u)
+    G = orc.Grid(q=q, n=n, bc=bc, wall_u=wall_u, tau=0.6)
+    blk = lbm.Blocks(desc)
+    blk.step_n(50, 25)
+    _, hist = G.run(G.equilibrium_state(), 0, 50, 50)
+    bm_ref = hist[0][1]
+    a, b, lmin, lmax = 1.0, 12.0, 0, 4
+    excused_total = 0
+    for buffer in (0, 1, 2):
+        lev = blk.levels(a, b, lmin, lmax, buffer)
+        ref = G.levels(bm_ref, a, b, lmin, lmax, buffer)
+        near = _dilate(_near_integer(bm_ref, a, b, EPS_S[storage]), buffer)
+        bad = (lev != ref) & ~near
+        assert not bad.any(), f"buffer {buffer}: {bad.sum()} level mismatches"
+        excused_total += int(((lev != ref) & near).sum())
+        if buffer == 0:
+            lev0 = lev
+        else:
+            # the buffer layer is the neighbourhood maximum of the raw levels
+            nz, ny, nx = lev0.shape
+            for z in range(nz):
+                for y in range(ny):
+                    for x in range(nx):
+                        nbh = lev0[max(0, z - buffer):z + buffer + 1, max(0, y - buffer):y + buffer + 1,
+                                   max(0, x - buffer):x + buffer + 1]
+                        assert lev[z, y, x] == nbh.max()
+    assert len(np.unique(lev0)) >= 2, "the workload should produce several levels"
+    print(f"levels {name}: distinct {np.unique(lev0).tolist()}, excused {excused_total}")
+    blk.close()
+
+
+@pytest.mark.parametrize("storage", [0, 2], ids=["f64", "f32s"])
+@pytest.mark.parametrize("kind", [0, 1], ids=["l2", "kkn"])
+def test_time_averaged_sensor(lbm, orc, storage, kind, scheme):
+    """Averaging switched on after step 10; 15 sensor steps (every 2nd step
+    up to step 40); per-block maxima of the time-averaged cell sensor."""
+    n = (24, 20, 17)
+    wall_u = _wall(0.08)
+    print(f"\n[case] average storage={storage} kind={kind} {scheme}", flush=True)
+    desc = lbm.make_desc(19, n, (WALL,) * 6, 0.6, storage=storage, sensor_kind=kind, wall_u=wall_u)
+    G = orc.Grid(q=19, n=n, bc=(WALL,) * 6, wall_u=wall_u, tau=0.6, sensor_kind=kind)
+    blk = lbm.Blocks(desc)
+    blk.step_n(10, 2)
+    blk.average_begin()
+    blk.step_n(30, 2)
+    bm, samples = blk.average()
+    S10, _ = G.run(G.equilibrium_state(), 0, 10, 0)
+    _, mean, cnt = G.sensor_history(S10, 10, 30, 2, start=10)
+    assert samples == cnt == 15
+    ref = G.block_max(mean)
+    err = np.abs(bm - ref) / np.maximum(ref, 1e-3)
+    print(f"average: max rel err {err.max():.2e}")
+    assert err.max() <= (1e-11 if storage == 0 else 2e-5)
+    blk.average_end()
+    blk.step_n(4, 2)
+    assert blk.average()[1] == 15          # no longer accumulating
+    blk.close()

@@ -425,3 +425,59 @@ def test_tau_from_reynolds(orc):
     Re = 1000 has tau = 0.5192."""
     assert abs(orc.tau_from_reynolds(0.1, 64, 100) - 0.692) < 1e-15
     assert abs(orc.tau_from_reynolds(0.05, 128, 1000) - 0.5192) < 1e-15
+
+
+# ---------------------------------------------------------------- level map --
+def test_level_map_closed_form(orc):
+    """Sec. 3.4: l = clamp([a log2 K + b], l_min, l_max) with [.] = floor;
+    non-finite K refines to l_max, K = 0 coarsens to l_min."""
+    G = orc.Grid(q=9, n=(48, 8, 1))
+    K = np.array([[[2.0 ** -12, 2.0 ** -10, 2.0 ** -9.5, 2.0 ** -8, np.nan, 0.0]]])
+    lev = G.levels(K, a=1.0, b=10.0, lmin=0, lmax=1)
+    assert lev.tolist() == [[[0, 0, 0, 1, 1, 0]]]
+    lev = G.levels(K, a=2.0, b=24.0, lmin=-1, lmax=6)
+    # 2*(-12)+24=0, -20+24=4, -19+24=5, -16+24=8->6, nan->6, 0->-1
+    assert lev.tolist() == [[[0, 4, 5, 6, 6, -1]]]
+
+
+def test_level_map_buffer_layer(orc):
+    """Sec. 5.2: one layer of buffer blocks around tagged blocks: each block
+    takes the largest level within Chebyshev distance 1 (26 neighbours in 3D),
+    and distance 0 changes nothing."""
+    G = orc.Grid(q=19, n=(40, 32, 24))
+    nb = G.nblocks
+    K = np.full((nb[2], nb[1], nb[0]), 1e-5)
+    K[1, 2, 3] = 1e-2
+    lev0 = G.levels(K, 1.0, 10.0, 0, 3, buffer=0)
+    assert lev0.sum() == lev0[1, 2, 3] and lev0[1, 2, 3] == 3
+    lev1 = G.levels(K, 1.0, 10.0, 0, 3, buffer=1)
+    expected = np.zeros_like(lev0)
+    expected[0:3, 1:4, 2:5] = 3
+    assert (lev1 == expected).all()
+    lev2 = G.levels(K, 1.0, 10.0, 0, 3, buffer=2)
+    expected2 = np.zeros_like(lev0)
+    expected2[0:3, 0:4, 1:5] = 3          # the grid has 5 x 4 x 3 blocks
+    assert (lev2 == expected2).all()
+
+
+def test_time_averaged_sensor_matches_step_by_step(orc):
+    """Sec. 5.1 averages the sensor over time before building the mesh: the
+    running mean over sensor steps equals the mean of the per-step sensors
+    recomputed independently from stored states."""
+    n = (12, 10, 1)
+    bc = (WALL, WALL, WALL, WALL, PERIODIC, PERIODIC)
+    wall_u = [[0.0] * 3 for _ in range(6)]
+    wall_u[3][0] = 0.1
+    G = orc.Grid(q=9, n=n, bc=bc, wall_u=wall_u, tau=0.7)
+    S0 = G.equilibrium_state()
+    S, mean, cnt = G.sensor_history(S0, 0, 30, 2, start=10)
+    assert cnt == 10
+    ref = np.zeros(G.shape)
+    Sk = S0
+    for k in range(1, 31):
+        Sn, _ = G.run(Sk, k - 1, 1, 0)
+        if k % 2 == 0 and k > 10:
+            ref += G.sensor(G.stream(Sk))
+        Sk = Sn
+    assert np.abs(mean - ref / 10).max() < 1e-15
+    assert np.abs(S - Sk).max() == 0.0
