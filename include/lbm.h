@@ -186,6 +186,13 @@ lbm_status lbm_sensor_average_end(lbm_blocks *h);
  * be NULL. */
 lbm_status lbm_get_macros(lbm_blocks *h, double *rho_host, double *u_host);
 
+/* Synchronises the stream and returns per-block means of the fields of
+ * lbm_get_macros: means_host[nbz][nby][nbx][4] = (rho - rho0, u_x, u_y, u_z)
+ * averaged over the cells of each 8^d block (edge blocks average the cells
+ * they hold), float64.  These are the inputs of the learned flag predictor
+ * (include/lbm_cnn.h); the blocks are those of the sensor (Sec. 3.4). */
+lbm_status lbm_block_means(lbm_blocks *h, double *means_host);
+
 /* Stored populations S_k as float64 [q][cells] (checkpointing, tests). */
 lbm_status lbm_get_populations(lbm_blocks *h, double *f_host);
 

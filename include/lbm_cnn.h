@@ -1,0 +1,78 @@
+/*
+ * lbm_cnn.h -- kernels of the learned refinement-flag predictor: a small 3D
+ * convolutional network over per-block averaged (rho, u) that predicts the
+ * kinetic sensor's block maximum some steps ahead, so that regridding can
+ * refine ahead of moving features.  The network is not part of the paper;
+ * the sensor it predicts is (Sec. 3.2, block maxima of Sec. 3.4).
+ *
+ * Layouts and conventions:
+ *   - Activations are float32, channels last: x[n][z][y][x][c], with the
+ *     channel stride C4 = the channel count rounded up to a multiple of 4
+ *     (padding channels hold zeros).  Grids are D x H x W voxels.
+ *   - A 3x3x3 convolution with zero padding ("same" size) maps Ci to Co
+ *     channels.  Float32 master weights are w[co][tap][ci], tap = (kz*3 +
+ *     ky)*3 + kx; the kernels read them packed to bfloat16 as a matrix
+ *     [Co16][K16] (K = 27 * Ci4, both sides padded to multiples of 16) made
+ *     by lbm_cnn_pack_weights.
+ *   - Products run on the matrix cores (bfloat16 inputs, float32
+ *     accumulation: v_mfma_f32_16x16x16_bf16); everything else is float32.
+ *   - All device pointers are caller-owned; every call is asynchronous on
+ *     `stream` (hipStream_t, NULL: null stream) and returns 0 on success or
+ *     a negative code (-1: bad argument, -3: HIP launch error).
+ */
+#ifndef LBM_CNN_H
+#define LBM_CNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Number of uint16 (bfloat16) values of a packed weight matrix. */
+int64_t lbm_cnn_packed_size(int32_t co, int32_t ci);
+
+/* Packs w[co][27][ci] (float32) into bfloat16 [Co16][K16].  flip != 0 packs
+ * instead the weights of the data-gradient convolution: out channel ci, in
+ * channel co, tap mirrored (26 - tap), i.e. the matrix [Ci16][27 * Co4]. */
+int32_t lbm_cnn_pack_weights(const float *w, int32_t co, int32_t ci, int32_t flip, uint16_t *packed,
+                             void *stream);
+
+/* y[n][v][co] = act(sum_{tap, ci} w[co][tap][ci] x[n][v + tap - 13][ci] + bias[co]),
+ * act = relu if relu != 0, identity otherwise; bias may be NULL.  Writes all
+ * Co4 channels of y (padding channels get 0 + bias 0).  packed comes from
+ * lbm_cnn_pack_weights(co, ci). */
+int32_t lbm_cnn_conv3d_forward(const float *x, int32_t n, int32_t d, int32_t h, int32_t wd, int32_t ci,
+                               const uint16_t *packed, int32_t co, const float *bias, int32_t relu,
+                               float *y, void *stream);
+
+/* Bytes of the float32 workspace lbm_cnn_conv3d_wgrad needs. */
+int64_t lbm_cnn_wgrad_workspace(int32_t n, int32_t d, int32_t h, int32_t wd, int32_t ci, int32_t co);
+
+/* Weight and bias gradients of the convolution:
+ *   gw[co][tap][ci] = sum_{n, v} gz[n][v][co] x[n][v + tap - 13][ci],
+ *   gb[co] = sum_{n, v} gz[n][v][co]  (gb may be NULL).
+ * Deterministic: per-workgroup partial sums in `work`, folded in a fixed
+ * order. */
+int32_t lbm_cnn_conv3d_wgrad(const float *x, const float *gz, int32_t n, int32_t d, int32_t h, int32_t wd,
+                             int32_t ci, int32_t co, float *work, float *gw, float *gb, void *stream);
+
+/* g[i] = (a[i] > 0) ? g[i] : 0 for i < count (ReLU backward, in place). */
+int32_t lbm_cnn_relu_backward(const float *a, float *g, int64_t count, void *stream);
+
+/* Mean squared error of channel 0 of y (channel stride ystride) against
+ * target[v], v < count: loss[0] = mean (y - t)^2 (float32, written on the
+ * device), g[v][0] = 2 (y - t) / count and g's other channels 0. */
+int32_t lbm_cnn_mse(const float *y, int32_t ystride, const float *target, int64_t count, float *g,
+                    float *loss, void *stream);
+
+/* One Adam update (Kingma & Ba) of count parameters at step t >= 1. */
+int32_t lbm_cnn_adam(float *w, const float *g, float *m, float *v, int64_t count, float lr, float beta1,
+                     float beta2, float eps, int32_t t, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_CNN_H */

@@ -138,3 +138,17 @@ def channel3d(n=256, g=1e-6, tau=0.8, steps=10000, storage="f32", nx=None, nz=No
     return Workload(name=f"channel_d3q19_{nx}x{n}x{nz}_{storage}", q=19, n=(nx, n, nz),
                     bc=(PERIODIC, PERIODIC, WALL, WALL, PERIODIC, PERIODIC), tau=tau,
                     force=(g, 0.0, 0.0), steps=steps, storage=storage)
+
+
+def predictor_cavities(count: int, seed: int, n: int = 128, re_range=(1000.0, 5000.0), lid_range=(0.03, 0.08),
+                       storage: str = "f32s"):
+    """``count`` lid-driven 3D cavities for training and testing the flag
+    predictor: Reynolds number and lid speed of cavity k drawn uniformly from
+    the ranges (values 2k and 2k+1 of stream ``seed``)."""
+    r = uniform(seed, 2 * count)
+    out = []
+    for k in range(count):
+        re = re_range[0] + (re_range[1] - re_range[0]) * r[2 * k]
+        lid = lid_range[0] + (lid_range[1] - lid_range[0]) * r[2 * k + 1]
+        out.append(cavity3d(n=n, lid=lid, re=re, sensor_every=64, storage=storage))
+    return out

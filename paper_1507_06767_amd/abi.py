@@ -63,6 +63,12 @@ def _load_library():
         raise ImportError(
             f"{_LIB_PATH} is missing: build the HIP library first "
             "(python -c 'import __graft_entry__ as g; g.build()')")
+    # torch loads its bundled HIP runtime by the file name libamdhip64.so; the
+    # library asks for the soname libamdhip64.so.7, which that copy carries.
+    # Loading torch first makes both use one runtime: loaded the other way
+    # round, two runtimes would coexist and neither would know the other's
+    # device pointers.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(_LIB_PATH)
     H = ctypes.c_void_p
     D = ctypes.POINTER(lbm_desc)
@@ -73,6 +79,7 @@ def _load_library():
         "lbm_step_n": [H, ctypes.c_int64, ctypes.c_int32],
         "lbm_sensor_flags": [H, dp, ctypes.POINTER(ctypes.c_int8), ctypes.POINTER(ctypes.c_int64)],
         "lbm_get_macros": [H, dp, dp],
+        "lbm_block_means": [H, dp],
         "lbm_get_populations": [H, dp],
         "lbm_set_populations": [H, dp],
         "lbm_set_equilibrium": [H, dp, dp],
@@ -173,6 +180,11 @@ def lbm_sensor_flags(h, nblocks: int, block_max=None, flags=None):
 
 def lbm_get_macros(h, cells: int, rho=None, u=None):
     return _lib.lbm_get_macros(h, _dptr(rho, cells), _dptr(u, 3 * cells))
+
+
+def lbm_block_means(h, nblocks: int, means):
+    """means: float64[nblocks * 4] (rho - rho0, u_x, u_y, u_z per block)."""
+    return _lib.lbm_block_means(h, _dptr(means, 4 * nblocks))
 
 
 def lbm_get_populations(h, q: int, cells: int, f):

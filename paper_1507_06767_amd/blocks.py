@@ -87,6 +87,12 @@ class Blocks:
         _check(abi.lbm_get_macros(self.h, self.cells, rho, u))
         return rho.reshape(self.shape), u.reshape((3,) + self.shape)
 
+    def block_means(self):
+        """Per-block means of (rho - rho0, u_x, u_y, u_z), [nbz,nby,nbx,4]."""
+        m = np.empty(4 * self.nblocks)
+        _check(abi.lbm_block_means(self.h, self.nblocks, m))
+        return m.reshape(self.nb[2], self.nb[1], self.nb[0], 4)
+
     def populations(self):
         f = np.empty(self.q * self.cells)
         _check(abi.lbm_get_populations(self.h, self.q, self.cells, f))

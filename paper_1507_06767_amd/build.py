@@ -18,7 +18,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["lbm.hip", "step_f64.hip", "step_f32.hip", "step_f16.hip", "step_bf16.hip"]
+SOURCES = ["lbm.hip", "step_f64.hip", "step_f32.hip", "step_f16.hip", "step_bf16.hip", "cnn.hip"]
 OUT = os.path.join(HERE, "liblbm.so")
 
 HIPCC_FLAGS = [

@@ -1,0 +1,108 @@
+"""ctypes binding of include/lbm_cnn.h: same names, argument marshalling only.
+
+Tensors are torch tensors on the GPU; their dtype, contiguity, device and
+size are checked here against what the C function will touch, so that no
+kernel reads or writes past a buffer.  Every function returns the C status
+(0 on success) and enqueues its kernels on `stream` (torch's current stream
+when None).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import abi
+
+LBM_CNN_TAPS = 27
+
+_lib = abi._lib
+_P = ctypes.c_void_p
+_I32, _I64, _F = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+_SIG = {
+    "lbm_cnn_packed_size": ([_I32, _I32], _I64),
+    "lbm_cnn_pack_weights": ([_P, _I32, _I32, _I32, _P, _P], _I32),
+    "lbm_cnn_conv3d_forward": ([_P, _I32, _I32, _I32, _I32, _I32, _P, _I32, _P, _I32, _P, _P], _I32),
+    "lbm_cnn_wgrad_workspace": ([_I32, _I32, _I32, _I32, _I32, _I32], _I64),
+    "lbm_cnn_conv3d_wgrad": ([_P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P], _I32),
+    "lbm_cnn_relu_backward": ([_P, _P, _I64, _P], _I32),
+    "lbm_cnn_mse": ([_P, _I32, _P, _I64, _P, _P, _P], _I32),
+    "lbm_cnn_adam": ([_P, _P, _P, _P, _I64, _F, _F, _F, _F, _I32, _P], _I32),
+}
+for _name, (_args, _res) in _SIG.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = _res
+
+
+def pad4(c: int) -> int:
+    return (c + 3) // 4 * 4
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _ptr(t, dtype, numel, name, align=4):
+    if t is None:
+        return None
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous {dtype} CUDA tensor")
+    if t.numel() < numel:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {numel}")
+    if t.data_ptr() % align:
+        raise ValueError(f"{name} is not {align}-byte aligned")
+    return t.data_ptr()
+
+
+def lbm_cnn_packed_size(co: int, ci: int) -> int:
+    return int(_lib.lbm_cnn_packed_size(int(co), int(ci)))
+
+
+def lbm_cnn_pack_weights(w, co, ci, flip, packed, stream=None):
+    size = lbm_cnn_packed_size(ci, co) if flip else lbm_cnn_packed_size(co, ci)
+    return _lib.lbm_cnn_pack_weights(_ptr(w, torch.float32, co * LBM_CNN_TAPS * ci, "w"), int(co), int(ci),
+                                     int(bool(flip)), _ptr(packed, torch.int16, size, "packed", 8),
+                                     _stream(stream))
+
+
+def lbm_cnn_conv3d_forward(x, n, d, h, wd, ci, packed, co, bias, relu, y, stream=None):
+    nv = n * d * h * wd
+    return _lib.lbm_cnn_conv3d_forward(
+        _ptr(x, torch.float32, nv * pad4(ci), "x", 16), n, d, h, wd, ci,
+        _ptr(packed, torch.int16, lbm_cnn_packed_size(co, ci), "packed", 8), co,
+        _ptr(bias, torch.float32, co, "bias"), int(bool(relu)),
+        _ptr(y, torch.float32, nv * pad4(co), "y", 16), _stream(stream))
+
+
+def lbm_cnn_wgrad_workspace(n, d, h, wd, ci, co) -> int:
+    return int(_lib.lbm_cnn_wgrad_workspace(n, d, h, wd, ci, co))
+
+
+def lbm_cnn_conv3d_wgrad(x, gz, n, d, h, wd, ci, co, work, gw, gb, stream=None):
+    nv = n * d * h * wd
+    ws = lbm_cnn_wgrad_workspace(n, d, h, wd, ci, co) // 4
+    return _lib.lbm_cnn_conv3d_wgrad(
+        _ptr(x, torch.float32, nv * pad4(ci), "x"), _ptr(gz, torch.float32, nv * pad4(co), "gz"),
+        n, d, h, wd, ci, co, _ptr(work, torch.float32, ws, "work"),
+        _ptr(gw, torch.float32, co * LBM_CNN_TAPS * ci, "gw"), _ptr(gb, torch.float32, co, "gb"),
+        _stream(stream))
+
+
+def lbm_cnn_relu_backward(a, g, count, stream=None):
+    return _lib.lbm_cnn_relu_backward(_ptr(a, torch.float32, count, "a"), _ptr(g, torch.float32, count, "g"),
+                                      int(count), _stream(stream))
+
+
+def lbm_cnn_mse(y, ystride, target, count, g, loss, stream=None):
+    return _lib.lbm_cnn_mse(_ptr(y, torch.float32, count * ystride, "y"), int(ystride),
+                            _ptr(target, torch.float32, count, "target"), int(count),
+                            _ptr(g, torch.float32, count * ystride, "g"), _ptr(loss, torch.float32, 1, "loss"),
+                            _stream(stream))
+
+
+def lbm_cnn_adam(w, g, m, v, count, lr, beta1, beta2, eps, t, stream=None):
+    return _lib.lbm_cnn_adam(*(_ptr(a, torch.float32, count, nm) for a, nm in ((w, "w"), (g, "g"), (m, "m"),
+                                                                               (v, "v"))),
+                             int(count), float(lr), float(beta1), float(beta2), float(eps), int(t), _stream(stream))

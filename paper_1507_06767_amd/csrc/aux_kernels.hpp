@@ -123,6 +123,30 @@ __global__ void macros_kernel(Planes<T> p, double *rho_out, double *u_out, doubl
     }
 }
 
+// Per-block means of (rho - rho0, u_x, u_y, u_z) from per-cell fields (one
+// thread per block, cells summed in z, y, x order); edge blocks average the
+// cells they hold.  Output [block][4].
+__global__ void block_means_kernel(const double *rho, const double *u, int nx, int ny, int nz, int nbx, int nby,
+                                   int nbz, int bz, double rho0, double *out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbx * nby * nbz) return;
+    const int ib = b % nbx, jb = (b / nbx) % nby, kb = b / (nbx * nby);
+    const int64_t cells = (int64_t)nx * ny * nz;
+    const int x1 = min(nx, 8 * ib + 8), y1 = min(ny, 8 * jb + 8), z1 = min(nz, bz * kb + bz);
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int z = bz * kb; z < z1; ++z)
+        for (int y = 8 * jb; y < y1; ++y)
+            for (int x = 8 * ib; x < x1; ++x) {
+                const int64_t c = ((int64_t)z * ny + y) * nx + x;
+                s[0] += rho[c] - rho0;
+                s[1] += u[c];
+                s[2] += u[cells + c];
+                s[3] += u[2 * cells + c];
+            }
+    const double n = (double)((x1 - 8 * ib) * (y1 - 8 * jb) * (z1 - bz * kb));
+    for (int k = 0; k < 4; ++k) out[4 * (int64_t)b + k] = s[k] / n;
+}
+
 // Refinement level of every block from its sensor maximum (Sec. 3.4):
 // l = clamp(floor(a log2 M + b), lmin, lmax); non-finite M -> lmax, M <= 0 -> lmin.
 template <typename C>

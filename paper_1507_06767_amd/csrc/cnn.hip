@@ -1,0 +1,317 @@
+// cnn.hip -- kernels of the learned refinement-flag predictor (include/lbm_cnn.h).
+//
+// 3x3x3 "same" convolutions over channels-last float32 activations, as
+// implicit GEMMs on the gfx950 matrix cores: v_mfma_f32_16x16x16_bf16 takes a
+// 16x16 bfloat16 A tile and a 16x16 bfloat16 B tile spread over the 64 lanes
+// of a wave (lane i holds row i%16, reduction entries 4*(i/16)..+3 of A and
+// the transposed arrangement of B) and accumulates a 16x16 float32 tile
+// (lane i holds rows 4*(i/16)..+3 of column i%16).
+//  * forward: rows = 16 consecutive voxels, columns = 16 output channels,
+//    reduction = (tap, input channel), with the input gathered on the fly
+//    (zero outside the grid);
+//  * data gradient: the forward kernel applied to the output gradient with
+//    mirrored taps and transposed channels (packed by lbm_cnn_pack_weights);
+//  * weight gradient: rows = 16 output channels, columns = 16 (tap, input
+//    channel) pairs, reduction = voxels, per-workgroup partials folded in a
+//    fixed order.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "lbm_cnn.h"
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTaps = 27;
+constexpr int kWgradVoxels = 4096;   // voxels per weight-gradient workgroup
+
+__host__ __device__ inline int pad4(int c) { return (c + 3) / 4 * 4; }
+__host__ __device__ inline int pad16(int k) { return (k + 15) / 16 * 16; }
+
+__device__ inline short to_bf16(float v) {
+    return __builtin_bit_cast(short, static_cast<__bf16>(v));   // round to nearest even
+}
+
+__device__ inline bf16x4 to_bf16x4(float a, float b, float c, float d) {
+    bf16x4 r;
+    r[0] = to_bf16(a);
+    r[1] = to_bf16(b);
+    r[2] = to_bf16(c);
+    r[3] = to_bf16(d);
+    return r;
+}
+
+struct Vox {
+    int n, z, y, x;
+};
+
+__device__ inline Vox decompose(int v, int d, int h, int w) {
+    Vox r;
+    r.x = v % w;
+    r.y = (v / w) % h;
+    r.z = (v / (w * h)) % d;
+    r.n = v / (w * h * d);
+    return r;
+}
+
+// Index of the voxel at tap offset from p, or -1 outside the grid.
+__device__ inline int64_t tap_voxel(const Vox &p, int tap, int d, int h, int w) {
+    const int zz = p.z + tap / 9 - 1, yy = p.y + (tap / 3) % 3 - 1, xx = p.x + tap % 3 - 1;
+    if (zz < 0 || yy < 0 || xx < 0 || zz >= d || yy >= h || xx >= w) return -1;
+    return (((int64_t)p.n * d + zz) * h + yy) * w + xx;
+}
+
+__global__ void pack_kernel(const float *w, int co, int ci, int flip, uint16_t *out, int rows16, int k16) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= rows16 * k16) return;
+    const int row = idx / k16, k = idx % k16;
+    float v = 0.0f;
+    if (!flip) {
+        const int ci4 = pad4(ci), tap = k / ci4, c = k % ci4;
+        if (row < co && tap < kTaps && c < ci) v = w[((int64_t)row * kTaps + tap) * ci + c];
+    } else {
+        const int co4 = pad4(co), tap = k / co4, o = k % co4;
+        if (row < ci && tap < kTaps && o < co) v = w[((int64_t)o * kTaps + (kTaps - 1 - tap)) * ci + row];
+    }
+    out[idx] = __builtin_bit_cast(uint16_t, static_cast<__bf16>(v));
+}
+
+// One wave: 16 voxels x 16 output channels.  Four waves per workgroup, no
+// barriers, so a wave past the last voxel simply returns.
+__global__ __launch_bounds__(256) void conv_forward_kernel(const float *x, int n, int d, int h, int w, int ci,
+                                                           const uint16_t *packed, int co, const float *bias,
+                                                           int relu, float *y) {
+    const int ci4 = pad4(ci), co4 = pad4(co), k16 = pad16(kTaps * ci4);
+    const int nv = n * d * h * w;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int v0 = (blockIdx.x * 4 + wave) * 16;
+    const int co0 = blockIdx.y * 16;
+    if (v0 >= nv) return;
+    const int r = lane & 15, kg = lane >> 4;
+    const int va = v0 + r;
+    const Vox pa = decompose(va < nv ? va : 0, d, h, w);
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int kc = 0; kc < k16; kc += 16) {
+        const int k = kc + 4 * kg;
+        const int tap = k / ci4, c = k % ci4;   // 4 consecutive k share the tap
+        float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (va < nv && tap < kTaps) {
+            const int64_t src = tap_voxel(pa, tap, d, h, w);
+            if (src >= 0) a = *reinterpret_cast<const float4 *>(x + src * ci4 + c);
+        }
+        const bf16x4 A = to_bf16x4(a.x, a.y, a.z, a.w);
+        const bf16x4 B = *reinterpret_cast<const bf16x4 *>(packed + (int64_t)(co0 + r) * k16 + k);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B, acc, 0, 0, 0);
+    }
+    const int oc = co0 + r;
+    if (oc >= co4) return;
+    const float b = (bias && oc < co) ? bias[oc] : 0.0f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int v = v0 + 4 * kg + j;
+        if (v >= nv) continue;
+        float o = acc[j] + b;
+        if (relu) o = o > 0.0f ? o : 0.0f;
+        y[(int64_t)v * co4 + oc] = o;
+    }
+}
+
+// Weight gradient partials.  Workgroup (chunk, kt, ct): output channels
+// 16*ct.., reduction columns 16*kt.. over the chunk's voxels; each wave takes a
+// quarter of the voxels, the four wave tiles are summed in LDS in a fixed
+// order into work[chunk][co][k].
+__global__ __launch_bounds__(256) void conv_wgrad_kernel(const float *x, const float *gz, int n, int d, int h,
+                                                         int w, int ci, int co, float *work) {
+    const int ci4 = pad4(ci), co4 = pad4(co), k16 = pad16(kTaps * ci4), co16 = pad16(co);
+    const int nv = n * d * h * w;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int chunk = blockIdx.x, k0 = blockIdx.y * 16, c0 = blockIdx.z * 16;
+    const int r = lane & 15, kg = lane >> 4;
+    const int kcol = k0 + r;                       // this lane's B column
+    const int tap = kcol / ci4, cch = kcol % ci4;
+    const bool col_ok = tap < kTaps && cch < ci;
+    const int ocol = c0 + r;                       // this lane's A row (output channel)
+    const bool row_ok = ocol < co;
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    const int vbeg = chunk * kWgradVoxels + wave * (kWgradVoxels / 4);
+    const int vend = min(vbeg + kWgradVoxels / 4, nv);
+    for (int v0 = vbeg; v0 < vend; v0 += 16) {
+        float a[4], b[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int v = v0 + 4 * kg + j;
+            a[j] = 0.0f;
+            b[j] = 0.0f;
+            if (v < vend) {
+                if (row_ok) a[j] = gz[(int64_t)v * co4 + ocol];
+                if (col_ok) {
+                    const int64_t src = tap_voxel(decompose(v, d, h, w), tap, d, h, w);
+                    if (src >= 0) b[j] = x[src * ci4 + cch];
+                }
+            }
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(to_bf16x4(a[0], a[1], a[2], a[3]),
+                                                        to_bf16x4(b[0], b[1], b[2], b[3]), acc, 0, 0, 0);
+    }
+    __shared__ float tile[4][16][16];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) tile[wave][4 * kg + j][r] = acc[j];
+    __syncthreads();
+    const int t = threadIdx.x;   // 256 threads = one 16x16 tile
+    const int row = t / 16, col = t % 16;
+    const float s = ((tile[0][row][col] + tile[1][row][col]) + tile[2][row][col]) + tile[3][row][col];
+    work[((int64_t)chunk * co16 + c0 + row) * k16 + k0 + col] = s;
+}
+
+// gw[co][tap][ci] = sum over chunks (in order) of the partials.
+__global__ void wgrad_fold_kernel(const float *work, int nchunk, int ci, int co, float *gw) {
+    const int ci4 = pad4(ci), k16 = pad16(kTaps * ci4), co16 = pad16(co);
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= co * kTaps * ci) return;
+    const int c = idx % ci, tap = (idx / ci) % kTaps, o = idx / (ci * kTaps);
+    const int k = tap * ci4 + c;
+    float s = 0.0f;
+    for (int ch = 0; ch < nchunk; ++ch) s += work[((int64_t)ch * co16 + o) * k16 + k];
+    gw[idx] = s;
+}
+
+// gb[co] = sum_v gz[v][co]: one workgroup per channel, fixed-order tree.
+__global__ __launch_bounds__(256) void bias_grad_kernel(const float *gz, int64_t nv, int co4, float *gb) {
+    __shared__ float sh[256];
+    const int o = blockIdx.x;
+    float s = 0.0f;
+    for (int64_t v = threadIdx.x; v < nv; v += 256) s += gz[v * co4 + o];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) gb[o] = sh[0];
+}
+
+__global__ void relu_backward_kernel(const float *a, float *g, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count && !(a[i] > 0.0f)) g[i] = 0.0f;
+}
+
+__global__ __launch_bounds__(256) void mse_kernel(const float *y, int ys, const float *t, int64_t count, float *g,
+                                                  float *loss) {
+    __shared__ float sh[256];
+    float s = 0.0f;
+    const float scale = 2.0f / (float)count;
+    for (int64_t v = threadIdx.x; v < count; v += 256) {
+        const float e = y[v * ys] - t[v];
+        s += e * e;
+        g[v * ys] = scale * e;
+        for (int c = 1; c < ys; ++c) g[v * ys + c] = 0.0f;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = sh[0] / (float)count;
+}
+
+__global__ void adam_kernel(float *w, const float *g, float *m, float *v, int64_t count, float lr, float b1,
+                            float b2, float eps, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+int32_t launched() { return hipGetLastError() == hipSuccess ? 0 : -3; }
+
+unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+extern "C" {
+
+int64_t lbm_cnn_packed_size(int32_t co, int32_t ci) {
+    if (co < 1 || ci < 1) return -1;
+    return (int64_t)pad16(co) * pad16(kTaps * pad4(ci));
+}
+
+int32_t lbm_cnn_pack_weights(const float *w, int32_t co, int32_t ci, int32_t flip, uint16_t *packed,
+                             void *stream) {
+    if (!w || !packed || co < 1 || ci < 1) return -1;
+    const int rows16 = flip ? pad16(ci) : pad16(co);
+    const int k16 = flip ? pad16(kTaps * pad4(co)) : pad16(kTaps * pad4(ci));
+    hipLaunchKernelGGL(pack_kernel, dim3(blocks_for((int64_t)rows16 * k16, 256)), dim3(256), 0,
+                       (hipStream_t)stream, w, co, ci, flip, packed, rows16, k16);
+    return launched();
+}
+
+int32_t lbm_cnn_conv3d_forward(const float *x, int32_t n, int32_t d, int32_t h, int32_t wd, int32_t ci,
+                               const uint16_t *packed, int32_t co, const float *bias, int32_t relu,
+                               float *y, void *stream) {
+    if (!x || !packed || !y || n < 1 || d < 1 || h < 1 || wd < 1 || ci < 1 || co < 1) return -1;
+    if (((uintptr_t)x) % 16 || ((uintptr_t)packed) % 8) return -1;
+    const int64_t nv = (int64_t)n * d * h * wd;
+    if (nv >= (int64_t(1) << 31)) return -1;
+    const dim3 grid(blocks_for(nv, 64), pad16(co) / 16);
+    hipLaunchKernelGGL(conv_forward_kernel, grid, dim3(256), 0, (hipStream_t)stream, x, n, d, h, wd, ci, packed,
+                       co, bias, relu, y);
+    return launched();
+}
+
+int64_t lbm_cnn_wgrad_workspace(int32_t n, int32_t d, int32_t h, int32_t wd, int32_t ci, int32_t co) {
+    if (n < 1 || d < 1 || h < 1 || wd < 1 || ci < 1 || co < 1) return -1;
+    const int64_t nv = (int64_t)n * d * h * wd;
+    const int64_t nchunk = (nv + kWgradVoxels - 1) / kWgradVoxels;
+    return nchunk * pad16(co) * pad16(kTaps * pad4(ci)) * (int64_t)sizeof(float);
+}
+
+int32_t lbm_cnn_conv3d_wgrad(const float *x, const float *gz, int32_t n, int32_t d, int32_t h, int32_t wd,
+                             int32_t ci, int32_t co, float *work, float *gw, float *gb, void *stream) {
+    if (!x || !gz || !work || !gw || n < 1 || d < 1 || h < 1 || wd < 1 || ci < 1 || co < 1) return -1;
+    const int64_t nv = (int64_t)n * d * h * wd;
+    if (nv >= (int64_t(1) << 31)) return -1;
+    const int nchunk = (int)((nv + kWgradVoxels - 1) / kWgradVoxels);
+    hipStream_t st = (hipStream_t)stream;
+    const dim3 grid(nchunk, pad16(kTaps * pad4(ci)) / 16, pad16(co) / 16);
+    hipLaunchKernelGGL(conv_wgrad_kernel, grid, dim3(256), 0, st, x, gz, n, d, h, wd, ci, co, work);
+    hipLaunchKernelGGL(wgrad_fold_kernel, dim3(blocks_for((int64_t)co * kTaps * ci, 256)), dim3(256), 0, st,
+                       work, nchunk, ci, co, gw);
+    if (gb) hipLaunchKernelGGL(bias_grad_kernel, dim3(co), dim3(256), 0, st, gz, nv, pad4(co), gb);
+    return launched();
+}
+
+int32_t lbm_cnn_relu_backward(const float *a, float *g, int64_t count, void *stream) {
+    if (!a || !g || count < 0) return -1;
+    if (count == 0) return 0;
+    hipLaunchKernelGGL(relu_backward_kernel, dim3(blocks_for(count, 256)), dim3(256), 0, (hipStream_t)stream, a,
+                       g, count);
+    return launched();
+}
+
+int32_t lbm_cnn_mse(const float *y, int32_t ystride, const float *target, int64_t count, float *g,
+                    float *loss, void *stream) {
+    if (!y || !target || !g || !loss || ystride < 1 || count < 1) return -1;
+    hipLaunchKernelGGL(mse_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, y, ystride, target, count, g,
+                       loss);
+    return launched();
+}
+
+int32_t lbm_cnn_adam(float *w, const float *g, float *m, float *v, int64_t count, float lr, float beta1,
+                     float beta2, float eps, int32_t t, void *stream) {
+    if (!w || !g || !m || !v || count < 0 || t < 1) return -1;
+    if (count == 0) return 0;
+    const float c1 = 1.0f - powf(beta1, (float)t), c2 = 1.0f - powf(beta2, (float)t);
+    hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(count, 256)), dim3(256), 0, (hipStream_t)stream, w, g, m, v,
+                       count, lr, beta1, beta2, eps, c1, c2);
+    return launched();
+}
+
+}  // extern "C"

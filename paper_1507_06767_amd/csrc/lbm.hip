@@ -88,6 +88,7 @@ struct Layout {
     size_t avg_off;       // per-cell running sensor sums (time average)
     size_t lev_off;       // two per-block int8 level arrays
     size_t avgmax_off;    // per-block float64 maxima of the averaged sensor
+    size_t means_off;     // per-block float64 means of (rho - rho0, u)
 };
 
 bool is_fin(double v) { return std::isfinite(v); }
@@ -159,7 +160,8 @@ lbm_status check_desc(const lbm_desc *d, Layout *L) {
     L->avg_off = L->out_off + kAlign;
     L->lev_off = L->avg_off + round_up((size_t)cells * L->cbytes, kAlign);
     L->avgmax_off = L->lev_off + round_up((size_t)L->nblocks * 2, kAlign);
-    L->bytes[LBM_BUF_SCRATCH] = L->avgmax_off + round_up((size_t)L->nblocks * 8, kAlign);
+    L->means_off = L->avgmax_off + round_up((size_t)L->nblocks * 8, kAlign);
+    L->bytes[LBM_BUF_SCRATCH] = L->means_off + round_up((size_t)L->nblocks * 4 * 8, kAlign);
     return LBM_OK;
 }
 
@@ -630,6 +632,30 @@ lbm_status lbm_get_macros(lbm_blocks *h, double *rho_host, double *u_host) {
     HIP_TRY(hipGetLastError());
     if (rho_host) HIP_TRY(hipMemcpyAsync(rho_host, rho_d, cells * 8, hipMemcpyDeviceToHost, h->stream));
     if (u_host) HIP_TRY(hipMemcpyAsync(u_host, u_d, 3 * cells * 8, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_block_means(lbm_blocks *h, double *means_host) {
+    lbm_status st = check_handle(h);
+    if (st != LBM_OK) return st;
+    if (!means_host) return fail(LBM_EINVAL, "means_host is NULL");
+    const int64_t cells = h->L.cells;
+    double *rho_d = scratch_d(h, h->L.staging_off);
+    double *u_d = rho_d + cells;
+    double *out = scratch_d(h, h->L.means_off);
+    void *canon = canonical_state(h);
+    with_types(h, [&]<int Q, typename T>() {
+        hipLaunchKernelGGL((macros_kernel<Q, T>), dim3(grid_for(cells)), dim3(kAuxThreads), 0, h->stream,
+                           planes_of<Q, T>(h, canon), rho_d, u_d, h->d.force[0], h->d.force[1],
+                           h->d.force[2]);
+    });
+    const int bz = h->L.dim == 2 ? 1 : kBlockEdge;
+    hipLaunchKernelGGL(block_means_kernel, dim3(grid_for(h->L.nblocks)), dim3(kAuxThreads), 0, h->stream, rho_d,
+                       u_d, h->d.extent[0], h->d.extent[1], h->d.extent[2], h->L.nb[0], h->L.nb[1], h->L.nb[2], bz,
+                       h->d.rho0, out);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(means_host, out, h->L.nblocks * 4 * 8, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     return LBM_OK;
 }

@@ -1,0 +1,239 @@
+"""Learned refinement-flag predictor on top of the kinetic sensor.
+
+The sensor's block maxima M_b (Sec. 3.2, blocks of Sec. 3.4) say where the
+mesh must be fine now; regridding every so many steps wants to know where it
+must be fine by the next regrid.  ``FlagPredictor`` is a small 3D CNN over
+the block grid that predicts log10 M_b `horizon` steps ahead from the
+per-block means of (rho - rho0, u) and log10 M_b now.  It predicts the change
+of log10 M_b, so "no change" (reusing the current flags) is what an untrained
+network returns.
+
+Every product runs in the matrix-core kernels of liblbm.so (bindings in
+``cnn``): forward, data and weight gradients, ReLU backward, the loss and
+Adam.  Torch provides device memory and the stream; numpy only marshals the
+small per-block feature arrays (4096 blocks x 5 values at 128^3).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import cnn
+from .abi import LbmError
+
+LOG_FLOOR = 1e-12   # block maxima below this are taken as this before log10
+
+
+def _check(st, what):
+    if st != 0:
+        raise LbmError(st, f"{what} failed")
+
+
+def log_sensor(bm):
+    return np.log10(np.maximum(np.asarray(bm, dtype=np.float64), LOG_FLOOR))
+
+
+def features(means, bm):
+    """Raw per-block features [nbz, nby, nbx, 5]: (rho - rho0, u, log10 M)."""
+    return np.concatenate([np.asarray(means, dtype=np.float64), log_sensor(bm)[..., None]], axis=-1)
+
+
+@dataclass
+class Normalizer:
+    """Per-channel affine map of the raw features, fitted on training data."""
+    mean: np.ndarray
+    scale: np.ndarray
+
+    @staticmethod
+    def fit(raw):
+        flat = np.asarray(raw, dtype=np.float64).reshape(-1, raw.shape[-1])
+        sd = flat.std(axis=0)
+        return Normalizer(flat.mean(axis=0), np.where(sd > 0, 1.0 / np.maximum(sd, 1e-30), 1.0))
+
+    def __call__(self, raw):
+        return (np.asarray(raw, dtype=np.float64) - self.mean) * self.scale
+
+
+class _Layer:
+    def __init__(self, ci, co, relu, rng, device):
+        self.ci, self.co, self.relu = ci, co, relu
+        std = math.sqrt(2.0 / (27 * ci)) if relu else 0.1 * math.sqrt(1.0 / (27 * ci))
+        w = rng.standard_normal((co, 27, ci)) * std
+        self.w = torch.tensor(w, dtype=torch.float32, device=device)
+        self.b = torch.zeros(co, dtype=torch.float32, device=device)
+        self.gw = torch.zeros_like(self.w)
+        self.gb = torch.zeros_like(self.b)
+        self.mw, self.vw = torch.zeros_like(self.w), torch.zeros_like(self.w)
+        self.mb, self.vb = torch.zeros_like(self.b), torch.zeros_like(self.b)
+        self.packed = torch.zeros(cnn.lbm_cnn_packed_size(co, ci), dtype=torch.int16, device=device)
+        self.packed_flip = torch.zeros(cnn.lbm_cnn_packed_size(ci, co), dtype=torch.int16, device=device)
+
+    def pack(self, stream):
+        _check(cnn.lbm_cnn_pack_weights(self.w, self.co, self.ci, 0, self.packed, stream), "pack")
+        _check(cnn.lbm_cnn_pack_weights(self.w, self.co, self.ci, 1, self.packed_flip, stream), "pack flip")
+
+
+class FlagPredictor:
+    """channels: (input, hidden..., 1); 3x3x3 convolutions, ReLU between."""
+
+    def __init__(self, channels=(5, 16, 16, 16, 1), seed=0, device="cuda", stream=None):
+        self.device = torch.device(device)
+        self.stream = stream
+        rng = np.random.default_rng(seed)
+        self.channels = tuple(channels)
+        self.layers = [_Layer(channels[k], channels[k + 1], k + 2 < len(channels), rng, self.device)
+                       for k in range(len(channels) - 1)]
+        self.t = 0
+        self.normalizer = None
+        self._bufs = {}
+        self._pack()
+
+    # -- buffers ---------------------------------------------------------------
+    def _pack(self):
+        for L in self.layers:
+            L.pack(self.stream)
+
+    def _buffers(self, shape):
+        if shape not in self._bufs:
+            n, d, h, w = shape
+            nv = n * d * h * w
+            z = lambda c: torch.zeros(nv * cnn.pad4(c), dtype=torch.float32, device=self.device)
+            acts = [z(L.co) for L in self.layers]
+            grads = [z(c) for c in self.channels[:-1]] + [z(self.channels[-1])]
+            ws = max(cnn.lbm_cnn_wgrad_workspace(n, d, h, w, L.ci, L.co) for L in self.layers) // 4
+            self._bufs[shape] = dict(x=z(self.channels[0]), acts=acts, grads=grads,
+                                     work=torch.zeros(ws, dtype=torch.float32, device=self.device),
+                                     target=torch.zeros(nv, dtype=torch.float32, device=self.device),
+                                     loss=torch.zeros(1, dtype=torch.float32, device=self.device))
+        return self._bufs[shape]
+
+    def load_input(self, x, shape):
+        """x: float array (n, d, h, w, C0) (already normalized) -> device."""
+        B = self._buffers(shape)
+        c4 = cnn.pad4(self.channels[0])
+        xp = np.zeros(shape + (c4,), dtype=np.float32)
+        xp[..., :self.channels[0]] = x
+        B["x"].copy_(torch.from_numpy(xp.reshape(-1)))
+        return B
+
+    # -- network -----------------------------------------------------------------
+    def forward_device(self, shape):
+        """Runs the layers on the loaded input; returns the last activation."""
+        B = self._buffers(shape)
+        n, d, h, w = shape
+        a = B["x"]
+        for L, out in zip(self.layers, B["acts"]):
+            _check(cnn.lbm_cnn_conv3d_forward(a, n, d, h, w, L.ci, L.packed, L.co, L.b, L.relu, out,
+                                              self.stream), "conv forward")
+            a = out
+        return a
+
+    def backward_device(self, shape):
+        """Gradients of the loss whose output gradient is in grads[-1]."""
+        B = self._buffers(shape)
+        n, d, h, w = shape
+        nv = n * d * h * w
+        g = B["grads"][-1]
+        for k in range(len(self.layers) - 1, -1, -1):
+            L = self.layers[k]
+            if L.relu:
+                _check(cnn.lbm_cnn_relu_backward(B["acts"][k], g, nv * cnn.pad4(L.co), self.stream), "relu bwd")
+            inp = B["x"] if k == 0 else B["acts"][k - 1]
+            _check(cnn.lbm_cnn_conv3d_wgrad(inp, g, n, d, h, w, L.ci, L.co, B["work"], L.gw, L.gb, self.stream),
+                   "wgrad")
+            if k > 0:
+                gin = B["grads"][k]
+                _check(cnn.lbm_cnn_conv3d_forward(g, n, d, h, w, L.co, L.packed_flip, L.ci, None, 0, gin,
+                                                  self.stream), "dgrad")
+                g = gin
+
+    def loss_and_grads(self, x, target):
+        """Loss (float) and gradients (in each layer's gw, gb) on a batch.
+        x (n, d, h, w, C0) normalized inputs, target (n, d, h, w)."""
+        shape = tuple(target.shape)
+        B = self.load_input(x, shape)
+        B["target"].copy_(torch.from_numpy(np.ascontiguousarray(target, dtype=np.float32).reshape(-1)))
+        y = self.forward_device(shape)
+        nv = int(np.prod(shape))
+        _check(cnn.lbm_cnn_mse(y, cnn.pad4(self.channels[-1]), B["target"], nv, B["grads"][-1], B["loss"],
+                               self.stream), "mse")
+        self.backward_device(shape)
+        return B["loss"]
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.t += 1
+        for L in self.layers:
+            _check(cnn.lbm_cnn_adam(L.w, L.gw, L.mw, L.vw, L.w.numel(), lr, beta1, beta2, eps, self.t,
+                                    self.stream), "adam")
+            _check(cnn.lbm_cnn_adam(L.b, L.gb, L.mb, L.vb, L.b.numel(), lr, beta1, beta2, eps, self.t,
+                                    self.stream), "adam")
+        self._pack()
+
+    def predict_raw(self, x):
+        """Network output channel 0 for normalized inputs x (n, d, h, w, C0)."""
+        shape = tuple(x.shape[:4])
+        self.load_input(x, shape)
+        y = self.forward_device(shape)
+        c4 = cnn.pad4(self.channels[-1])
+        return y.view(-1, c4)[:, 0].cpu().numpy().astype(np.float64).reshape(shape)
+
+    # -- the flag predictor ------------------------------------------------------
+    def fit(self, raw, target_log, iters=1500, batch=8, lr=2e-3, seed=0, log_every=0):
+        """Trains on raw features [S, nbz, nby, nbx, 5] to predict
+        target_log [S, nbz, nby, nbx] = log10 M_b at the horizon.  The network
+        learns target - log10 M_b(now).  Returns the loss history."""
+        self.normalizer = Normalizer.fit(raw)
+        xs = self.normalizer(raw)
+        dy = np.asarray(target_log, dtype=np.float64) - raw[..., -1]
+        rng = np.random.default_rng(seed)
+        hist = []
+        S = raw.shape[0]
+        for it in range(iters):
+            idx = rng.choice(S, size=min(batch, S), replace=False)
+            loss = self.loss_and_grads(xs[idx], dy[idx])
+            self.adam_step(lr * 0.5 * (1.0 + math.cos(math.pi * it / iters)))
+            if log_every and (it % log_every == 0 or it + 1 == iters):
+                hist.append((it, float(loss.item())))
+        return hist
+
+    def predict_log(self, raw):
+        """Predicted log10 M_b at the horizon for raw features [S, ..., 5]."""
+        if self.normalizer is None:
+            raise RuntimeError("the predictor has not been fitted")
+        return raw[..., -1] + self.predict_raw(self.normalizer(raw))
+
+
+def snapshot_run(Blocks, desc, snapshots, horizon, warm=0):
+    """Runs one grid and records (raw features at t, log10 M_b at t + horizon)
+    for t = warm + horizon * j, j < snapshots.  Returns (raw, target_log) or
+    None if the run goes non-finite."""
+    blk = Blocks(desc)
+    try:
+        raw, tgt = [], []
+        if warm:
+            blk.step_n(warm - 1, 0)
+        blk.step_n(1, 1)
+        bm, _, _, bad = blk.sensor_flags()
+        cur = features(blk.block_means(), bm)
+        for _ in range(snapshots):
+            blk.step_n(horizon, horizon)
+            bm, _, _, bad = blk.sensor_flags()
+            if bad or not np.isfinite(cur).all():
+                return None
+            raw.append(cur)
+            tgt.append(log_sensor(bm))
+            cur = features(blk.block_means(), bm)
+        return np.stack(raw), np.stack(tgt)
+    finally:
+        blk.close()
+
+
+def flag_scores(pred_flags, true_flags):
+    """(precision, recall) of boolean refine flags."""
+    tp = float(np.sum(pred_flags & true_flags))
+    p = tp / max(1.0, float(np.sum(pred_flags)))
+    r = tp / max(1.0, float(np.sum(true_flags)))
+    return p, r

@@ -9,6 +9,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "lbm.h")
+HEADERS = sorted(os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+                 if f.endswith(".h"))
 
 
 @pytest.fixture(scope="module")
@@ -17,17 +19,46 @@ def lbm():
     return lbm
 
 
-def _declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text)))
+def _declared_functions(headers=None):
+    names = set()
+    for path in headers or HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(path).read(), flags=re.S)
+        names.update(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_interface():
-    names = _declared_functions()
-    for required in ("lbm_create_blocks", "lbm_step_n", "lbm_sensor_flags", "lbm_get_macros"):
+    names = _declared_functions([HEADER])
+    for required in ("lbm_create_blocks", "lbm_step_n", "lbm_sensor_flags", "lbm_get_macros",
+                     "lbm_block_means"):
         assert required in names
     assert len(names) >= 14
+    cnn = _declared_functions([os.path.join(ROOT, "include", "lbm_cnn.h")])
+    assert {"lbm_cnn_conv3d_forward", "lbm_cnn_conv3d_wgrad", "lbm_cnn_adam", "lbm_cnn_mse"} <= set(cnn)
+
+
+def test_cnn_sizes_and_argument_checks(lbm):
+    """Sizes of packed weights and the weight-gradient workspace, and the
+    argument checks that return before any launch."""
+    lib = ctypes.CDLL(lbm.library_path())
+    lib.lbm_cnn_packed_size.restype = ctypes.c_int64
+    lib.lbm_cnn_wgrad_workspace.restype = ctypes.c_int64
+    # Co16 x pad16(27 * Ci4): (16, 5) -> 16 x pad16(216) = 16 x 224
+    assert lib.lbm_cnn_packed_size(16, 5) == 16 * 224
+    assert lib.lbm_cnn_packed_size(1, 16) == 16 * 432
+    assert lib.lbm_cnn_packed_size(0, 4) == -1
+    # chunks of 4096 voxels x Co16 x K16 floats
+    assert lib.lbm_cnn_wgrad_workspace(2, 16, 16, 16, 16, 16) == 2 * 16 * 432 * 4
+    assert lib.lbm_cnn_wgrad_workspace(1, 16, 16, 17, 16, 1) == 2 * 16 * 432 * 4
+    f = lib.lbm_cnn_conv3d_forward
+    f.argtypes = [ctypes.c_void_p] + [ctypes.c_int32] * 5 + [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                                             ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    assert f(None, 1, 2, 2, 2, 4, None, 4, None, 0, None, None) == -1
+    assert f(16, 0, 2, 2, 2, 4, 16, 4, None, 0, 16, None) == -1
+    assert f(20, 1, 2, 2, 2, 4, 16, 4, None, 0, 16, None) == -1       # x not 16-byte aligned
+    lib.lbm_cnn_adam.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int64] + [ctypes.c_float] * 4 + \
+        [ctypes.c_int32, ctypes.c_void_p]
+    assert lib.lbm_cnn_adam(16, 16, 16, 16, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == -1   # t < 1
 
 
 def test_library_exports_every_declared_symbol(lbm):

@@ -1,0 +1,213 @@
+"""The flag predictor's matrix-core kernels against the FP64 network oracle
+(oracle/cnn.py), through the C interface of include/lbm_cnn.h.
+
+The kernels multiply in bfloat16 and accumulate in float32.  Each comparison
+gives the oracle the same bfloat16-rounded operands (oracle.cnn.bf16_round)
+and bounds the difference by the float32 accumulation error of a sum of K
+products in any order, K u sum |a_k b_k| with u = 2^-23 (covers truncating
+as well as nearest adds), K the number of products per output.
+"""
+import numpy as np
+import pytest
+
+from oracle import cnn as ocnn
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -23
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1507_06767_amd import cnn
+    return torch, cnn
+
+
+def _dev(torch, a, dtype=None):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype or torch.float32, device="cuda")
+
+
+def _padded(a, c4):
+    out = np.zeros(a.shape[:-1] + (c4,), dtype=np.float32)
+    out[..., :a.shape[-1]] = a
+    return out
+
+
+def _pack(torch, cnn, w, co, ci, flip):
+    size = cnn.lbm_cnn_packed_size(ci, co) if flip else cnn.lbm_cnn_packed_size(co, ci)
+    packed = torch.zeros(size, dtype=torch.int16, device="cuda")
+    assert cnn.lbm_cnn_pack_weights(_dev(torch, w), co, ci, flip, packed) == 0
+    return packed
+
+
+def _forward(torch, cnn, x, w, b, relu, flip=False):
+    """Runs lbm_cnn_conv3d_forward; returns the output with all C4 channels."""
+    n, d, h, wd, cin = x.shape
+    cout = w.shape[2] if flip else w.shape[0]
+    co, ci = w.shape[0], w.shape[2]
+    packed = _pack(torch, cnn, w, co, ci, flip)
+    xd = _dev(torch, _padded(x, cnn.pad4(cin)))
+    y = torch.full((n * d * h * wd * cnn.pad4(cout),), float("nan"), dtype=torch.float32, device="cuda")
+    bd = _dev(torch, b) if b is not None else None
+    assert cnn.lbm_cnn_conv3d_forward(xd, n, d, h, wd, cin, packed, cout, bd, relu, y) == 0
+    torch.cuda.synchronize()
+    return y.cpu().numpy().astype(np.float64).reshape(n, d, h, wd, cnn.pad4(cout))
+
+
+_SHAPES = [((2, 5, 6, 7), 5, 16), ((1, 9, 4, 11), 16, 16), ((3, 3, 5, 4), 16, 1), ((1, 16, 16, 16), 16, 7)]
+
+
+@pytest.mark.parametrize("relu", [0, 1])
+@pytest.mark.parametrize("case", _SHAPES, ids=[f"{c[0]}_{c[1]}to{c[2]}" for c in _SHAPES])
+def test_conv_forward(env, case, relu):
+    torch, cnn = env
+    shape, ci, co = case
+    print(f"\n[case] forward {shape} {ci}->{co} relu={relu}", flush=True)
+    rng = np.random.default_rng(100 * ci + co + sum(shape))
+    x = rng.standard_normal(shape + (ci,)).astype(np.float32)
+    w = (rng.standard_normal((co, 27, ci)) * 0.2).astype(np.float32)
+    b = (rng.standard_normal(co) * 0.1).astype(np.float32)
+    y = _forward(torch, cnn, x, w, b, relu)
+    xq, wq = ocnn.bf16_round(x), ocnn.bf16_round(w)
+    ref = ocnn.conv3d(xq, wq, b.astype(np.float64))
+    if relu:
+        ref = ocnn.relu(ref)
+    bound = (27 * ci + 1) * U32 * (ocnn.conv3d(np.abs(xq), np.abs(wq)) + np.abs(b)) + 1e-30
+    err = np.abs(y[..., :co] - ref)
+    print(f"forward: max err {err.max():.2e}, max err/bound {(err / bound).max():.3f}")
+    assert (err <= bound).all()
+    assert (y[..., co:] == 0).all(), "padding channels must be zero"
+
+
+@pytest.mark.parametrize("case", _SHAPES[:3], ids=[f"{c[0]}_{c[1]}to{c[2]}" for c in _SHAPES[:3]])
+def test_conv_data_gradient(env, case):
+    """Forward kernel with flip-packed weights = gradient with respect to the
+    input."""
+    torch, cnn = env
+    shape, ci, co = case
+    print(f"\n[case] dgrad {shape} {ci}->{co}", flush=True)
+    rng = np.random.default_rng(7 + ci + co)
+    gz = rng.standard_normal(shape + (co,)).astype(np.float32)
+    w = (rng.standard_normal((co, 27, ci)) * 0.2).astype(np.float32)
+    gx = _forward(torch, cnn, gz, w, None, 0, flip=True)
+    gq, wq = ocnn.bf16_round(gz), ocnn.bf16_round(w)
+    ref = ocnn.conv3d_dgrad(gq, wq)
+    bound = 27 * co * U32 * ocnn.conv3d_dgrad(np.abs(gq), np.abs(wq)) + 1e-30
+    err = np.abs(gx[..., :ci] - ref)
+    print(f"dgrad: max err {err.max():.2e}, max err/bound {(err / bound).max():.3f}")
+    assert (err <= bound).all()
+    assert (gx[..., ci:] == 0).all()
+
+
+_WSHAPES = [((2, 5, 6, 7), 5, 16), ((1, 16, 16, 17), 16, 16), ((2, 8, 8, 8), 16, 1)]
+
+
+@pytest.mark.parametrize("case", _WSHAPES, ids=[f"{c[0]}_{c[1]}to{c[2]}" for c in _WSHAPES])
+def test_conv_weight_gradient(env, case):
+    torch, cnn = env
+    shape, ci, co = case
+    n, d, h, wd = shape
+    print(f"\n[case] wgrad {shape} {ci}->{co}", flush=True)
+    rng = np.random.default_rng(11 + ci + co)
+    x = rng.standard_normal(shape + (ci,)).astype(np.float32)
+    gz = rng.standard_normal(shape + (co,)).astype(np.float32)
+    xd = _dev(torch, _padded(x, cnn.pad4(ci)))
+    gd = _dev(torch, _padded(gz, cnn.pad4(co)))
+    work = torch.zeros(cnn.lbm_cnn_wgrad_workspace(n, d, h, wd, ci, co) // 4, dtype=torch.float32, device="cuda")
+    outs = []
+    for _ in range(2):
+        gw = torch.full((co * 27 * ci,), float("nan"), dtype=torch.float32, device="cuda")
+        gb = torch.full((co,), float("nan"), dtype=torch.float32, device="cuda")
+        assert cnn.lbm_cnn_conv3d_wgrad(xd, gd, n, d, h, wd, ci, co, work, gw, gb) == 0
+        torch.cuda.synchronize()
+        outs.append((gw.cpu().numpy().astype(np.float64).reshape(co, 27, ci), gb.cpu().numpy().astype(np.float64)))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1]), "not deterministic"
+    gw, gb = outs[0]
+    xq, gq = ocnn.bf16_round(x), ocnn.bf16_round(gz)
+    ref_w, _ = ocnn.conv3d_wgrad(xq, gq)
+    nv = n * d * h * wd
+    bound_w = nv * U32 * ocnn.conv3d_wgrad(np.abs(xq), np.abs(gq))[0] + 1e-30
+    _, ref_b = ocnn.conv3d_wgrad(x, gz)                       # bias gradient: float32 sums, no rounding
+    bound_b = nv * U32 * np.abs(gz.astype(np.float64)).reshape(-1, co).sum(axis=0)
+    ew, eb = np.abs(gw - ref_w), np.abs(gb - ref_b)
+    print(f"wgrad: max err {ew.max():.2e} (err/bound {(ew / bound_w).max():.3f}); "
+          f"bias grad max err {eb.max():.2e} (err/bound {(eb / bound_b).max():.3f})")
+    assert (ew <= bound_w).all() and (eb <= bound_b).all()
+
+
+def test_relu_backward_mse_adam(env):
+    torch, cnn = env
+    print("\n[case] relu backward, mse, adam", flush=True)
+    rng = np.random.default_rng(5)
+    a = rng.standard_normal(1000).astype(np.float32)
+    a[::7] = 0.0
+    g = rng.standard_normal(1000).astype(np.float32)
+    gd = _dev(torch, g)
+    assert cnn.lbm_cnn_relu_backward(_dev(torch, a), gd, 1000) == 0
+    assert np.array_equal(gd.cpu().numpy(), np.where(a > 0, g, 0.0).astype(np.float32))
+    # MSE on channel 0 of a 4-channel output
+    nv = 3001
+    y = rng.standard_normal((nv, 4)).astype(np.float32)
+    t = rng.standard_normal(nv).astype(np.float32)
+    gy = torch.full((nv * 4,), float("nan"), dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    assert cnn.lbm_cnn_mse(_dev(torch, y), 4, _dev(torch, t), nv, gy, loss) == 0
+    torch.cuda.synchronize()
+    ref_l, ref_g = ocnn.mse(y[:, 0], t)
+    gy = gy.cpu().numpy().reshape(nv, 4)
+    assert abs(loss.item() - ref_l) <= 1e-5 * ref_l
+    assert np.allclose(gy[:, 0], ref_g, rtol=1e-6, atol=0) and (gy[:, 1:] == 0).all()
+    # Adam, 5 steps
+    w0 = rng.standard_normal(777)
+    wd, md, vd = _dev(torch, w0), torch.zeros(777, device="cuda"), torch.zeros(777, device="cuda")
+    w, m, v = w0.copy(), np.zeros(777), np.zeros(777)
+    for step in range(1, 6):
+        gr = rng.standard_normal(777).astype(np.float32)
+        assert cnn.lbm_cnn_adam(wd, _dev(torch, gr), md, vd, 777, 1e-2, 0.9, 0.999, 1e-8, step) == 0
+        w, m, v = ocnn.adam(w, gr.astype(np.float64), m, v, step, 1e-2)
+    torch.cuda.synchronize()
+    err = np.abs(wd.cpu().numpy() - w).max()
+    print(f"adam: max err after 5 steps {err:.2e}")
+    assert err < 1e-6
+
+
+def test_network_gradients_against_oracle(env):
+    """A 5 -> 16 -> 16 -> 16 -> 1 network on two 16^3 block grids: loss and
+    every weight and bias gradient from the GPU against the oracle's
+    backpropagation with bfloat16-rounded product inputs (and, for scale,
+    against the oracle in plain float64).
+
+    Between layers the GPU rounds float32 activations and gradients to
+    bfloat16 while the oracle rounds float64 ones, so a few values per layer
+    fall on opposite sides of a rounding boundary and differ by one bfloat16
+    ulp (2^-8 relative); these differences pass through the later layers.
+    The bound of 5e-3 on the relative L2 error of each gradient is about 3x
+    the largest measured on MI355X (1.4e-3, a bias gradient, whose sum
+    cancels).  Against plain float64 the gradients keep their direction
+    (cosine > 0.99)."""
+    torch, cnn = env
+    from paper_1507_06767_amd.predictor import FlagPredictor
+    print("\n[case] network gradients 2x16^3", flush=True)
+    net = FlagPredictor(seed=3)
+    rng = np.random.default_rng(9)
+    shape = (2, 16, 16, 16)
+    x = rng.standard_normal(shape + (5,)).astype(np.float32)
+    t = rng.standard_normal(shape).astype(np.float32)
+    loss = net.loss_and_grads(x, t).item()
+    params = [(L.w.cpu().numpy().astype(np.float64), L.b.cpu().numpy().astype(np.float64)) for L in net.layers]
+    ref_loss, ref = ocnn.loss_and_grads(params, x, t, q=ocnn.bf16_round)
+    plain_loss, plain = ocnn.loss_and_grads(params, x, t)
+    print(f"loss gpu {loss:.6e} oracle(bf16 products) {ref_loss:.6e} oracle(fp64) {plain_loss:.6e}")
+    assert abs(loss - ref_loss) <= 1e-4 * ref_loss
+    for k, L in enumerate(net.layers):
+        gw = L.gw.cpu().numpy().astype(np.float64)
+        gb = L.gb.cpu().numpy().astype(np.float64)
+        rw = np.linalg.norm(gw - ref[k][0]) / np.linalg.norm(ref[k][0])
+        rb = np.linalg.norm(gb - ref[k][1]) / np.linalg.norm(ref[k][1])
+        pw = np.linalg.norm(gw - plain[k][0]) / np.linalg.norm(plain[k][0])
+        cos = float(np.sum(gw * plain[k][0]) / (np.linalg.norm(gw) * np.linalg.norm(plain[k][0])))
+        print(f"layer {k}: rel L2 err w {rw:.2e} b {rb:.2e} (vs fp64 oracle: w {pw:.2e}, cosine {cos:.5f})")
+        assert rw < 5e-3 and rb < 5e-3
+        assert cos > 0.99

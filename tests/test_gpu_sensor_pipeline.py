@@ -123,3 +123,28 @@ def test_time_averaged_sensor(lbm, orc, storage, kind, scheme):
     blk.step_n(4, 2)
     assert blk.average()[1] == 15          # no longer accumulating
     blk.close()
+
+
+@pytest.mark.parametrize("storage", [0, 2], ids=["f64", "f32s"])
+@pytest.mark.parametrize("case", _CASES, ids=[c[0] for c in _CASES])
+def test_block_means(lbm, orc, case, storage):
+    """Per-block means of (rho - rho0, u) -- the flag predictor's inputs --
+    against the oracle's macroscopic fields averaged per block (ragged edge
+    blocks on both grids)."""
+    from oracle import cnn as ocnn
+    name, q, n, bc = case
+    print(f"\n[case] block means {name} storage={storage}", flush=True)
+    wall_u = _wall(0.08)
+    desc = lbm.make_desc(q, n, bc, 0.6, storage=storage, wall_u=wall_u)
+    G = orc.Grid(q=q, n=n, bc=bc, wall_u=wall_u, tau=0.6)
+    blk = lbm.Blocks(desc)
+    blk.step_n(30, 0)
+    m = blk.block_means()
+    S, _ = G.run(G.equilibrium_state(), 0, 30, 0)
+    rho, u = G.macros(S)
+    ref = ocnn.block_means(rho, u, G.block)
+    assert m.shape == ref.shape
+    err = np.abs(m - ref).max()
+    print(f"block means {name}: max abs err {err:.2e} (max |u| {np.abs(ref[..., 1:]).max():.2e})")
+    assert err <= (1e-13 if storage == 0 else 2e-7)
+    blk.close()
