@@ -76,6 +76,8 @@ class _Params(ctypes.Structure):
         ("block", ctypes.c_int32 * 3),
         ("theta_refine", ctypes.c_double),
         ("theta_coarsen", ctypes.c_double),
+        ("smagorinsky", ctypes.c_double),
+        ("wall_profile", ctypes.c_int32 * 6),
     ]
 
 
@@ -159,6 +161,8 @@ class Grid:
     block: tuple = None
     theta_refine: float = 1e-3
     theta_coarsen: float = 5e-4
+    smagorinsky: float = 0.0
+    wall_profile: tuple = (0,) * 6
     _p: _Params = field(default=None, init=False, repr=False)
 
     def __post_init__(self):
@@ -177,6 +181,9 @@ class Grid:
         p.tau, p.rho0 = float(self.tau), float(self.rho0)
         p.sensor_kind = int(self.sensor_kind)
         p.theta_refine, p.theta_coarsen = float(self.theta_refine), float(self.theta_coarsen)
+        p.smagorinsky = float(self.smagorinsky)
+        for k in range(6):
+            p.wall_profile[k] = int(self.wall_profile[k])
         self._p = p
         self._perm = abi_permutation(self.q)      # interface index -> oracle index
         self._inv = np.argsort(self._perm)         # oracle index -> interface index

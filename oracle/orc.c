@@ -66,6 +66,8 @@ typedef struct {
     int32_t block[3];        /* sensor block edge per axis */
     double theta_refine;     /* refine iff M > theta_refine */
     double theta_coarsen;    /* coarsen iff M < theta_coarsen */
+    double smagorinsky;      /* Smagorinsky constant C (0: plain BGK) */
+    int32_t wall_profile[6]; /* 1: smoothed wall velocity on that face */
 } orc_params;
 
 /* ---------------------------------------------------------------------------
@@ -181,6 +183,8 @@ static int check_params(const orc_params *p, orc_lattice *L)
     for (int a = 0; a < 3; ++a) if (p->n[a] < 1) return -1;
     if (L->d == 2 && p->n[2] != 1) return -1;
     if (!(p->tau > 0.5)) return -1;
+    if (!(p->smagorinsky >= 0.0)) return -1;
+    for (int f = 0; f < 6; ++f) if (p->wall_profile[f] != 0 && p->wall_profile[f] != 1) return -1;
     /* a periodic face needs its opposite face to be periodic as well */
     for (int a = 0; a < 3; ++a)
         if ((p->bc[2 * a] == 0) != (p->bc[2 * a + 1] == 0)) return -1;
@@ -198,6 +202,24 @@ int orc_equilibrium_field(const orc_params *p, const double *rho, const double *
     return 0;
 }
 
+/* Smoothed wall velocity (the lid profile of the 3D cavity, Sec. 5.1): the
+ * face's velocity times prod over the face's in-plane axes a of
+ * (1 - s_a^18)^2, s_a = 2 (x_a + 1/2) / n_a - 1 the cell-centre coordinate
+ * mapped to (-1, 1), i.e. x/h - 1 on a side of length 2h.  An axis with one
+ * cell (the z axis of a 2D grid) has s = 0 and contributes 1. */
+static double wall_profile_factor(const orc_params *p, int face, const int *x)
+{
+    if (!p->wall_profile[face]) return 1.0;
+    double g = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        if (a == face / 2) continue;
+        const double s = 2.0 * (x[a] + 0.5) / p->n[a] - 1.0;
+        const double t = 1.0 - pow(s, 18.0);
+        g *= t * t;
+    }
+    return g;
+}
+
 /* ---------------------------------------------------------------------------
  * Streaming with boundary conditions (push form of the streaming step of
  * Sec. 2.2): every post-collision population S_i(x) moves to x + xi_i.  If
@@ -205,7 +227,9 @@ int orc_equilibrium_field(const orc_params *p, const double *rho, const double *
  * opposite face; if it leaves through a wall face it is reflected back into
  * x as the opposite population (halfway bounce-back), with the moving-wall
  * correction of the moving bounce-back rule,
- *   f_{opp(i)}(x) = S_i(x) - 2 w_i rho_w (xi_i . u_w) / c_s^2 .
+ *   f_{opp(i)}(x) = S_i(x) - 2 w_i rho_w (xi_i . u_w) / c_s^2 ,
+ * u_w the sum of the velocities of the wall faces crossed, each times its
+ * profile factor at x (1 unless the face is smoothed).
  * ------------------------------------------------------------------------- */
 int orc_stream(const orc_params *p, const double *S, double *f)
 {
@@ -234,7 +258,8 @@ int orc_stream(const orc_params *p, const double *S, double *f)
                     t[a] = (t[a] + p->n[a]) % p->n[a];
                 } else {
                     solid = 1;
-                    for (int b = 0; b < 3; ++b) uw[b] += p->wall_u[face][b];
+                    const double g = wall_profile_factor(p, face, x);
+                    for (int b = 0; b < 3; ++b) uw[b] += g * p->wall_u[face][b];
                 }
             }
             const double Si = S[cell * q + i];
@@ -287,14 +312,43 @@ int orc_sensor(const orc_params *p, const double *f, double *s)
 }
 
 /* ---------------------------------------------------------------------------
+ * Relaxation time of a cell.  Plain BGK: tau.  With the Smagorinsky model
+ * (the subgrid model the paper adds to BGK at high Reynolds number, Sec. 4)
+ * the viscosity is c_s^2 (tau_e - 1/2) = c_s^2 (tau - 1/2) + C^2 |S|, with
+ * |S| = sqrt(2 S:S) and the strain rate read from the non-equilibrium
+ * momentum flux of the cell, Pi = sum_i xi_i xi_i (f_i - f^eq_i) =
+ * -2 rho c_s^2 tau_e S.  Then tau_e (tau_e - tau) = C^2 sqrt(2) |Pi| /
+ * (2 rho c_s^4), |Pi| = sqrt(Pi:Pi), whose positive root is taken.
+ * ------------------------------------------------------------------------- */
+static double relaxation_time(const orc_lattice *L, const orc_params *p, const double *fc, const double *feq,
+                              double rho)
+{
+    if (p->smagorinsky == 0.0) return p->tau;
+    double Pi[3][3] = {{0.0}};
+    for (int i = 0; i < L->q; ++i) {
+        const double fneq = fc[i] - feq[i];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) Pi[a][b] += L->c[i][a] * L->c[i][b] * fneq;
+    }
+    double pp = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) pp += Pi[a][b] * Pi[a][b];
+    const double C2 = p->smagorinsky * p->smagorinsky;
+    const double k = C2 * sqrt(2.0) * sqrt(pp) / (2.0 * rho * L->cs2 * L->cs2);
+    return 0.5 * (p->tau + sqrt(p->tau * p->tau + 4.0 * k));
+}
+
+/* ---------------------------------------------------------------------------
  * BGK collision (Eq. bgklb): f^out_i = f_i - (f_i - f^eq_i) / tau, plus Guo's
- * forcing term (1 - 1/(2 tau)) w_i [ (xi_i - u)/c_s^2 + (xi_i.u) xi_i / c_s^4 ].F
+ * forcing term (1 - 1/(2 tau)) w_i [ (xi_i - u)/c_s^2 + (xi_i.u) xi_i / c_s^4 ].F,
+ * tau the cell's relaxation time (relaxation_time).
  * ------------------------------------------------------------------------- */
 static void collide_cell(const orc_lattice *L, const orc_params *p, const double *fc, double *Sc)
 {
     double rho, u[3], feq[ORC_MAXQ];
     moments(L, fc, p->force, +1.0, &rho, u);
     equilibrium(L, rho, u, feq);
+    const double tau = relaxation_time(L, p, fc, feq, rho);
     const double cs2 = L->cs2;
     for (int i = 0; i < L->q; ++i) {
         double xu = 0.0;
@@ -302,8 +356,8 @@ static void collide_cell(const orc_lattice *L, const orc_params *p, const double
         double src = 0.0;
         for (int a = 0; a < 3; ++a)
             src += ((L->c[i][a] - u[a]) / cs2 + xu * L->c[i][a] / (cs2 * cs2)) * p->force[a];
-        src *= L->w[i] * (1.0 - 1.0 / (2.0 * p->tau));
-        Sc[i] = fc[i] - (fc[i] - feq[i]) / p->tau + src;
+        src *= L->w[i] * (1.0 - 1.0 / (2.0 * tau));
+        Sc[i] = fc[i] - (fc[i] - feq[i]) / tau + src;
     }
 }
 
