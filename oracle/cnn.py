@@ -95,22 +95,30 @@ def mse(y0, target):
     return float(np.mean(e * e)), 2.0 * e / e.size
 
 
-def forward(params, x):
+def _ident(a):
+    return a
+
+
+def forward(params, x, q=None):
     """Network forward: conv + ReLU on every layer but the last.  params is a
-    list of (w, b); returns the list of layer outputs (post-activation)."""
+    list of (w, b); returns the list of layer outputs (post-activation).
+    q, if given, rounds both operands of every convolution product (e.g.
+    bf16_round, the precision the matrix-core kernels multiply in)."""
+    q = q or _ident
     acts = []
     a = np.asarray(x, dtype=np.float64)
     for k, (w, b) in enumerate(params):
-        z = conv3d(a, w, b)
+        z = conv3d(q(a), q(w), b)
         a = relu(z) if k + 1 < len(params) else z
         acts.append(a)
     return acts
 
 
-def loss_and_grads(params, x, target):
+def loss_and_grads(params, x, target, q=None):
     """MSE of the last layer's channel 0 against target (n, d, h, w) and the
-    gradient of every (w, b) by backpropagation."""
-    acts = forward(params, x)
+    gradient of every (w, b) by backpropagation; q as in forward."""
+    q = q or _ident
+    acts = forward(params, x, q)
     loss, g0 = mse(acts[-1][..., 0], target)
     g = np.zeros_like(acts[-1])
     g[..., 0] = g0
@@ -119,9 +127,9 @@ def loss_and_grads(params, x, target):
         if k + 1 < len(params):
             g = g * (acts[k] > 0.0)
         inp = x if k == 0 else acts[k - 1]
-        grads[k] = conv3d_wgrad(inp, g)
+        grads[k] = conv3d_wgrad(q(inp), q(g))
         if k > 0:
-            g = conv3d_dgrad(g, params[k][0])
+            g = conv3d_dgrad(q(g), q(params[k][0]))
     return loss, grads
 
 

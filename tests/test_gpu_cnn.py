@@ -184,13 +184,13 @@ def test_network_gradients_against_oracle(env):
     fall on opposite sides of a rounding boundary and differ by one bfloat16
     ulp (2^-8 relative); these differences pass through the later layers.
     The bound of 5e-3 on the relative L2 error of each gradient is about 3x
-    the largest measured on MI355X (1.4e-3, a bias gradient, whose sum
+    the largest measured on MI355X (1.8e-3, a bias gradient, whose sum
     cancels).  Against plain float64 the gradients keep their direction
     (cosine > 0.99)."""
     torch, cnn = env
     from paper_1507_06767_amd.predictor import FlagPredictor
     print("\n[case] network gradients 2x16^3", flush=True)
-    net = FlagPredictor(seed=3)
+    net = FlagPredictor(channels=(5, 16, 16, 16, 1), seed=3)
     rng = np.random.default_rng(9)
     shape = (2, 16, 16, 16)
     x = rng.standard_normal(shape + (5,)).astype(np.float32)
