@@ -59,7 +59,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 1u
+#define LBM_ABI_VERSION 2u
 
 typedef int32_t lbm_status;
 enum {
@@ -84,6 +84,8 @@ enum { LBM_BUF_F_A = 0, LBM_BUF_F_B = 1, LBM_BUF_BLOCK_MAX = 2,  /* lbm_desc.buf
 enum { LBM_FLAG_COARSEN = -1, LBM_FLAG_KEEP = 0, LBM_FLAG_REFINE = 1, LBM_FLAG_NONFINITE = 2 };
 
 typedef struct lbm_blocks lbm_blocks;   /* opaque handle */
+
+enum { LBM_PROFILE_UNIFORM = 0, LBM_PROFILE_SMOOTH = 1 };
 
 typedef struct {
     uint32_t abi_version;   /* LBM_ABI_VERSION */
@@ -118,6 +120,17 @@ typedef struct {
     double theta_refine;    /* flag REFINE iff block max > theta_refine */
     double theta_coarsen;   /* flag COARSEN iff block max < theta_coarsen
                                (<= theta_refine) */
+    double smagorinsky;     /* Smagorinsky constant C in [0, 1] (0: plain BGK).  The
+                               subgrid model the paper adds to BGK at high Reynolds
+                               number (Sec. 4, C = 0.14): per cell the relaxation time
+                               tau_e = (tau + sqrt(tau^2 + 18 sqrt(2) C^2 |Pi| / rho)) / 2,
+                               Pi = sum_i xi_i xi_i (f_i - f^eq_i), i.e. the viscosity
+                               c_s^2 (tau - 1/2) plus C^2 |S|, |S| = sqrt(2 S:S) */
+    int32_t wall_profile[6];  /* per face: LBM_PROFILE_UNIFORM, or LBM_PROFILE_SMOOTH
+                               for the smoothed lid of the 3D cavity (Sec. 5.1): the
+                               face's wall_u times prod over its in-plane axes of
+                               (1 - s^18)^2, s = (2 x + 1 - n) / n in (-1, 1) at the
+                               fluid cell's centre (ignored on periodic faces) */
     void *buf[LBM_NBUF];    /* caller-owned device buffers, see lbm_required_bytes();
                                F_A and F_B must be 256-byte aligned; no two overlap */
     size_t buf_bytes[LBM_NBUF];  /* their sizes in bytes, >= the required sizes */

@@ -15,13 +15,14 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
-LBM_ABI_VERSION = 1
+LBM_ABI_VERSION = 2
 LBM_OK, LBM_EINVAL, LBM_ENOTSUP, LBM_EHIP, LBM_ESTATE, LBM_ENONFINITE = 0, -1, -2, -3, -4, -5
 LBM_D2Q9, LBM_D3Q19 = 9, 19
 LBM_F64, LBM_F32, LBM_F32_SHIFTED, LBM_F16_SHIFTED, LBM_BF16_SHIFTED = 0, 1, 2, 3, 4
 LBM_F16_SHIFTED_SR, LBM_BF16_SHIFTED_SR = 5, 6
 LBM_SENSOR_L2, LBM_SENSOR_KKN = 0, 1
 LBM_BC_PERIODIC, LBM_BC_WALL = 0, 1
+LBM_PROFILE_UNIFORM, LBM_PROFILE_SMOOTH = 0, 1
 LBM_NBUF = 5
 STATUS_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOTSUP", -3: "LBM_EHIP",
                 -4: "LBM_ESTATE", -5: "LBM_ENONFINITE"}
@@ -48,6 +49,8 @@ class lbm_desc(ctypes.Structure):
         ("force", ctypes.c_double * 3),
         ("theta_refine", ctypes.c_double),
         ("theta_coarsen", ctypes.c_double),
+        ("smagorinsky", ctypes.c_double),
+        ("wall_profile", ctypes.c_int32 * 6),
         ("buf", ctypes.c_void_p * LBM_NBUF),
         ("buf_bytes", ctypes.c_size_t * LBM_NBUF),
         ("stream", ctypes.c_void_p),
@@ -128,7 +131,7 @@ def _counts(desc: lbm_desc):
 
 def make_desc(lattice, extent, face_bc, tau, storage=LBM_F32, sensor_kind=LBM_SENSOR_L2,
               wall_u=None, rho0=1.0, force=(0.0, 0.0, 0.0), theta_refine=1e-3,
-              theta_coarsen=5e-4, block=None) -> lbm_desc:
+              theta_coarsen=5e-4, block=None, smagorinsky=0.0, wall_profile=None) -> lbm_desc:
     """A descriptor with the buffers left empty."""
     d = lbm_desc()
     d.abi_version = LBM_ABI_VERSION
@@ -143,6 +146,9 @@ def make_desc(lattice, extent, face_bc, tau, storage=LBM_F32, sensor_kind=LBM_SE
             d.wall_u[f][a] = float(wall_u[f][a]) if wall_u is not None else 0.0
     d.tau, d.rho0 = float(tau), float(rho0)
     d.theta_refine, d.theta_coarsen = float(theta_refine), float(theta_coarsen)
+    d.smagorinsky = float(smagorinsky)
+    for f in range(6):
+        d.wall_profile[f] = int(wall_profile[f]) if wall_profile is not None else LBM_PROFILE_UNIFORM
     return d
 
 

@@ -1,7 +1,7 @@
 // launch.hpp -- host-side launch of the step kernels.
 //
-// The kernel variants (lattice x storage x sensor kind x force x tile width x
-// streaming scheme) are instantiated in one translation unit per storage
+// The kernel variants (lattice x storage x sensor kind x collision model x
+// tile width x streaming scheme) are instantiated in one translation unit per storage
 // family (step_f64.hip, step_f32.hip, step_f16.hip, step_bf16.hip) so that
 // they compile in parallel; lbm.hip only sees the declaration.
 #pragma once
@@ -19,6 +19,7 @@ struct LaunchCfg {
     bool sensor;       // evaluate sensor, block maxima and flags in this step
     int sensor_kind;   // kSensorL2 or kSensorKKn
     bool force;        // body force present
+    bool smag;         // Smagorinsky subgrid model on
 };
 
 // 3D float64 marches over z inside a workgroup (a 64-bit block maximum
@@ -34,25 +35,30 @@ template <int Q, typename T, typename C, bool SH>
 void launch_step_kernel(const StepArgs<C> &a, const LaunchCfg &c);
 
 #ifdef LBM_LAUNCH_DEFINITIONS
-template <bool ZM, int Q, typename T, typename C, bool SH, bool SENS, int SK, bool FORCE, int BX, int SCH>
+template <bool ZM, int Q, typename T, typename C, bool SH, bool SENS, int SK, int MODEL, int BX, int SCH>
 void launch_one(hipStream_t st, const StepArgs<C> &a) {
     const dim3 g(a.ntiles), b(BX, kTileY);
-    if constexpr (ZM) hipLaunchKernelGGL((step_zmarch<Q, T, C, SH, SENS, SK, FORCE, BX>), g, b, 0, st, a);
-    else hipLaunchKernelGGL((step_cells<Q, T, C, SH, SENS, SK, FORCE, BX, SCH>), g, b, 0, st, a);
+    if constexpr (ZM) hipLaunchKernelGGL((step_zmarch<Q, T, C, SH, SENS, SK, MODEL, BX>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((step_cells<Q, T, C, SH, SENS, SK, MODEL, BX, SCH>), g, b, 0, st, a);
+}
+
+template <bool ZM, int Q, typename T, typename C, bool SH, bool SENS, int SK, int BX, int SCH>
+void launch_model(const StepArgs<C> &a, const LaunchCfg &c) {
+    switch ((c.force ? kModelForce : 0) | (c.smag ? kModelSmag : 0)) {
+        case kModelForce: launch_one<ZM, Q, T, C, SH, SENS, SK, kModelForce, BX, SCH>(c.stream, a); break;
+        case kModelSmag: launch_one<ZM, Q, T, C, SH, SENS, SK, kModelSmag, BX, SCH>(c.stream, a); break;
+        case kModelForce | kModelSmag:
+            launch_one<ZM, Q, T, C, SH, SENS, SK, kModelForce | kModelSmag, BX, SCH>(c.stream, a);
+            break;
+        default: launch_one<ZM, Q, T, C, SH, SENS, SK, 0, BX, SCH>(c.stream, a); break;
+    }
 }
 
 template <bool ZM, int Q, typename T, typename C, bool SH, int BX, int SCH>
 void launch_sk(const StepArgs<C> &a, const LaunchCfg &c) {
-    if (!c.sensor) {
-        if (c.force) launch_one<ZM, Q, T, C, SH, false, kSensorL2, true, BX, SCH>(c.stream, a);
-        else launch_one<ZM, Q, T, C, SH, false, kSensorL2, false, BX, SCH>(c.stream, a);
-    } else if (c.sensor_kind == kSensorL2) {
-        if (c.force) launch_one<ZM, Q, T, C, SH, true, kSensorL2, true, BX, SCH>(c.stream, a);
-        else launch_one<ZM, Q, T, C, SH, true, kSensorL2, false, BX, SCH>(c.stream, a);
-    } else {
-        if (c.force) launch_one<ZM, Q, T, C, SH, true, kSensorKKn, true, BX, SCH>(c.stream, a);
-        else launch_one<ZM, Q, T, C, SH, true, kSensorKKn, false, BX, SCH>(c.stream, a);
-    }
+    if (!c.sensor) launch_model<ZM, Q, T, C, SH, false, kSensorL2, BX, SCH>(a, c);
+    else if (c.sensor_kind == kSensorL2) launch_model<ZM, Q, T, C, SH, true, kSensorL2, BX, SCH>(a, c);
+    else launch_model<ZM, Q, T, C, SH, true, kSensorKKn, BX, SCH>(a, c);
 }
 
 template <int Q, typename T, typename C, bool SH, int BX>

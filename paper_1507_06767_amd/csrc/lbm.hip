@@ -133,6 +133,11 @@ lbm_status check_desc(const lbm_desc *d, Layout *L) {
     if (dim == 2 && (d->force[2] != 0.0)) return fail(LBM_EINVAL, "D2Q9: force[2] must be 0");
     if (!is_fin(d->theta_refine) || !is_fin(d->theta_coarsen) || d->theta_coarsen > d->theta_refine)
         return fail(LBM_EINVAL, "thresholds must be finite with theta_coarsen <= theta_refine");
+    if (!is_fin(d->smagorinsky) || d->smagorinsky < 0.0 || d->smagorinsky > 1.0)
+        return fail(LBM_EINVAL, "smagorinsky = %g must be in [0, 1]", d->smagorinsky);
+    for (int f = 0; f < 6; ++f)
+        if (d->wall_profile[f] != LBM_PROFILE_UNIFORM && d->wall_profile[f] != LBM_PROFILE_SMOOTH)
+            return fail(LBM_EINVAL, "wall_profile[%d] = %d", f, d->wall_profile[f]);
 
     L->q = d->lattice;
     L->dim = dim;
@@ -273,6 +278,9 @@ StepArgs<C> step_args(lbm_blocks *h, const void *src, void *dst, bool zmarch, in
     a.nbx = h->L.nb[0];
     a.nby = h->L.nb[1];
     a.wall = h->wall_mask;
+    a.profile = 0;
+    for (int f = 0; f < 6; ++f)
+        if (d.face_bc[f] == LBM_BC_WALL && d.wall_profile[f] == LBM_PROFILE_SMOOTH) a.profile |= 1u << f;
     static_for<0, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         using V = Vel<Q, i>;
@@ -284,6 +292,8 @@ StepArgs<C> step_args(lbm_blocks *h, const void *src, void *dst, bool zmarch, in
     });
     a.omega = (C)(1.0 / d.tau);
     a.guo = (C)(1.0 - 0.5 / d.tau);
+    a.tau0 = (C)d.tau;
+    a.smag = (C)(18.0 * std::sqrt(2.0) * d.smagorinsky * d.smagorinsky);
     a.rho0 = (C)d.rho0;
     for (int c = 0; c < 3; ++c) a.F[c] = (C)d.force[c];
     a.theta_r = d.theta_refine;
@@ -338,6 +348,7 @@ void launch_step(lbm_blocks *h, bool sens) {
     c.sensor = sens;
     c.sensor_kind = h->d.sensor_kind;
     c.force = h->has_force;
+    c.smag = h->d.smagorinsky > 0.0;
     constexpr bool zm = uses_zmarch<Q, C>();
     c.tile_x = zm ? 64 : h->tile_x;
     const StepArgs<C> a = step_args<Q, C>(h, src, dst, zm, c.tile_x);

@@ -76,6 +76,8 @@ constexpr int kSensorKKn = 1;
 constexpr int kPingPong = 0;   // streaming schemes, see above
 constexpr int kStream = 1;
 constexpr int kLocal = 2;
+constexpr int kModelForce = 1;   // collision-model bits: Guo body force
+constexpr int kModelSmag = 2;    //                       Smagorinsky subgrid model
 
 template <typename C>
 struct StepArgs {
@@ -87,9 +89,12 @@ struct StepArgs {
     int nbx, nby;           // sensor blocks along x, y
     uint32_t wall;          // bit f set: face f (-x,+x,-y,+y,-z,+z) is a wall
     C wcorr[19][6];         // 6 w_i rho0 (xi_i . u_face): moving-wall term per face
+    uint32_t profile;       // bit f set: face f's velocity is smoothed (wall_factor)
     C shift[19];            // w_i rho0 rounded to C
     C omega;                // 1 / tau
     C guo;                  // 1 - 1 / (2 tau)
+    C tau0;                 // tau (Smagorinsky: the molecular part)
+    C smag;                 // 18 sqrt(2) C_smag^2 (Smagorinsky closed form)
     C rho0;
     C F[3];                 // body-force density
     double theta_r, theta_c;
@@ -176,10 +181,32 @@ __device__ __forceinline__ Geo make_geo(const StepArgs<C> &a, int x, int y, int 
     return g;
 }
 
+// Factor of face F's wall velocity at the cell: 1, or for a smoothed face
+// (the lid profile of Sec. 5.1) the product over the face's in-plane axes of
+// (1 - s^18)^2, s = (2 x + 1 - n) / n the cell centre mapped to (-1, 1).  An
+// axis of one cell has s = 0.
+template <int F, typename C>
+__device__ __forceinline__ C wall_factor(const StepArgs<C> &a, const Geo &g) {
+    if (!((a.profile >> F) & 1u)) return C(1);
+    const int coord[3] = {g.x, g.y, g.z};
+    const int ext[3] = {a.nx, a.ny, a.nz};
+    C r = C(1);
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        if (ax == F / 2) continue;
+        const C s = C(2 * coord[ax] + 1 - ext[ax]) / C(ext[ax]);
+        const C s2 = s * s, s4 = s2 * s2, s8 = s4 * s4;
+        const C t = C(1) - s8 * s8 * s2;
+        r *= t * t;
+    }
+    return r;
+}
+
 // The pull link of population I at the cell: its source cell x - xi_I (after
 // periodic wrap), whether the source lies beyond a wall (then the link is
 // bounced), and the moving-wall term 6 w_I rho0 (xi_I . u_w) summed over the
-// wall faces crossed (0 off walls).
+// wall faces crossed, each face's velocity times its wall_factor (0 off
+// walls).
 template <typename C>
 struct Link {
     bool wall;
@@ -196,12 +223,12 @@ __device__ __forceinline__ Link<C> link(const StepArgs<C> &a, const Geo &g) {
     Link<C> l;
     l.wall = false;
     l.corr = C(0);
-    if constexpr (V::x > 0) { l.wall = l.wall || g.wxm; l.corr += g.wxm ? a.wcorr[I][0] : C(0); }
-    if constexpr (V::x < 0) { l.wall = l.wall || g.wxp; l.corr += g.wxp ? a.wcorr[I][1] : C(0); }
-    if constexpr (V::y > 0) { l.wall = l.wall || g.wym; l.corr += g.wym ? a.wcorr[I][2] : C(0); }
-    if constexpr (V::y < 0) { l.wall = l.wall || g.wyp; l.corr += g.wyp ? a.wcorr[I][3] : C(0); }
-    if constexpr (V::z > 0) { l.wall = l.wall || g.wzm; l.corr += g.wzm ? a.wcorr[I][4] : C(0); }
-    if constexpr (V::z < 0) { l.wall = l.wall || g.wzp; l.corr += g.wzp ? a.wcorr[I][5] : C(0); }
+    if constexpr (V::x > 0) { l.wall = l.wall || g.wxm; if (g.wxm) l.corr += a.wcorr[I][0] * wall_factor<0>(a, g); }
+    if constexpr (V::x < 0) { l.wall = l.wall || g.wxp; if (g.wxp) l.corr += a.wcorr[I][1] * wall_factor<1>(a, g); }
+    if constexpr (V::y > 0) { l.wall = l.wall || g.wym; if (g.wym) l.corr += a.wcorr[I][2] * wall_factor<2>(a, g); }
+    if constexpr (V::y < 0) { l.wall = l.wall || g.wyp; if (g.wyp) l.corr += a.wcorr[I][3] * wall_factor<3>(a, g); }
+    if constexpr (V::z > 0) { l.wall = l.wall || g.wzm; if (g.wzm) l.corr += a.wcorr[I][4] * wall_factor<4>(a, g); }
+    if constexpr (V::z < 0) { l.wall = l.wall || g.wzp; if (g.wzp) l.corr += a.wcorr[I][5] * wall_factor<5>(a, g); }
     l.src = (uint32_t)((sz * a.ny + sy) * a.nx + sx);
     return l;
 }
@@ -347,8 +374,10 @@ __device__ __forceinline__ void store_pop(const StepArgs<C> &a, const Geo &g, C 
 // Moments, equilibrium, sensor, BGK + Guo collision and the store of one
 // cell.  Returns the cell's sensor value: ||f^neq||^2 / ||f^eq||^2 (L2; the
 // square root is taken once per block) or K_Kn.
-template <int Q, typename T, typename C, bool SHIFTED, bool SENSOR, int SKIND, bool FORCE, int SCHEME>
+template <int Q, typename T, typename C, bool SHIFTED, bool SENSOR, int SKIND, int MODEL, int SCHEME>
 __device__ __forceinline__ C collide_store(const StepArgs<C> &a, const Geo &g, const C (&d)[Q]) {
+    constexpr bool FORCE = (MODEL & kModelForce) != 0;
+    constexpr bool SMAG = (MODEL & kModelSmag) != 0;
     // moments (Eqs. rho and u), Guo's half-force shift
     C drho = C(0), mx = C(0), my = C(0), mz = C(0);
     static_for<0, Q>([&](auto ic) {
@@ -372,6 +401,32 @@ __device__ __forceinline__ C collide_store(const StepArgs<C> &a, const Geo &g, c
     C uF = C(0);
     if constexpr (FORCE) uF = u[0] * a.F[0] + u[1] * a.F[1] + u[2] * a.F[2];
 
+    // Smagorinsky (the subgrid model of Sec. 4): the cell's relaxation time
+    // tau_e = (tau + sqrt(tau^2 + 18 sqrt(2) C^2 |Pi| / rho)) / 2 from the
+    // non-equilibrium momentum flux Pi = sum_i xi_i xi_i f^neq_i.
+    C omega = a.omega, guo = a.guo;
+    if constexpr (SMAG) {
+        C pxx = C(0), pyy = C(0), pzz = C(0), pxy = C(0), pxz = C(0), pyz = C(0);
+        static_for<0, Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            using V = Vel<Q, i>;
+            const C cu = dot_c<Q, i>(u);
+            const C cj = dot_c<Q, i>(j);
+            const C p2 = C(4.5) * cu * cu - C(1.5) * usq;
+            const C fneq = d[i] - wmul<C, V::w>(drho + C(3) * cj + (a.rho0 * p2 + drho * p2));
+            if constexpr (V::x != 0) pxx += fneq;
+            if constexpr (V::y != 0) pyy += fneq;
+            if constexpr (V::z != 0) pzz += fneq;
+            if constexpr (V::x * V::y != 0) pxy += C(V::x * V::y) * fneq;
+            if constexpr (V::x * V::z != 0) pxz += C(V::x * V::z) * fneq;
+            if constexpr (V::y * V::z != 0) pyz += C(V::y * V::z) * fneq;
+        });
+        const C pp = pxx * pxx + pyy * pyy + pzz * pzz + C(2) * (pxy * pxy + pxz * pxz + pyz * pyz);
+        const C tau_e = C(0.5) * (a.tau0 + sqrt(a.tau0 * a.tau0 + a.smag * sqrt(pp) * inv_rho));
+        omega = C(1) / tau_e;
+        guo = C(1) - C(0.5) * omega;
+    }
+
     C num = C(0), den = C(0), kkn = C(0);
     const uint32_t ckey = Storage<T>::sr ? cell_key(g.cell, a.step) : 0u;
     static_for<0, Q>([&](auto ic) {
@@ -394,13 +449,13 @@ __device__ __forceinline__ C collide_store(const StepArgs<C> &a, const Geo &g, c
                 kkn += fabs(fneq / feq);
             }
         }
-        C out = d[i] - a.omega * fneq;
+        C out = d[i] - omega * fneq;
         if constexpr (FORCE) {
             C cF = C(0);
             if constexpr (V::x != 0) cF += C(V::x) * a.F[0];
             if constexpr (V::y != 0) cF += C(V::y) * a.F[1];
             if constexpr (V::z != 0) cF += C(V::z) * a.F[2];
-            out += a.guo * wmul<C, V::w>(C(3) * (cF - uF) + C(9) * cu * cF);
+            out += guo * wmul<C, V::w>(C(3) * (cF - uF) + C(9) * cu * cF);
         }
         if constexpr (!SHIFTED) out += a.shift[i];
         store_pop<Q, i, T, C, SCHEME>(a, g, out, ckey);
@@ -457,7 +512,7 @@ __device__ __forceinline__ void accumulate(const StepArgs<C> &a, uint32_t cell, 
     if (a.avg) a.avg[cell] += finish<SKIND>(s);
 }
 
-template <int Q, typename T, typename C, bool SHIFTED, bool SENSOR, int SKIND, bool FORCE, int BX, int SCHEME>
+template <int Q, typename T, typename C, bool SHIFTED, bool SENSOR, int SKIND, int MODEL, int BX, int SCHEME>
 __global__ __launch_bounds__(BX *kTileY) void step_cells(const StepArgs<C> a) {
     constexpr int D = Lattice<Q>::D;
     static_assert(BX % kBlockEdge == 0, "tile width must hold whole blocks");
@@ -476,7 +531,7 @@ __global__ __launch_bounds__(BX *kTileY) void step_cells(const StepArgs<C> a) {
         const Geo g = make_geo<D>(a, x, y, z);
         C d[Q];
         load_cell<Q, T, C, SHIFTED, SCHEME>(a, g, d);
-        s = collide_store<Q, T, C, SHIFTED, SENSOR, SKIND, FORCE, SCHEME>(a, g, d);
+        s = collide_store<Q, T, C, SHIFTED, SENSOR, SKIND, MODEL, SCHEME>(a, g, d);
         if constexpr (SENSOR) accumulate<SKIND>(a, g.cell, s);
     }
     if constexpr (SENSOR) {
@@ -510,7 +565,7 @@ __global__ __launch_bounds__(BX *kTileY) void step_cells(const StepArgs<C> a) {
     }
 }
 
-template <int Q, typename T, typename C, bool SHIFTED, bool SENSOR, int SKIND, bool FORCE, int BX>
+template <int Q, typename T, typename C, bool SHIFTED, bool SENSOR, int SKIND, int MODEL, int BX>
 __global__ __launch_bounds__(BX *kTileY) void step_zmarch(const StepArgs<C> a) {
     static_assert(Lattice<Q>::D == 3, "z-march is for 3D grids");
     const int tile = xcd_tile(blockIdx.x, a.ntiles);
@@ -530,7 +585,7 @@ __global__ __launch_bounds__(BX *kTileY) void step_zmarch(const StepArgs<C> a) {
             const Geo g = make_geo<3>(a, x, y, z);
             C d[Q];
             load_cell<Q, T, C, SHIFTED, kPingPong>(a, g, d);
-            const C s = collide_store<Q, T, C, SHIFTED, SENSOR, SKIND, FORCE, kPingPong>(a, g, d);
+            const C s = collide_store<Q, T, C, SHIFTED, SENSOR, SKIND, MODEL, kPingPong>(a, g, d);
             if constexpr (SENSOR) {
                 m = nan_max(m, s);
                 accumulate<SKIND>(a, g.cell, s);

@@ -1,0 +1,106 @@
+"""Parity of the model options with the FP64 oracle: the Smagorinsky subgrid
+model (Sec. 4) and the smoothed lid velocity (Sec. 5.1), alone, together and
+with a body force, on both streaming schemes.  Tolerances are those of the
+BGK parity tests (float64: 1e-12 relative fields and 1e-11 relative block
+maxima; shifted float32: 1e-5 and 2e-5)."""
+import numpy as np
+import pytest
+
+import lbm_inputs
+from lbm_inputs import PERIODIC, WALL
+
+pytestmark = pytest.mark.gpu
+
+EPS_S = {0: 1e-11, 2: 2e-5}
+U_TOL = {0: 1e-12, 2: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1507_06767_amd as lbm
+    return lbm
+
+
+@pytest.fixture(params=["inplace", "pingpong"])
+def scheme(request, monkeypatch):
+    monkeypatch.setenv("LBM_STREAMING", request.param)
+    return request.param
+
+
+def _wall(lid, face=3, comp=0):
+    w = [[0.0] * 3 for _ in range(6)]
+    w[face][comp] = lid
+    return w
+
+
+_LID = (0, 0, 0, 1, 0, 0)
+_CASES = [
+    # name, q, n, bc, wall_u, tau, force, smagorinsky, profile, init
+    ("cav3d_smag", 19, (36, 20, 17), (WALL,) * 6, _wall(0.08), 0.503, (0, 0, 0), 0.14, None, "rest"),
+    ("cav3d_lid", 19, (36, 20, 17), (WALL,) * 6, _wall(0.08), 0.55, (0, 0, 0), 0.0, _LID, "rest"),
+    ("cav3d_smag_lid", 19, (33, 24, 16), (WALL,) * 6, _wall(0.1), 0.502, (0, 0, 0), 0.14, _LID, "rest"),
+    ("box3d_smag_force", 19, (20, 17, 18), (PERIODIC,) * 6, _wall(0.0), 0.51, (2e-6, 0, -1e-6), 0.2, None,
+     "perturbed"),
+    ("cav2d_smag_lid", 9, (70, 37, 1), (WALL, WALL, WALL, WALL, PERIODIC, PERIODIC), _wall(0.1), 0.502,
+     (0, 0, 0), 0.14, _LID, "rest"),
+    ("chan2d_smag_force", 9, (40, 33, 1), (PERIODIC, PERIODIC, WALL, WALL, PERIODIC, PERIODIC), _wall(0.0),
+     0.505, (1e-5, 0, 0), 0.14, None, "perturbed"),
+]
+
+
+@pytest.mark.parametrize("storage", [0, 2], ids=["f64", "f32s"])
+@pytest.mark.parametrize("case", _CASES, ids=[c[0] for c in _CASES])
+def test_model_options(lbm, orc, case, storage, scheme):
+    name, q, n, bc, wall_u, tau, force, smag, prof, init = case
+    print(f"\n[case] {name} storage={storage} {scheme}", flush=True)
+    prof = prof or (0,) * 6
+    desc = lbm.make_desc(q, n, bc, tau, storage=storage, wall_u=wall_u, force=force, smagorinsky=smag,
+                         wall_profile=prof)
+    G = orc.Grid(q=q, n=n, bc=bc, wall_u=wall_u, tau=tau, force=force, smagorinsky=smag, wall_profile=prof)
+    u0 = lbm_inputs.velocity_perturbation(n, 0.03, seed=5, dims=2 if q == 9 else 3) if init == "perturbed" else None
+    S0 = G.equilibrium_state(u=u0)
+    blk = lbm.Blocks(desc)
+    if u0 is not None:
+        blk.set_equilibrium(u=u0)
+    steps, every = 60, 30
+    S_ref, hist = G.run(S0, 0, steps, every)
+    worst = 0.0
+    for k, bm_ref, fl_ref in hist:
+        blk.step_n(every, every)
+        bm, fl, kk, bad = blk.sensor_flags()
+        assert kk == k and not bad
+        err = np.abs(bm - bm_ref) / np.maximum(bm_ref, 1e-3)
+        worst = max(worst, float(err.max()))
+        near = (np.abs(bm_ref - 1e-3) <= EPS_S[storage] * 1e-3) | (np.abs(bm_ref - 5e-4) <= EPS_S[storage] * 5e-4)
+        assert not ((fl != fl_ref) & ~near).any()
+    rho, u = blk.macros()
+    rho_r, u_r = G.macros(S_ref)
+    eu = np.linalg.norm(u - u_r) / np.linalg.norm(u_r)
+    er = np.linalg.norm(rho - rho_r) / np.linalg.norm(rho_r)
+    print(f"{name}: u rel err {eu:.2e}, rho rel err {er:.2e}, block max rel err {worst:.2e}")
+    assert worst <= EPS_S[storage] and eu <= U_TOL[storage] and er <= U_TOL[storage]
+    if storage == 0:
+        assert np.abs(blk.populations() - S_ref).max() < 1e-13
+    blk.close()
+
+
+def test_smagorinsky_stabilises_the_predictor_cavity(lbm):
+    """The 128^3 cavity at Re 4500 and lid 0.035 (tau = 0.503) diverges with
+    plain BGK within 2000 steps; with the Smagorinsky model (C = 0.14) it
+    stays finite.  This is the setting the flag predictor's training runs
+    use."""
+    w = lbm_inputs.cavity3d(n=128, lid=0.035, re=4500.0)
+    st, tau = lbm.lbm_tau_from_reynolds(w.lid_speed, w.n_across, w.reynolds)
+    out = {}
+    for smag in (0.0, 0.14):
+        print(f"\n[case] cavity128 Re 4500 smagorinsky={smag}", flush=True)
+        desc = lbm.make_desc(19, w.n, w.bc, tau, storage=lbm.LBM_F32_SHIFTED, wall_u=w.wall_u, smagorinsky=smag)
+        blk = lbm.Blocks(desc)
+        blk.step_n(2000, 500)
+        _, _, _, bad = blk.sensor_flags()
+        out[smag] = bad
+        blk.close()
+    print(f"non-finite: BGK {out[0.0]}, Smagorinsky {out[0.14]}")
+    assert out[0.0] and not out[0.14]
