@@ -4,14 +4,14 @@ The sensor's block maxima M_b (Sec. 3.2, blocks of Sec. 3.4) say where the
 mesh must be fine now; regridding every so many steps wants to know where it
 must be fine by the next regrid.  ``FlagPredictor`` is a small 3D CNN over
 the block grid that predicts log10 M_b `horizon` steps ahead from the
-per-block means of (rho - rho0, u) and log10 M_b now.  It predicts the change
-of log10 M_b, so "no change" (reusing the current flags) is what an untrained
-network returns.
+per-block means of (rho - rho0, u) and log10 M_b now and one horizon earlier
+(the sensor's recent trend).  It predicts the change of log10 M_b, so "no
+change" (reusing the current flags) is what an untrained network returns.
 
 Every product runs in the matrix-core kernels of liblbm.so (bindings in
 ``cnn``): forward, data and weight gradients, ReLU backward, the loss and
 Adam.  Torch provides device memory and the stream; numpy only marshals the
-small per-block feature arrays (4096 blocks x 5 values at 128^3).
+small per-block feature arrays (4096 blocks x 6 values at 128^3).
 """
 from __future__ import annotations
 
@@ -36,9 +36,14 @@ def log_sensor(bm):
     return np.log10(np.maximum(np.asarray(bm, dtype=np.float64), LOG_FLOOR))
 
 
-def features(means, bm):
-    """Raw per-block features [nbz, nby, nbx, 5]: (rho - rho0, u, log10 M)."""
-    return np.concatenate([np.asarray(means, dtype=np.float64), log_sensor(bm)[..., None]], axis=-1)
+def features(means, bm, bm_prev=None):
+    """Raw per-block features [nbz, nby, nbx, 5 or 6]: (rho - rho0, u,
+    [log10 M one horizon earlier,] log10 M); log10 M now is the last."""
+    parts = [np.asarray(means, dtype=np.float64)]
+    if bm_prev is not None:
+        parts.append(log_sensor(bm_prev)[..., None])
+    parts.append(log_sensor(bm)[..., None])
+    return np.concatenate(parts, axis=-1)
 
 
 @dataclass
@@ -79,7 +84,7 @@ class _Layer:
 class FlagPredictor:
     """channels: (input, hidden..., 1); 3x3x3 convolutions, ReLU between."""
 
-    def __init__(self, channels=(5, 16, 16, 16, 1), seed=0, device="cuda", stream=None):
+    def __init__(self, channels=(6, 16, 16, 16, 1), seed=0, device="cuda", stream=None):
         self.device = torch.device(device)
         self.stream = stream
         rng = np.random.default_rng(seed)
@@ -182,7 +187,7 @@ class FlagPredictor:
 
     # -- the flag predictor ------------------------------------------------------
     def fit(self, raw, target_log, iters=1500, batch=8, lr=2e-3, seed=0, log_every=0):
-        """Trains on raw features [S, nbz, nby, nbx, 5] to predict
+        """Trains on raw features [S, nbz, nby, nbx, C0] to predict
         target_log [S, nbz, nby, nbx] = log10 M_b at the horizon.  The network
         learns target - log10 M_b(now).  Returns the loss history."""
         self.normalizer = Normalizer.fit(raw)
@@ -200,32 +205,41 @@ class FlagPredictor:
         return hist
 
     def predict_log(self, raw):
-        """Predicted log10 M_b at the horizon for raw features [S, ..., 5]."""
+        """Predicted log10 M_b at the horizon for raw features [S, ..., C0]."""
         if self.normalizer is None:
             raise RuntimeError("the predictor has not been fitted")
         return raw[..., -1] + self.predict_raw(self.normalizer(raw))
 
 
-def snapshot_run(Blocks, desc, snapshots, horizon, warm=0):
+def snapshot_run(Blocks, desc, snapshots, horizon, warm, history=True):
     """Runs one grid and records (raw features at t, log10 M_b at t + horizon)
-    for t = warm + horizon * j, j < snapshots.  Returns (raw, target_log) or
-    None if the run goes non-finite."""
+    for t = warm + horizon * j, j < snapshots.  With history the features
+    hold log10 M_b at t - horizon too (warm >= 2 horizon; else warm >=
+    horizon).  Returns (raw, target_log) or None if the run goes non-finite."""
+    if warm < (2 * horizon if history else horizon):
+        raise ValueError("warm must leave room for the sensor history")
     blk = Blocks(desc)
     try:
         raw, tgt = [], []
-        if warm:
-            blk.step_n(warm - 1, 0)
+        start = warm - (horizon if history else 0)
+        blk.step_n(start - 1, 0)
         blk.step_n(1, 1)
         bm, _, _, bad = blk.sensor_flags()
-        cur = features(blk.block_means(), bm)
-        for _ in range(snapshots):
+        prev = None
+        if history:
+            prev = bm
             blk.step_n(horizon, horizon)
             bm, _, _, bad = blk.sensor_flags()
+        cur = features(blk.block_means(), bm, prev)
+        for _ in range(snapshots):
+            blk.step_n(horizon, horizon)
+            nxt, _, _, bad = blk.sensor_flags()
             if bad or not np.isfinite(cur).all():
                 return None
             raw.append(cur)
-            tgt.append(log_sensor(bm))
-            cur = features(blk.block_means(), bm)
+            tgt.append(log_sensor(nxt))
+            cur = features(blk.block_means(), nxt, bm if history else None)
+            bm = nxt
         return np.stack(raw), np.stack(tgt)
     finally:
         blk.close()
