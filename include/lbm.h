@@ -39,6 +39,8 @@
  *          6 (0,0,-1) 7 (1,1,0) 8 (-1,-1,0) 9 (1,-1,0) 10 (-1,1,0)
  *          11 (1,0,1) 12 (-1,0,-1) 13 (1,0,-1) 14 (-1,0,1) 15 (0,1,1)
  *          16 (0,-1,-1) 17 (0,1,-1) 18 (0,-1,1)
+ *   D3Q27: 0..18 as D3Q19, then 19 (1,1,1) 20 (-1,-1,-1) 21 (1,1,-1)
+ *          22 (-1,-1,1) 23 (1,-1,1) 24 (-1,1,-1) 25 (-1,1,1) 26 (1,-1,-1)
  *
  * Boundary faces, in the order -x,+x,-y,+y,-z,+z, are periodic or walls.
  * Walls use halfway bounce-back: all n cells along an axis are fluid and the
@@ -71,7 +73,7 @@ enum {
     LBM_ENONFINITE = -5   /* a sensor block holds a NaN or Inf (data still written) */
 };
 
-enum { LBM_D2Q9 = 9, LBM_D3Q19 = 19 };                          /* lbm_desc.lattice */
+enum { LBM_D2Q9 = 9, LBM_D3Q19 = 19, LBM_D3Q27 = 27 };         /* lbm_desc.lattice */
 enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F32_SHIFTED = 2,          /* lbm_desc.storage */
        LBM_F16_SHIFTED = 3, LBM_BF16_SHIFTED = 4,
        LBM_F16_SHIFTED_SR = 5, LBM_BF16_SHIFTED_SR = 6 };
@@ -89,7 +91,7 @@ enum { LBM_PROFILE_UNIFORM = 0, LBM_PROFILE_SMOOTH = 1 };
 
 typedef struct {
     uint32_t abi_version;   /* LBM_ABI_VERSION */
-    int32_t lattice;        /* LBM_D2Q9 or LBM_D3Q19 */
+    int32_t lattice;        /* LBM_D2Q9, LBM_D3Q19 or LBM_D3Q27 */
     int32_t storage;        /* LBM_F64: populations and arithmetic in float64.
                                LBM_F32: float32 populations f_i, float32 arithmetic.
                                LBM_F32_SHIFTED: float32 stores f_i - w_i rho0,
@@ -105,8 +107,8 @@ typedef struct {
                                LBM_SENSOR_KKN: (1/q) sum_i |f^neq_i / f^eq_i| (Eq. kkn) */
     int32_t extent[3];      /* cells along x, y, z; extent[2] == 1 for D2Q9;
                                extent[0]*extent[1]*extent[2] < 2^31 */
-    int32_t block[3];       /* sensor block edge: {8,8,1} for D2Q9, {8,8,8} for
-                               D3Q19 (other sizes: LBM_ENOTSUP).  Blocks start at
+    int32_t block[3];       /* sensor block edge: {8,8,1} for D2Q9, {8,8,8} in 3D
+                               (other sizes: LBM_ENOTSUP).  Blocks start at
                                the origin; partial blocks at the far faces are
                                allowed and take the maximum of the cells they hold. */
     int32_t face_bc[6];     /* -x,+x,-y,+y,-z,+z: LBM_BC_PERIODIC or LBM_BC_WALL; a

@@ -9,7 +9,7 @@ not been built the import of ``abi`` raises.
 """
 from .abi import (  # noqa: F401
     LbmError, LBM_OK, LBM_EINVAL, LBM_ENOTSUP, LBM_EHIP, LBM_ESTATE, LBM_ENONFINITE,
-    LBM_D2Q9, LBM_D3Q19, LBM_F64, LBM_F32, LBM_F32_SHIFTED, LBM_F16_SHIFTED, LBM_BF16_SHIFTED,
+    LBM_D2Q9, LBM_D3Q19, LBM_D3Q27, LBM_F64, LBM_F32, LBM_F32_SHIFTED, LBM_F16_SHIFTED, LBM_BF16_SHIFTED,
     LBM_F16_SHIFTED_SR, LBM_BF16_SHIFTED_SR,
     LBM_SENSOR_L2, LBM_SENSOR_KKN,
     LBM_BC_PERIODIC, LBM_BC_WALL, LBM_PROFILE_UNIFORM, LBM_PROFILE_SMOOTH, lbm_desc, make_desc, library_path,

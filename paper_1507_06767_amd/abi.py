@@ -17,7 +17,7 @@ _LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_ABI_VERSION = 2
 LBM_OK, LBM_EINVAL, LBM_ENOTSUP, LBM_EHIP, LBM_ESTATE, LBM_ENONFINITE = 0, -1, -2, -3, -4, -5
-LBM_D2Q9, LBM_D3Q19 = 9, 19
+LBM_D2Q9, LBM_D3Q19, LBM_D3Q27 = 9, 19, 27
 LBM_F64, LBM_F32, LBM_F32_SHIFTED, LBM_F16_SHIFTED, LBM_BF16_SHIFTED = 0, 1, 2, 3, 4
 LBM_F16_SHIFTED_SR, LBM_BF16_SHIFTED_SR = 5, 6
 LBM_SENSOR_L2, LBM_SENSOR_KKN = 0, 1

@@ -1,11 +1,12 @@
 """Build liblbm.so for gfx950 with hipcc (in-tree, next to this file).
 
 Run as ``python paper_1507_06767_amd/build.py`` (by path: importing the
-package would load the library being rebuilt).  The host runtime and the
-step-kernel instantiations of each storage family are separate translation
-units, compiled in parallel and linked into one shared library.  Flags: -O3,
-C++20, no fast-math (division and square root stay correctly rounded), and
-the packed FP32 instructions disabled for the device code.
+package would load the library being rebuilt).  The host runtime, the
+predictor kernels and one object per step-kernel instantiation (lattice x
+storage type, all from step_inst.hip) are compiled in parallel and linked
+into one shared library.  Flags: -O3, C++20, no fast-math (division and
+square root stay correctly rounded), and the packed FP32 instructions
+disabled for the device code.
 """
 from __future__ import annotations
 
@@ -18,7 +19,17 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["lbm.hip", "step_f64.hip", "step_f32.hip", "step_f16.hip", "step_bf16.hip", "cnn.hip"]
+LATTICES = (9, 19, 27)
+# storage type, arithmetic type, shifted storage, object tag
+STORAGE_TYPES = [("double", "double", "false", "f64"), ("float", "float", "false", "f32"),
+                 ("float", "float", "true", "f32s"), ("_Float16", "float", "true", "f16s"),
+                 ("half_sr", "float", "true", "f16sr"), ("__bf16", "float", "true", "bf16s"),
+                 ("bf16_sr", "float", "true", "bf16sr")]
+# (source, extra defines, object name)
+UNITS = [("lbm.hip", [], "lbm.o"), ("cnn.hip", [], "cnn.o")] + [
+    ("step_inst.hip", [f"-DLBM_Q={q}", f"-DLBM_T={t}", f"-DLBM_C={c}", f"-DLBM_SH={sh}"], f"step_q{q}_{tag}.o")
+    for q in LATTICES for t, c, sh, tag in STORAGE_TYPES]
+SOURCES = sorted({u[0] for u in UNITS})
 OUT = os.path.join(HERE, "liblbm.so")
 
 HIPCC_FLAGS = [
@@ -30,17 +41,20 @@ HIPCC_FLAGS = [
 
 def build(out: str = OUT, extra=()) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    jobs = max(1, min(len(UNITS), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
     with tempfile.TemporaryDirectory(prefix="lbm_build_") as tmp:
-        objs = [os.path.join(tmp, src.replace(".hip", ".o")) for src in SOURCES]
+        objs = [os.path.join(tmp, u[2]) for u in UNITS]
 
         def compile_one(k):
-            cmd = [hipcc, *HIPCC_FLAGS, *extra, "-c", "-o", objs[k], os.path.join(CSRC, SOURCES[k])]
+            src, defines, _ = UNITS[k]
+            cmd = [hipcc, *HIPCC_FLAGS, *defines, *extra, "-c", "-o", objs[k], os.path.join(CSRC, src)]
             return subprocess.run(cmd).returncode
 
+        # the largest units first, so that they do not start last
+        order = sorted(range(len(UNITS)), key=lambda k: UNITS[k][0] != "step_inst.hip")
         with ThreadPoolExecutor(max_workers=jobs) as pool:
-            codes = list(pool.map(compile_one, range(len(SOURCES))))
-        failed = [src for src, rc in zip(SOURCES, codes) if rc != 0]
+            codes = dict(zip(order, pool.map(compile_one, order)))
+        failed = [UNITS[k][2] for k in range(len(UNITS)) if codes[k] != 0]
         if failed:
             raise RuntimeError(f"hipcc failed for {failed}")
         tmp_out = out + ".tmp"

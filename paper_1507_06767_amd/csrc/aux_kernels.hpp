@@ -30,7 +30,7 @@ struct Planes {
     T *f;              // plane i at f + i*pitch
     int64_t pitch;
     int cells;
-    double shift[19];  // storage shift per population (0 for plain storage)
+    double shift[kMaxQ];  // storage shift per population (0 for plain storage)
 };
 
 // Rest state: f_i = w_i rho0 (stored as f_i - shift_i).

@@ -1,6 +1,7 @@
 // lattice.hpp -- compile-time velocity sets in the interface order of lbm.h.
 //
-// D2Q9 and D3Q19 with c_s^2 = 1/3 (Sec. 2.2).  Every loop over populations
+// D2Q9, D3Q19 and D3Q27 with c_s^2 = 1/3 (Sec. 2.2; the paper's 3D runs use
+// D3Q27).  Every loop over populations
 // in the kernels is unrolled with static_for, so each xi_i and w_i below is a
 // literal in the generated code: no table is read at run time.
 #pragma once
@@ -33,6 +34,20 @@ struct Lattice<19> {
     static constexpr double w_by_len2[3] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0};
 };
 
+template <>
+struct Lattice<27> {
+    static constexpr int D = 3;
+    static constexpr int c[27][3] = {
+        {0, 0, 0},   {1, 0, 0},   {-1, 0, 0},  {0, 1, 0},   {0, -1, 0}, {0, 0, 1},   {0, 0, -1},
+        {1, 1, 0},   {-1, -1, 0}, {1, -1, 0},  {-1, 1, 0},  {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
+        {-1, 0, 1},  {0, 1, 1},   {0, -1, -1}, {0, 1, -1},  {0, -1, 1}, {1, 1, 1},   {-1, -1, -1},
+        {1, 1, -1},  {-1, -1, 1}, {1, -1, 1},  {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1}};
+    // weights by squared length: 8/27, 2/27, 1/54, 1/216
+    static constexpr double w_by_len2[4] = {8.0 / 27.0, 2.0 / 27.0, 1.0 / 54.0, 1.0 / 216.0};
+};
+
+constexpr int kMaxQ = 27;
+
 template <int Q, int I>
 struct Vel {
     static constexpr int x = Lattice<Q>::c[I][0];
@@ -64,5 +79,6 @@ constexpr bool lattice_is_consistent() {
 }
 static_assert(lattice_is_consistent<9>(), "D2Q9 opposite rule");
 static_assert(lattice_is_consistent<19>(), "D3Q19 opposite rule");
+static_assert(lattice_is_consistent<27>(), "D3Q27 opposite rule");
 
 }  // namespace lbm

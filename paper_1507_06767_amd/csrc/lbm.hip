@@ -97,8 +97,8 @@ lbm_status check_desc(const lbm_desc *d, Layout *L) {
     if (!d) return fail(LBM_EINVAL, "descriptor is NULL");
     if (d->abi_version != LBM_ABI_VERSION)
         return fail(LBM_EINVAL, "abi_version %u, library has %u", d->abi_version, LBM_ABI_VERSION);
-    if (d->lattice != LBM_D2Q9 && d->lattice != LBM_D3Q19)
-        return fail(LBM_ENOTSUP, "lattice %d not supported (9 or 19)", d->lattice);
+    if (d->lattice != LBM_D2Q9 && d->lattice != LBM_D3Q19 && d->lattice != LBM_D3Q27)
+        return fail(LBM_ENOTSUP, "lattice %d not supported (9, 19 or 27)", d->lattice);
     if (d->storage < LBM_F64 || d->storage > LBM_BF16_SHIFTED_SR)
         return fail(LBM_ENOTSUP, "storage %d not supported", d->storage);
     if (d->sensor_kind != LBM_SENSOR_L2 && d->sensor_kind != LBM_SENSOR_KKN)
@@ -226,7 +226,7 @@ namespace {
 // stores non-temporally.  3D float64 always uses ping-pong (its z-march
 // kernel).  LBM_STREAMING=pingpong|inplace overrides the choice for tests.
 bool inplace_setting(const lbm_desc *d, const Layout &L) {
-    if (d->lattice == LBM_D3Q19 && d->storage == LBM_F64) return false;
+    if (d->lattice != LBM_D2Q9 && d->storage == LBM_F64) return false;
     const char *s = std::getenv("LBM_STREAMING");
     if (s && std::strcmp(s, "pingpong") == 0) return false;
     if (s && std::strcmp(s, "inplace") == 0) return true;
@@ -324,7 +324,8 @@ void with_storage_type(lbm_blocks *h, F &&f) {
 template <typename F>
 void with_types(lbm_blocks *h, F &&f) {
     if (h->d.lattice == 9) with_storage_type<9>(h, f);
-    else with_storage_type<19>(h, f);
+    else if (h->d.lattice == 19) with_storage_type<19>(h, f);
+    else with_storage_type<27>(h, f);
 }
 
 unsigned grid_for(int64_t n) { return (unsigned)((n + kAuxThreads - 1) / kAuxThreads); }
@@ -392,25 +393,23 @@ void *canonical_state(lbm_blocks *h) {
     return B;
 }
 
-void launch_step_any(lbm_blocks *h, bool sens) {
-    const int q = h->d.lattice, s = h->d.storage;
-    if (q == 9) {
-        if (s == LBM_F64) launch_step<9, double, double, false>(h, sens);
-        else if (s == LBM_F32) launch_step<9, float, float, false>(h, sens);
-        else if (s == LBM_F32_SHIFTED) launch_step<9, float, float, true>(h, sens);
-        else if (s == LBM_F16_SHIFTED) launch_step<9, _Float16, float, true>(h, sens);
-        else if (s == LBM_BF16_SHIFTED) launch_step<9, __bf16, float, true>(h, sens);
-        else if (s == LBM_F16_SHIFTED_SR) launch_step<9, half_sr, float, true>(h, sens);
-        else launch_step<9, bf16_sr, float, true>(h, sens);
-    } else {
-        if (s == LBM_F64) launch_step<19, double, double, false>(h, sens);
-        else if (s == LBM_F32) launch_step<19, float, float, false>(h, sens);
-        else if (s == LBM_F32_SHIFTED) launch_step<19, float, float, true>(h, sens);
-        else if (s == LBM_F16_SHIFTED) launch_step<19, _Float16, float, true>(h, sens);
-        else if (s == LBM_BF16_SHIFTED) launch_step<19, __bf16, float, true>(h, sens);
-        else if (s == LBM_F16_SHIFTED_SR) launch_step<19, half_sr, float, true>(h, sens);
-        else launch_step<19, bf16_sr, float, true>(h, sens);
+template <int Q>
+void launch_step_q(lbm_blocks *h, bool sens) {
+    switch (h->d.storage) {
+        case LBM_F64: launch_step<Q, double, double, false>(h, sens); break;
+        case LBM_F32: launch_step<Q, float, float, false>(h, sens); break;
+        case LBM_F32_SHIFTED: launch_step<Q, float, float, true>(h, sens); break;
+        case LBM_F16_SHIFTED: launch_step<Q, _Float16, float, true>(h, sens); break;
+        case LBM_BF16_SHIFTED: launch_step<Q, __bf16, float, true>(h, sens); break;
+        case LBM_F16_SHIFTED_SR: launch_step<Q, half_sr, float, true>(h, sens); break;
+        default: launch_step<Q, bf16_sr, float, true>(h, sens); break;
     }
+}
+
+void launch_step_any(lbm_blocks *h, bool sens) {
+    if (h->d.lattice == 9) launch_step_q<9>(h, sens);
+    else if (h->d.lattice == 19) launch_step_q<19>(h, sens);
+    else launch_step_q<27>(h, sens);
 }
 
 lbm_status check_handle(lbm_blocks *h) {

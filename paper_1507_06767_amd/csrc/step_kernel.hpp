@@ -88,9 +88,9 @@ struct StepArgs {
     int ntx, nty, ntiles;   // tiles along x, y; total tiles (workgroups)
     int nbx, nby;           // sensor blocks along x, y
     uint32_t wall;          // bit f set: face f (-x,+x,-y,+y,-z,+z) is a wall
-    C wcorr[19][6];         // 6 w_i rho0 (xi_i . u_face): moving-wall term per face
+    C wcorr[kMaxQ][6];      // 6 w_i rho0 (xi_i . u_face): moving-wall term per face
     uint32_t profile;       // bit f set: face f's velocity is smoothed (wall_factor)
-    C shift[19];            // w_i rho0 rounded to C
+    C shift[kMaxQ];         // w_i rho0 rounded to C
     C omega;                // 1 / tau
     C guo;                  // 1 - 1 / (2 tau)
     C tau0;                 // tau (Smagorinsky: the molecular part)

@@ -96,7 +96,10 @@ def test_required_bytes_layout(lbm):
     (dict(tau=float("nan")), "LBM_EINVAL"),
     (dict(extent=(0, 8, 8)), "LBM_EINVAL"),
     (dict(face_bc=(0, 1, 1, 1, 1, 1)), "LBM_EINVAL"),
-    (dict(lattice=27), "LBM_ENOTSUP"),
+    (dict(lattice=15), "LBM_ENOTSUP"),
+    (dict(smagorinsky=-0.1), "LBM_EINVAL"),
+    (dict(smagorinsky=float("inf")), "LBM_EINVAL"),
+    (dict(wall_profile=(0, 0, 0, 2, 0, 0)), "LBM_EINVAL"),
     (dict(storage=7), "LBM_ENOTSUP"),
     (dict(block=(4, 4, 4)), "LBM_ENOTSUP"),
     (dict(rho0=-1.0), "LBM_EINVAL"),

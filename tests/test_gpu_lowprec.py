@@ -60,6 +60,7 @@ _CASES = [
     ("cav3d", 19, (40, 19, 13), (WALL,) * 6, _wall(0.05), 0.6, (0, 0, 0), None),
     ("box3d", 19, (20, 17, 18), (PERIODIC,) * 6, _wall(), 0.7, (0, 0, 0), 0.02),
     ("cav2d", 9, (70, 37, 1), (WALL, WALL, WALL, WALL, PERIODIC, PERIODIC), _wall(0.1), 0.6, (0, 0, 0), None),
+    ("cav3d_q27", 27, (40, 19, 13), (WALL,) * 6, _wall(0.05), 0.6, (0, 0, 0), None),
 ]
 
 
