@@ -6,7 +6,8 @@ and the refine/coarsen flags evaluated at every step.  A "step" is one
 launch of the fused kernel over the whole grid.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--workload cavity128|cavity256|channel256]
-                  [--storage f32|f32s|f64|f16s|bf16s|f16sr|bf16sr] [--no-cpu-baseline]
+                  [--storage f32|f32s|f64|f16s|bf16s|f16sr|bf16sr] [--lattice 19|27]
+                  [--smagorinsky C] [--no-cpu-baseline]
 
 MLUPS = cells * K / t / 1e6 over K back-to-back steps (HIP events on the
 library's stream).  The roofline entry prices the dominant kernel at its
@@ -111,6 +112,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="cavity128")
     ap.add_argument("--storage", default="f32", choices=["f32", "f32s", "f64", "f16s", "bf16s", "f16sr", "bf16sr"])
+    ap.add_argument("--lattice", type=int, default=19, choices=[19, 27])
+    ap.add_argument("--smagorinsky", type=float, default=0.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=20)
     ap.add_argument("--kernel-samples", type=int, default=200,
@@ -130,13 +133,17 @@ def main():
                "f16s": lbm.LBM_F16_SHIFTED, "bf16s": lbm.LBM_BF16_SHIFTED,
                "f16sr": lbm.LBM_F16_SHIFTED_SR, "bf16sr": lbm.LBM_BF16_SHIFTED_SR}[args.storage]
     w = _workload(args.workload, args.storage)
+    if args.lattice != w.q:
+        import dataclasses
+        w = dataclasses.replace(w, q=args.lattice, name=w.name.replace("d3q19", f"d3q{args.lattice}"))
     if w.reynolds is not None:
         st, tau = lbm.lbm_tau_from_reynolds(w.lid_speed, w.n_across, w.reynolds)
         assert st == 0
     else:
         tau = w.tau
     desc = lbm.make_desc(w.q, w.n, w.bc, tau, storage=storage, wall_u=w.wall_u, force=w.force,
-                         theta_refine=w.theta_refine, theta_coarsen=w.theta_coarsen)
+                         theta_refine=w.theta_refine, theta_coarsen=w.theta_coarsen,
+                         smagorinsky=args.smagorinsky)
     torch.cuda.set_device(0)
     blk = lbm.Blocks(desc, device="cuda:0")
     stream = blk.stream
@@ -197,9 +204,10 @@ def main():
         "vs_baseline": None,
         "dtype": args.storage,
         "data": "synthetic",
-        "config": {"workload": w.name, "lattice": f"D{3 if w.q == 19 else 2}Q{w.q}",
+        "config": {"workload": w.name, "lattice": f"D{2 if w.q == 9 else 3}Q{w.q}",
                    "extent": list(w.n), "tau": tau, "sensor": "L2 ratio, 8^3 block max + flags",
-                   "sensor_every": every, "theta_refine": w.theta_refine},
+                   "sensor_every": every, "theta_refine": w.theta_refine,
+                   "smagorinsky": args.smagorinsky},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
