@@ -87,7 +87,9 @@ enum { LBM_FLAG_COARSEN = -1, LBM_FLAG_KEEP = 0, LBM_FLAG_REFINE = 1, LBM_FLAG_N
 
 typedef struct lbm_blocks lbm_blocks;   /* opaque handle */
 
-enum { LBM_PROFILE_UNIFORM = 0, LBM_PROFILE_SMOOTH = 1 };
+enum { LBM_PROFILE_UNIFORM = 0, LBM_PROFILE_SMOOTH = 1 };      /* lbm_desc.wall_profile[] */
+enum { LBM_STREAMING_AUTO = 0, LBM_STREAMING_PINGPONG = 1,    /* lbm_desc.streaming */
+       LBM_STREAMING_INPLACE = 2 };
 
 typedef struct {
     uint32_t abi_version;   /* LBM_ABI_VERSION */
@@ -133,6 +135,11 @@ typedef struct {
                                face's wall_u times prod over its in-plane axes of
                                (1 - s^18)^2, s = (2 x + 1 - n) / n in (-1, 1) at the
                                fluid cell's centre (ignored on periodic faces) */
+    int32_t streaming;      /* LBM_STREAMING_AUTO: in place (one buffer, the AA pattern)
+                               when a buffer is at most 512 MiB, except 3D float64;
+                               PINGPONG: read F_A, write F_B, swap (required by
+                               lbm_create_hierarchy); INPLACE: in place (not for 3D
+                               float64).  Results are identical bit for bit. */
     void *buf[LBM_NBUF];    /* caller-owned device buffers, see lbm_required_bytes();
                                F_A and F_B must be 256-byte aligned; no two overlap */
     size_t buf_bytes[LBM_NBUF];  /* their sizes in bytes, >= the required sizes */
@@ -246,6 +253,93 @@ void lbm_destroy(lbm_blocks *h);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *lbm_last_error(void);
+
+/* Picks the fastest tile width (32, 64 or 128 cells along x) for the handle's
+ * step kernel by timing `reps` launches (in-place: `reps` pairs) of each on
+ * the handle's stream, and keeps it for later steps.  The state is not
+ * changed: ping-pong timings write only the spare buffer, in-place ones run
+ * on a copy in F_B.  Every tile width gives bit-identical results.  3D
+ * float64 (one tile shape) returns 64 at once.  Synchronises the stream. */
+lbm_status lbm_autotune(lbm_blocks *h, int32_t reps, int32_t *tile_x);
+
+/* ---------------------------------------------------------------------------
+ * Two-level patch hierarchy: boxes of the handle's grid refined by a factor 2
+ * (the static refinement built from the sensor in Sec. 5.1, coupled as in the
+ * AMR runs of Sec. 5.2, after Dupuis & Chopard).  Acoustic scaling: every
+ * coarse step is two fine steps with tau_f = 2 tau - 1/2.  Coupling:
+ *   - ghost layer of each patch: from an abutting patch where one holds the
+ *     cell, else trilinear interpolation of the coarse post-collision
+ *     populations (linear in time between coarse steps), whose
+ *     non-equilibrium part S - f^eq(rho, u) is scaled by
+ *     alpha = (tau_f - 1) / (2 (tau - 1));
+ *   - restriction: after each coarse step every covered coarse cell takes the
+ *     mean of its 8 fine cells, non-equilibrium part scaled by 1/alpha.
+ * The coarse handle keeps stepping every cell; it must stream ping-pong
+ * (lbm_desc.streaming = LBM_STREAMING_PINGPONG), be 3D, store float64,
+ * float32 or shifted float32, have no body force and no Smagorinsky model,
+ * and have tau and 2 tau - 1/2 at least 0.05 away from 1 (else
+ * LBM_ENOTSUP).  While the hierarchy exists the coarse handle must only be
+ * stepped through lbm_hierarchy_step.
+ *
+ * Boxes are in coarse cells, [lo, hi) per axis, with 1 <= lo, hi <= n - 1,
+ * extents multiples of 4 (fine extents multiples of 8, whole 8^3 sensor
+ * blocks), and may touch but not overlap (LBM_EINVAL otherwise).  Fine
+ * sensor blocks are numbered patch by patch, x fastest within a patch.
+ * ------------------------------------------------------------------------- */
+typedef struct lbm_hierarchy lbm_hierarchy;   /* opaque handle */
+
+typedef struct {
+    int32_t lo[3];   /* first coarse cell of the box along x, y, z */
+    int32_t hi[3];   /* one past the last */
+} lbm_box;
+
+enum { LBM_HBUF_F_A = 0, LBM_HBUF_F_B = 1, LBM_HBUF_BLOCK_MAX = 2,   /* hierarchy buffers */
+       LBM_HBUF_FLAGS = 3, LBM_HBUF_META = 4, LBM_NHBUF = 5 };
+
+/* Sizes of the five caller-owned device buffers of a hierarchy: the fine
+ * populations twice (padded patches, ping-pong), the fine block maxima (the
+ * coarse handle's compute precision), the fine flags, and META (patch table,
+ * block-to-patch map, coarse cover map, staging).  Host computation only. */
+lbm_status lbm_hierarchy_required_bytes(const lbm_blocks *coarse, int32_t nbox, const lbm_box *boxes,
+                                        size_t bytes[LBM_NHBUF]);
+
+/* Creates the hierarchy over `coarse`; buffers must be 256-byte aligned device
+ * memory of at least the required sizes.  The fine state starts as the
+ * interpolation of the coarse state.  use_graph != 0 replays pairs of coarse
+ * steps from a captured HIP graph (needs a non-NULL stream; with the NULL
+ * stream the steps are launched one by one).  Synchronises the stream. */
+lbm_status lbm_create_hierarchy(lbm_blocks *coarse, int32_t nbox, const lbm_box *boxes, void *const buf[LBM_NHBUF],
+                                const size_t buf_bytes[LBM_NHBUF], int32_t use_graph, lbm_hierarchy **out);
+
+/* n coarse steps (2n fine steps), asynchronous.  On coarse steps k with
+ * k % sensor_every == 0 (sensor_every > 0) the coarse sensor runs as in
+ * lbm_step_n and the fine sensor on the second fine step. */
+lbm_status lbm_hierarchy_step(lbm_hierarchy *H, int64_t n, int32_t sensor_every);
+
+/* Fine block maxima (float64, NULL allowed), flags (int8, NULL allowed) of
+ * the last fine sensor step, and that coarse step index.  Synchronises. */
+lbm_status lbm_hierarchy_sensor(lbm_hierarchy *H, double *block_max_host, int8_t *flags_host, int64_t *step);
+
+/* Interior fields of one patch, float64 [ez][ey][ex] (x fastest): rho, u
+ * [3][...], and populations [q][...] in the interface velocity order; each
+ * may be NULL.  Synchronises. */
+lbm_status lbm_hierarchy_patch_fields(lbm_hierarchy *H, int32_t patch, double *rho_host, double *u_host,
+                                      double *f_host);
+
+/* Fine cells and blocks, effective cells N_eff = n_coarse / 2 + n_fine (the
+ * cost measure of Sec. 5.2: cells of level i weighted by their update rate),
+ * tau_f, and the fine step's tile depth and persistent workgroup count.
+ * Any pointer may be NULL. */
+lbm_status lbm_hierarchy_info(lbm_hierarchy *H, int64_t *fine_cells, int64_t *fine_blocks, double *n_eff,
+                              double *tau_fine, int32_t *tile_z, int32_t *workgroups);
+
+/* Picks the fine step's tile (8 x 8 x tile_z threads, tile_z in 2, 4, 8) and
+ * persistent workgroup count (2 to 16 per compute unit) by timing `reps`
+ * launches of each; the state is not changed.  Synchronises. */
+lbm_status lbm_hierarchy_autotune(lbm_hierarchy *H, int32_t reps, int32_t *tile_z, int32_t *workgroups);
+
+/* Releases the hierarchy (host memory and graphs); buffers are untouched. */
+void lbm_destroy_hierarchy(lbm_hierarchy *H);
 
 #ifdef __cplusplus
 }

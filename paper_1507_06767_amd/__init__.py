@@ -12,10 +12,14 @@ from .abi import (  # noqa: F401
     LBM_D2Q9, LBM_D3Q19, LBM_D3Q27, LBM_F64, LBM_F32, LBM_F32_SHIFTED, LBM_F16_SHIFTED, LBM_BF16_SHIFTED,
     LBM_F16_SHIFTED_SR, LBM_BF16_SHIFTED_SR,
     LBM_SENSOR_L2, LBM_SENSOR_KKN,
-    LBM_BC_PERIODIC, LBM_BC_WALL, LBM_PROFILE_UNIFORM, LBM_PROFILE_SMOOTH, lbm_desc, make_desc, library_path,
+    LBM_BC_PERIODIC, LBM_BC_WALL, LBM_PROFILE_UNIFORM, LBM_PROFILE_SMOOTH,
+    LBM_STREAMING_AUTO, LBM_STREAMING_PINGPONG, LBM_STREAMING_INPLACE, lbm_desc, lbm_box, make_desc, library_path,
     lbm_required_bytes, lbm_create_blocks, lbm_step_n, lbm_sensor_flags, lbm_get_macros, lbm_block_means,
     lbm_get_populations, lbm_set_populations, lbm_set_equilibrium, lbm_get_step, lbm_set_step, lbm_get_scheme,
     lbm_conservation, lbm_tau_from_reynolds, lbm_destroy, lbm_last_error,
     lbm_sensor_levels, lbm_sensor_average_begin, lbm_sensor_average, lbm_sensor_average_end,
+    lbm_autotune, lbm_hierarchy_required_bytes, lbm_create_hierarchy, lbm_hierarchy_step, lbm_hierarchy_sensor,
+    lbm_hierarchy_patch_fields, lbm_hierarchy_info, lbm_hierarchy_autotune, lbm_destroy_hierarchy,
 )
 from .blocks import Blocks  # noqa: F401
+from .hierarchy import Hierarchy  # noqa: F401

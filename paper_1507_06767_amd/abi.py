@@ -23,6 +23,7 @@ LBM_F16_SHIFTED_SR, LBM_BF16_SHIFTED_SR = 5, 6
 LBM_SENSOR_L2, LBM_SENSOR_KKN = 0, 1
 LBM_BC_PERIODIC, LBM_BC_WALL = 0, 1
 LBM_PROFILE_UNIFORM, LBM_PROFILE_SMOOTH = 0, 1
+LBM_STREAMING_AUTO, LBM_STREAMING_PINGPONG, LBM_STREAMING_INPLACE = 0, 1, 2
 LBM_NBUF = 5
 STATUS_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOTSUP", -3: "LBM_EHIP",
                 -4: "LBM_ESTATE", -5: "LBM_ENONFINITE"}
@@ -51,10 +52,18 @@ class lbm_desc(ctypes.Structure):
         ("theta_coarsen", ctypes.c_double),
         ("smagorinsky", ctypes.c_double),
         ("wall_profile", ctypes.c_int32 * 6),
+        ("streaming", ctypes.c_int32),
         ("buf", ctypes.c_void_p * LBM_NBUF),
         ("buf_bytes", ctypes.c_size_t * LBM_NBUF),
         ("stream", ctypes.c_void_p),
     ]
+
+
+LBM_NHBUF = 5
+
+
+class lbm_box(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_int32 * 3), ("hi", ctypes.c_int32 * 3)]
 
 
 def library_path() -> str:
@@ -98,12 +107,27 @@ def _load_library():
         "lbm_conservation": [H, dp],
         "lbm_tau_from_reynolds": [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp],
     }
+    i32p, i64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+    BP = ctypes.POINTER(lbm_box)
+    sig.update({
+        "lbm_autotune": [H, ctypes.c_int32, i32p],
+        "lbm_hierarchy_required_bytes": [H, ctypes.c_int32, BP, ctypes.POINTER(ctypes.c_size_t)],
+        "lbm_create_hierarchy": [H, ctypes.c_int32, BP, ctypes.POINTER(ctypes.c_void_p),
+                                 ctypes.POINTER(ctypes.c_size_t), ctypes.c_int32, ctypes.POINTER(H)],
+        "lbm_hierarchy_step": [H, ctypes.c_int64, ctypes.c_int32],
+        "lbm_hierarchy_sensor": [H, dp, ctypes.POINTER(ctypes.c_int8), i64p],
+        "lbm_hierarchy_patch_fields": [H, ctypes.c_int32, dp, dp, dp],
+        "lbm_hierarchy_info": [H, i64p, i64p, dp, dp, i32p, i32p],
+        "lbm_hierarchy_autotune": [H, ctypes.c_int32, i32p, i32p],
+    })
     for name, args in sig.items():
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int32
     lib.lbm_destroy.argtypes = [H]
     lib.lbm_destroy.restype = None
+    lib.lbm_destroy_hierarchy.argtypes = [H]
+    lib.lbm_destroy_hierarchy.restype = None
     lib.lbm_last_error.argtypes = []
     lib.lbm_last_error.restype = ctypes.c_char_p
     return lib
@@ -131,7 +155,8 @@ def _counts(desc: lbm_desc):
 
 def make_desc(lattice, extent, face_bc, tau, storage=LBM_F32, sensor_kind=LBM_SENSOR_L2,
               wall_u=None, rho0=1.0, force=(0.0, 0.0, 0.0), theta_refine=1e-3,
-              theta_coarsen=5e-4, block=None, smagorinsky=0.0, wall_profile=None) -> lbm_desc:
+              theta_coarsen=5e-4, block=None, smagorinsky=0.0, wall_profile=None,
+              streaming=LBM_STREAMING_AUTO) -> lbm_desc:
     """A descriptor with the buffers left empty."""
     d = lbm_desc()
     d.abi_version = LBM_ABI_VERSION
@@ -149,6 +174,7 @@ def make_desc(lattice, extent, face_bc, tau, storage=LBM_F32, sensor_kind=LBM_SE
     d.smagorinsky = float(smagorinsky)
     for f in range(6):
         d.wall_profile[f] = int(wall_profile[f]) if wall_profile is not None else LBM_PROFILE_UNIFORM
+    d.streaming = int(streaming)
     return d
 
 
@@ -258,3 +284,71 @@ def lbm_tau_from_reynolds(u: float, n_across: float, re: float):
 
 def lbm_destroy(h):
     _lib.lbm_destroy(h)
+
+
+def lbm_autotune(h, reps: int):
+    t = ctypes.c_int32(0)
+    st = _lib.lbm_autotune(h, int(reps), ctypes.byref(t))
+    return st, t.value
+
+
+def _boxes(boxes):
+    arr = (lbm_box * len(boxes))()
+    for k, (lo, hi) in enumerate(boxes):
+        for a in range(3):
+            arr[k].lo[a], arr[k].hi[a] = int(lo[a]), int(hi[a])
+    return arr
+
+
+def lbm_hierarchy_required_bytes(h, boxes):
+    out = (ctypes.c_size_t * LBM_NHBUF)()
+    st = _lib.lbm_hierarchy_required_bytes(h, len(boxes), _boxes(boxes), out)
+    return st, list(out)
+
+
+def lbm_create_hierarchy(h, boxes, bufs, buf_bytes, use_graph: bool):
+    """bufs: LBM_NHBUF device addresses; buf_bytes: their sizes."""
+    pb = (ctypes.c_void_p * LBM_NHBUF)(*bufs)
+    pn = (ctypes.c_size_t * LBM_NHBUF)(*buf_bytes)
+    H = ctypes.c_void_p()
+    st = _lib.lbm_create_hierarchy(h, len(boxes), _boxes(boxes), pb, pn, int(bool(use_graph)), ctypes.byref(H))
+    return st, H
+
+
+def lbm_hierarchy_step(H, n: int, sensor_every: int):
+    return _lib.lbm_hierarchy_step(H, int(n), int(sensor_every))
+
+
+def lbm_hierarchy_sensor(H, nblocks: int, block_max=None, flags=None):
+    if flags is not None and not (isinstance(flags, np.ndarray) and flags.dtype == np.int8
+                                  and flags.flags.c_contiguous and flags.size == nblocks):
+        raise TypeError("flags must be a C-contiguous int8 array of nblocks values")
+    step = ctypes.c_int64(-1)
+    fp = flags.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)) if flags is not None else None
+    st = _lib.lbm_hierarchy_sensor(H, _dptr(block_max, nblocks), fp, ctypes.byref(step))
+    return st, step.value
+
+
+def lbm_hierarchy_patch_fields(H, patch: int, cells: int, q: int, rho=None, u=None, f=None):
+    return _lib.lbm_hierarchy_patch_fields(H, int(patch), _dptr(rho, cells), _dptr(u, 3 * cells),
+                                           _dptr(f, q * cells))
+
+
+def lbm_hierarchy_info(H):
+    """(status, fine_cells, fine_blocks, n_eff, tau_fine, tile_z, workgroups)."""
+    fc, fb = ctypes.c_int64(0), ctypes.c_int64(0)
+    ne, tf = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    tz, wg = ctypes.c_int32(0), ctypes.c_int32(0)
+    st = _lib.lbm_hierarchy_info(H, ctypes.byref(fc), ctypes.byref(fb), ctypes.byref(ne), ctypes.byref(tf),
+                                 ctypes.byref(tz), ctypes.byref(wg))
+    return st, fc.value, fb.value, ne.value, tf.value, tz.value, wg.value
+
+
+def lbm_hierarchy_autotune(H, reps: int):
+    tz, wg = ctypes.c_int32(0), ctypes.c_int32(0)
+    st = _lib.lbm_hierarchy_autotune(H, int(reps), ctypes.byref(tz), ctypes.byref(wg))
+    return st, tz.value, wg.value
+
+
+def lbm_destroy_hierarchy(H):
+    _lib.lbm_destroy_hierarchy(H)

@@ -124,6 +124,12 @@ class Blocks:
     def step(self, value: int):
         _check(abi.lbm_set_step(self.h, value))
 
+    def autotune(self, reps: int = 5):
+        """Times the tile widths of the step kernel and keeps the fastest."""
+        st, tx = abi.lbm_autotune(self.h, reps)
+        _check(st)
+        return tx
+
     def scheme(self):
         """dict(inplace, next_is_gather, tile_x) of the handle."""
         st, ip, nxt, tx = abi.lbm_get_scheme(self.h)

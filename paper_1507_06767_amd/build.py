@@ -2,9 +2,10 @@
 
 Run as ``python paper_1507_06767_amd/build.py`` (by path: importing the
 package would load the library being rebuilt).  The host runtime, the
-predictor kernels and one object per step-kernel instantiation (lattice x
-storage type, all from step_inst.hip) are compiled in parallel and linked
-into one shared library.  Flags: -O3, C++20, no fast-math (division and
+predictor kernels, one object per step-kernel instantiation (lattice x
+storage type, all from step_inst.hip) and the patch-hierarchy kernels per
+lattice (patch_inst.hip) are compiled in parallel and linked into one shared
+library.  Flags: -O3, C++20, no fast-math (division and
 square root stay correctly rounded), and the packed FP32 instructions
 disabled for the device code.
 """
@@ -28,7 +29,8 @@ STORAGE_TYPES = [("double", "double", "false", "f64"), ("float", "float", "false
 # (source, extra defines, object name)
 UNITS = [("lbm.hip", [], "lbm.o"), ("cnn.hip", [], "cnn.o")] + [
     ("step_inst.hip", [f"-DLBM_Q={q}", f"-DLBM_T={t}", f"-DLBM_C={c}", f"-DLBM_SH={sh}"], f"step_q{q}_{tag}.o")
-    for q in LATTICES for t, c, sh, tag in STORAGE_TYPES]
+    for q in LATTICES for t, c, sh, tag in STORAGE_TYPES] + [
+    ("patch_inst.hip", [f"-DLBM_Q={q}"], f"patch_q{q}.o") for q in (19, 27)]
 SOURCES = sorted({u[0] for u in UNITS})
 OUT = os.path.join(HERE, "liblbm.so")
 
@@ -51,7 +53,7 @@ def build(out: str = OUT, extra=()) -> str:
             return subprocess.run(cmd).returncode
 
         # the largest units first, so that they do not start last
-        order = sorted(range(len(UNITS)), key=lambda k: UNITS[k][0] != "step_inst.hip")
+        order = sorted(range(len(UNITS)), key=lambda k: UNITS[k][0] == "cnn.hip")
         with ThreadPoolExecutor(max_workers=jobs) as pool:
             codes = dict(zip(order, pool.map(compile_one, order)))
         failed = [UNITS[k][2] for k in range(len(UNITS)) if codes[k] != 0]

@@ -1,0 +1,470 @@
+// hierarchy_host.hpp -- host side of the two-level patch hierarchy
+// (include/lbm.h, lbm_create_hierarchy and friends).  Part of the lbm.hip
+// translation unit: it uses that file's handle internals and helpers.
+//
+// One coarse step of the hierarchy (coarse state X -> Y, fine A -> B -> A):
+//   1. ghost layers of the fine state A from X (and from abutting patches);
+//   2. fine step A -> B;
+//   3. coarse step X -> Y (every coarse cell, the step kernel of the handle);
+//   4. ghost layers of B from (X + Y) / 2 (linear time interpolation);
+//   5. fine step B -> A (with the fine sensor on sensor steps);
+//   6. restriction: covered coarse cells of Y from the fine state A.
+// Steps 1-6 of two consecutive coarse steps are captured once into a HIP
+// graph per coarse parity and replayed (the kernels' arguments repeat every
+// two coarse steps).
+
+#include "patch_kernels.hpp"
+
+struct lbm_hierarchy {
+    lbm_blocks *coarse;
+    int q;
+    int npatch;
+    std::vector<lbm_box> boxes;
+    std::vector<PatchRec> rec;
+    int64_t total_padded, covered, nblocks, fine_cells, max_patch_cells;
+    int64_t pitch;            // elements between fine planes
+    size_t elem;              // bytes per stored value
+    size_t meta_patch, meta_blk, meta_cover, meta_stage;   // offsets inside META
+    size_t bytes[LBM_NHBUF];
+    void *buf[LBM_NHBUF];
+    int cur;                  // fine state in F_A (0) or F_B (1)
+    double tau_f, alpha;
+    int bz, nwg;              // tile depth and persistent workgroups of the fine step
+    bool use_graph;
+    hipGraphExec_t graph[2];  // two coarse steps, by the coarse buffer parity
+    int64_t step;             // coarse steps taken through the hierarchy
+    int64_t last_sensor_step;
+    std::vector<unsigned char> bmax_host;
+};
+
+namespace {
+
+constexpr int kHierCUs = 256;
+
+// Layout of the hierarchy for a coarse handle and boxes; validates both.
+lbm_status hier_layout(const lbm_blocks *h, int32_t nbox, const lbm_box *boxes, lbm_hierarchy *H) {
+    if (!h) return fail(LBM_EINVAL, "coarse handle is NULL");
+    if (nbox < 1 || !boxes) return fail(LBM_EINVAL, "need at least one box");
+    const lbm_desc &d = h->d;
+    if (d.lattice == LBM_D2Q9) return fail(LBM_ENOTSUP, "the hierarchy is 3D (D3Q19 or D3Q27)");
+    if (d.storage != LBM_F64 && d.storage != LBM_F32 && d.storage != LBM_F32_SHIFTED)
+        return fail(LBM_ENOTSUP, "the hierarchy supports float64, float32 and shifted float32 storage");
+    if (h->inplace) return fail(LBM_ENOTSUP, "the coarse handle must stream ping-pong (LBM_STREAMING_PINGPONG)");
+    if (h->has_force || d.smagorinsky > 0.0)
+        return fail(LBM_ENOTSUP, "the hierarchy couples plain BGK without body force");
+    const double tau_c = d.tau, tau_f = 2.0 * tau_c - 0.5;
+    if (std::fabs(tau_c - 1.0) < 0.05 || std::fabs(tau_f - 1.0) < 0.05)
+        return fail(LBM_ENOTSUP, "tau = %g: the non-equilibrium rescaling needs tau and 2 tau - 1/2 away from 1",
+                    tau_c);
+    const int n[3] = {d.extent[0], d.extent[1], d.extent[2]};
+    std::vector<int> cover((size_t)h->L.cells, -1);
+    H->q = d.lattice;
+    H->npatch = nbox;
+    H->boxes.assign(boxes, boxes + nbox);
+    H->rec.assign(nbox, PatchRec{});
+    int64_t padded = 0, blocks = 0, cov = 0, maxc = 0;
+    for (int p = 0; p < nbox; ++p) {
+        const lbm_box &b = boxes[p];
+        PatchRec &r = H->rec[p];
+        for (int a = 0; a < 3; ++a) {
+            if (b.lo[a] < 1 || b.hi[a] > n[a] - 1 || b.hi[a] <= b.lo[a])
+                return fail(LBM_EINVAL, "box %d axis %d: need 1 <= lo < hi <= n - 1 (coarse cells)", p, a);
+            if ((b.hi[a] - b.lo[a]) % 4)
+                return fail(LBM_EINVAL, "box %d axis %d: extent %d is not a multiple of 4 coarse cells", p, a,
+                            b.hi[a] - b.lo[a]);
+            r.o[a] = 2 * b.lo[a];
+            r.e[a] = 2 * (b.hi[a] - b.lo[a]);
+        }
+        for (int z = b.lo[2]; z < b.hi[2]; ++z)
+            for (int y = b.lo[1]; y < b.hi[1]; ++y)
+                for (int x = b.lo[0]; x < b.hi[0]; ++x) {
+                    int &c = cover[((size_t)z * n[1] + y) * n[0] + x];
+                    if (c >= 0) return fail(LBM_EINVAL, "boxes %d and %d overlap", c, p);
+                    c = p;
+                }
+        r.off = (int)padded;
+        r.blk0 = (int)blocks;
+        r.coff = (int)cov;
+        const int64_t pc = (int64_t)(r.e[0] + 2) * (r.e[1] + 2) * (r.e[2] + 2);
+        const int64_t cells = (int64_t)r.e[0] * r.e[1] * r.e[2];
+        padded += pc;
+        blocks += cells / 512;
+        cov += cells / 8;
+        maxc = std::max(maxc, cells);
+    }
+    if (padded >= (int64_t(1) << 31)) return fail(LBM_ENOTSUP, "patches hold more than 2^31 padded cells");
+    H->total_padded = padded;
+    H->nblocks = blocks;
+    H->covered = cov;
+    H->fine_cells = 8 * cov;
+    H->max_patch_cells = maxc;
+    H->elem = h->L.elem;
+    H->pitch = (int64_t)round_up((size_t)padded, 64) + 64;
+    H->tau_f = tau_f;
+    H->alpha = (tau_f - 1.0) / (2.0 * (tau_c - 1.0));
+    H->bytes[LBM_HBUF_F_A] = H->bytes[LBM_HBUF_F_B] = round_up((size_t)H->q * H->pitch * H->elem, kAlign);
+    H->bytes[LBM_HBUF_BLOCK_MAX] = round_up((size_t)blocks * h->L.cbytes, kAlign);
+    H->bytes[LBM_HBUF_FLAGS] = round_up((size_t)blocks, kAlign);
+    H->meta_patch = 0;
+    H->meta_blk = round_up((size_t)nbox * sizeof(PatchRec), kAlign);
+    H->meta_cover = H->meta_blk + round_up((size_t)blocks * 4, kAlign);
+    H->meta_stage = H->meta_cover + round_up((size_t)h->L.cells * 4, kAlign);
+    H->bytes[LBM_HBUF_META] = H->meta_stage + round_up((size_t)maxc * (H->q + 4) * 8, kAlign);
+    H->bmax_host.assign((size_t)blocks * h->L.cbytes, 0);
+    return LBM_OK;
+}
+
+template <typename C>
+PatchArgs<C> patch_args(lbm_hierarchy *H, const void *src, void *dst) {
+    const lbm_desc &d = H->coarse->d;
+    PatchArgs<C> a{};
+    a.src = src;
+    a.dst = dst;
+    a.pitch = H->pitch;
+    char *meta = static_cast<char *>(H->buf[LBM_HBUF_META]);
+    a.patch = reinterpret_cast<const PatchRec *>(meta + H->meta_patch);
+    a.blk_patch = reinterpret_cast<const int *>(meta + H->meta_blk);
+    a.npatch = H->npatch;
+    a.nblocks = (int)H->nblocks;
+    for (int i = 0; i < kMaxQ; ++i) a.shift[i] = C(0);
+    auto fill_shift = [&]<int Q>() {
+        static_for<0, Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            a.shift[i] = (C)(Vel<Q, i>::w * d.rho0);
+        });
+    };
+    if (H->q == 19) fill_shift.template operator()<19>();
+    else fill_shift.template operator()<27>();
+    a.rho0 = (C)d.rho0;
+    a.omega = (C)(1.0 / H->tau_f);
+    a.theta_r = d.theta_refine;
+    a.theta_c = d.theta_coarsen;
+    a.block_max = static_cast<C *>(H->buf[LBM_HBUF_BLOCK_MAX]);
+    a.flags = static_cast<int8_t *>(H->buf[LBM_HBUF_FLAGS]);
+    return a;
+}
+
+template <typename C>
+CoarseView<C> coarse_view(lbm_hierarchy *H, const void *s0, const void *s1, double w1, void *out) {
+    const lbm_blocks *h = H->coarse;
+    CoarseView<C> v{};
+    v.s0 = s0;
+    v.s1 = s1;
+    v.out = out;
+    v.pitch = h->L.pitch;
+    v.nx = h->d.extent[0];
+    v.ny = h->d.extent[1];
+    v.nz = h->d.extent[2];
+    v.cover = reinterpret_cast<const int *>(static_cast<char *>(H->buf[LBM_HBUF_META]) + H->meta_cover);
+    v.w1 = (C)w1;
+    v.alpha = (C)H->alpha;
+    return v;
+}
+
+// Calls f.template operator()<Q, T, C, SH>() for the hierarchy's types.
+template <typename F>
+void with_hier_types(lbm_hierarchy *H, F &&f) {
+    const int s = H->coarse->d.storage;
+    auto by_q = [&]<int Q>() {
+        if (s == LBM_F64) f.template operator()<Q, double, double, false>();
+        else if (s == LBM_F32) f.template operator()<Q, float, float, false>();
+        else f.template operator()<Q, float, float, true>();
+    };
+    if (H->q == 19) by_q.template operator()<19>();
+    else by_q.template operator()<27>();
+}
+
+void *fine_buf(lbm_hierarchy *H, int which) { return H->buf[which ? LBM_HBUF_F_B : LBM_HBUF_F_A]; }
+
+void hier_fine_step(lbm_hierarchy *H, const void *src, void *dst, bool sensor) {
+    with_hier_types(H, [&]<int Q, typename T, typename C, bool SH>() {
+        PatchLaunch l{H->coarse->stream, sensor, H->coarse->d.sensor_kind, H->bz, H->nwg};
+        launch_patch_step<Q, T, C, SH>(patch_args<C>(H, src, dst), l);
+    });
+}
+
+void hier_fill(lbm_hierarchy *H, void *state, const void *s0, const void *s1, double w1, bool all_cells) {
+    with_hier_types(H, [&]<int Q, typename T, typename C, bool SH>() {
+        launch_patch_fill<Q, T, C, SH>(patch_args<C>(H, state, state), coarse_view<C>(H, s0, s1, w1, nullptr),
+                                       state, H->total_padded, all_cells, H->coarse->stream);
+    });
+}
+
+// One coarse step (steps 1-6 above) enqueued on the coarse handle's stream.
+void hier_coarse_step(lbm_hierarchy *H, bool sens) {
+    lbm_blocks *h = H->coarse;
+    void *X = state_ptr(h);
+    void *Y = h->d.buf[h->cur ? LBM_BUF_F_A : LBM_BUF_F_B];
+    void *A = fine_buf(H, H->cur), *B = fine_buf(H, H->cur ^ 1);
+    hier_fill(H, A, X, X, 0.0, false);
+    hier_fine_step(H, A, B, false);
+    const int64_t step = h->step + 1;
+    launch_step_any(h, sens);
+    h->cur ^= 1;
+    h->step = step;
+    if (sens) h->last_sensor_step = step;
+    hier_fill(H, B, X, Y, 0.5, false);
+    hier_fine_step(H, B, A, sens);
+    with_hier_types(H, [&]<int Q, typename T, typename C, bool SH>() {
+        launch_patch_restrict<Q, T, C, SH>(patch_args<C>(H, A, A), coarse_view<C>(H, Y, Y, 0.0, Y), A,
+                                           H->covered, h->stream);
+    });
+    H->step += 1;
+    if (sens) H->last_sensor_step = H->step;
+}
+
+lbm_status hier_capture(lbm_hierarchy *H, int parity) {
+    lbm_blocks *h = H->coarse;
+    const int64_t s0 = h->step, s1 = h->last_sensor_step, s2 = H->step, s3 = H->last_sensor_step;
+    HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    hier_coarse_step(H, false);
+    hier_coarse_step(H, false);
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamEndCapture(h->stream, &g));
+    h->step = s0;
+    h->last_sensor_step = s1;
+    H->step = s2;
+    H->last_sensor_step = s3;
+    hipError_t e = hipGraphInstantiate(&H->graph[parity], g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        H->graph[parity] = nullptr;
+        return fail(LBM_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    return LBM_OK;
+}
+
+lbm_status hier_check(lbm_hierarchy *H) {
+    if (!H) return fail(LBM_EINVAL, "hierarchy is NULL");
+    return check_handle(H->coarse);
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_hierarchy_required_bytes(const lbm_blocks *coarse, int32_t nbox, const lbm_box *boxes,
+                                        size_t bytes[LBM_NHBUF]) {
+    if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+    lbm_hierarchy H;
+    lbm_status st = hier_layout(coarse, nbox, boxes, &H);
+    if (st != LBM_OK) return st;
+    for (int b = 0; b < LBM_NHBUF; ++b) bytes[b] = H.bytes[b];
+    return LBM_OK;
+}
+
+lbm_status lbm_create_hierarchy(lbm_blocks *coarse, int32_t nbox, const lbm_box *boxes, void *const buf[LBM_NHBUF],
+                                const size_t buf_bytes[LBM_NHBUF], int32_t use_graph, lbm_hierarchy **out) {
+    if (!out || !buf || !buf_bytes) return fail(LBM_EINVAL, "out, buf and buf_bytes must not be NULL");
+    lbm_status st = check_handle(coarse);
+    if (st != LBM_OK) return st;
+    lbm_hierarchy *H = new (std::nothrow) lbm_hierarchy();
+    if (!H) return fail(LBM_EINVAL, "out of host memory");
+    st = hier_layout(coarse, nbox, boxes, H);
+    if (st != LBM_OK) {
+        delete H;
+        return st;
+    }
+    static const char *names[LBM_NHBUF] = {"F_A", "F_B", "BLOCK_MAX", "FLAGS", "META"};
+    for (int b = 0; b < LBM_NHBUF; ++b) {
+        if (!buf[b] || buf_bytes[b] < H->bytes[b] || (uintptr_t)buf[b] % kAlign) {
+            delete H;
+            return fail(LBM_EINVAL, "hierarchy buffer %s: NULL, smaller than %zu bytes or not 256-byte aligned",
+                        names[b], H->bytes[b]);
+        }
+        H->buf[b] = buf[b];
+    }
+    H->coarse = coarse;
+    H->cur = 0;
+    H->bz = 8;
+    H->nwg = (int)std::min<int64_t>(H->nblocks, 8 * kHierCUs);
+    H->use_graph = use_graph != 0 && coarse->stream != nullptr;
+    H->graph[0] = H->graph[1] = nullptr;
+    H->step = 0;
+    H->last_sensor_step = -1;
+    // tables: patch records, block -> patch, coarse cover map
+    std::vector<int> blk((size_t)H->nblocks);
+    for (int p = 0; p < H->npatch; ++p) {
+        const PatchRec &r = H->rec[p];
+        const int64_t nb = (int64_t)r.e[0] * r.e[1] * r.e[2] / 512;
+        for (int64_t k = 0; k < nb; ++k) blk[r.blk0 + k] = p;
+    }
+    std::vector<int> cover((size_t)coarse->L.cells, -1);
+    for (int p = 0; p < H->npatch; ++p) {
+        const lbm_box &b = H->boxes[p];
+        for (int z = b.lo[2]; z < b.hi[2]; ++z)
+            for (int y = b.lo[1]; y < b.hi[1]; ++y)
+                for (int x = b.lo[0]; x < b.hi[0]; ++x)
+                    cover[((size_t)z * coarse->d.extent[1] + y) * coarse->d.extent[0] + x] = p;
+    }
+    char *meta = static_cast<char *>(H->buf[LBM_HBUF_META]);
+    hipStream_t s = coarse->stream;
+    hipError_t e = hipMemcpyAsync(meta + H->meta_patch, H->rec.data(), H->rec.size() * sizeof(PatchRec),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(meta + H->meta_blk, blk.data(), blk.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(meta + H->meta_cover, cover.data(), cover.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        // the initial fine state: every padded cell interpolated from the coarse state
+        void *X = state_ptr(coarse);
+        hier_fill(H, fine_buf(H, 0), X, X, 0.0, true);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        delete H;
+        return fail(LBM_EHIP, "hierarchy set-up: %s", hipGetErrorString(e));
+    }
+    *out = H;
+    return LBM_OK;
+}
+
+lbm_status lbm_hierarchy_step(lbm_hierarchy *H, int64_t n, int32_t sensor_every) {
+    lbm_status st = hier_check(H);
+    if (st != LBM_OK) return st;
+    if (n < 0 || sensor_every < 0) return fail(LBM_EINVAL, "n and sensor_every must be >= 0");
+    lbm_blocks *h = H->coarse;
+    int64_t k = 0;
+    while (k < n) {
+        const int64_t step = h->step + 1;
+        const bool sens = sensor_every > 0 && step % sensor_every == 0;
+        const bool sens2 = sensor_every > 0 && (step + 1) % sensor_every == 0;
+        if (H->use_graph && !sens && !sens2 && n - k >= 2) {
+            const int parity = h->cur;
+            if (!H->graph[parity]) {
+                st = hier_capture(H, parity);
+                if (st != LBM_OK) return st;
+            }
+            HIP_TRY(hipGraphLaunch(H->graph[parity], h->stream));
+            h->step += 2;
+            H->step += 2;
+            k += 2;   // two coarse steps: both parities are back where they were
+            continue;
+        }
+        hier_coarse_step(H, sens);
+        ++k;
+    }
+    HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
+lbm_status lbm_hierarchy_sensor(lbm_hierarchy *H, double *block_max_host, int8_t *flags_host, int64_t *step) {
+    lbm_status st = hier_check(H);
+    if (st != LBM_OK) return st;
+    if (H->last_sensor_step < 0) return fail(LBM_ESTATE, "no fine sensor step has run");
+    lbm_blocks *h = H->coarse;
+    if (block_max_host)
+        HIP_TRY(hipMemcpyAsync(H->bmax_host.data(), H->buf[LBM_HBUF_BLOCK_MAX], H->bmax_host.size(),
+                               hipMemcpyDeviceToHost, h->stream));
+    if (flags_host)
+        HIP_TRY(hipMemcpyAsync(flags_host, H->buf[LBM_HBUF_FLAGS], H->nblocks, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (block_max_host) {
+        for (int64_t b = 0; b < H->nblocks; ++b) {
+            if (h->L.cbytes == 8) block_max_host[b] = reinterpret_cast<const double *>(H->bmax_host.data())[b];
+            else block_max_host[b] = reinterpret_cast<const float *>(H->bmax_host.data())[b];
+        }
+    }
+    if (step) *step = H->last_sensor_step;
+    return LBM_OK;
+}
+
+lbm_status lbm_hierarchy_patch_fields(lbm_hierarchy *H, int32_t patch, double *rho_host, double *u_host,
+                                      double *f_host) {
+    lbm_status st = hier_check(H);
+    if (st != LBM_OK) return st;
+    if (patch < 0 || patch >= H->npatch) return fail(LBM_EINVAL, "patch %d out of range", patch);
+    const PatchRec &r = H->rec[patch];
+    const int64_t n = (int64_t)r.e[0] * r.e[1] * r.e[2];
+    double *stage = reinterpret_cast<double *>(static_cast<char *>(H->buf[LBM_HBUF_META]) + H->meta_stage);
+    double *rho_d = stage, *u_d = stage + n, *f_d = stage + 4 * n;
+    hipStream_t s = H->coarse->stream;
+    with_hier_types(H, [&]<int Q, typename T, typename C, bool SH>() {
+        launch_patch_macros<Q, T, C, SH>(patch_args<C>(H, fine_buf(H, H->cur), nullptr), fine_buf(H, H->cur), patch,
+                                         n, rho_d, u_d, f_host ? f_d : nullptr, s);
+    });
+    HIP_TRY(hipGetLastError());
+    if (rho_host) HIP_TRY(hipMemcpyAsync(rho_host, rho_d, n * 8, hipMemcpyDeviceToHost, s));
+    if (u_host) HIP_TRY(hipMemcpyAsync(u_host, u_d, 3 * n * 8, hipMemcpyDeviceToHost, s));
+    if (f_host) HIP_TRY(hipMemcpyAsync(f_host, f_d, H->q * n * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return LBM_OK;
+}
+
+lbm_status lbm_hierarchy_info(lbm_hierarchy *H, int64_t *fine_cells, int64_t *fine_blocks, double *n_eff,
+                              double *tau_fine, int32_t *tile_z, int32_t *workgroups) {
+    lbm_status st = hier_check(H);
+    if (st != LBM_OK) return st;
+    if (fine_cells) *fine_cells = H->fine_cells;
+    if (fine_blocks) *fine_blocks = H->nblocks;
+    // effective cells (Sec. 5.2): cells of level i weighted by 2^-(L - i); the
+    // coarse level (i = 0) steps once per two fine steps (L = 1)
+    if (n_eff) *n_eff = 0.5 * (double)H->coarse->L.cells + (double)H->fine_cells;
+    if (tau_fine) *tau_fine = H->tau_f;
+    if (tile_z) *tile_z = H->bz;
+    if (workgroups) *workgroups = H->nwg;
+    return LBM_OK;
+}
+
+lbm_status lbm_hierarchy_autotune(lbm_hierarchy *H, int32_t reps, int32_t *tile_z, int32_t *workgroups) {
+    lbm_status st = hier_check(H);
+    if (st != LBM_OK) return st;
+    if (reps < 1) return fail(LBM_EINVAL, "reps = %d < 1", reps);
+    hipStream_t s = H->coarse->stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    // the timed launches read the fine state and write the other fine buffer,
+    // which the next step overwrites: the state is left unchanged
+    const void *src = fine_buf(H, H->cur);
+    void *dst = fine_buf(H, H->cur ^ 1);
+    float best = 1e30f;
+    int best_bz = H->bz, best_nwg = H->nwg;
+    const int bzs[3] = {2, 4, 8};
+    const int per_cu[4] = {2, 4, 8, 16};
+    hipError_t e = hipSuccess;
+    for (int bz : bzs) {
+        for (int pc : per_cu) {
+            H->bz = bz;
+            H->nwg = (int)std::min<int64_t>(H->nblocks, (int64_t)pc * kHierCUs);
+            hier_fine_step(H, src, dst, false);   // warm-up
+            e = hipEventRecord(e0, s);
+            for (int r = 0; r < reps && e == hipSuccess; ++r) hier_fine_step(H, src, dst, false);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) break;
+            if (ms < best) {
+                best = ms;
+                best_bz = bz;
+                best_nwg = H->nwg;
+            }
+        }
+        if (e != hipSuccess) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    H->bz = best_bz;
+    H->nwg = best_nwg;
+    // graphs captured with the old tile shape are stale
+    for (int p = 0; p < 2; ++p)
+        if (H->graph[p]) {
+            hipGraphExecDestroy(H->graph[p]);
+            H->graph[p] = nullptr;
+        }
+    if (e != hipSuccess) return fail(LBM_EHIP, "autotune: %s", hipGetErrorString(e));
+    if (tile_z) *tile_z = H->bz;
+    if (workgroups) *workgroups = H->nwg;
+    return LBM_OK;
+}
+
+void lbm_destroy_hierarchy(lbm_hierarchy *H) {
+    if (!H) return;
+    for (int p = 0; p < 2; ++p)
+        if (H->graph[p]) hipGraphExecDestroy(H->graph[p]);
+    delete H;
+}
+
+}  // extern "C"

@@ -138,6 +138,10 @@ lbm_status check_desc(const lbm_desc *d, Layout *L) {
     for (int f = 0; f < 6; ++f)
         if (d->wall_profile[f] != LBM_PROFILE_UNIFORM && d->wall_profile[f] != LBM_PROFILE_SMOOTH)
             return fail(LBM_EINVAL, "wall_profile[%d] = %d", f, d->wall_profile[f]);
+    if (d->streaming < LBM_STREAMING_AUTO || d->streaming > LBM_STREAMING_INPLACE)
+        return fail(LBM_EINVAL, "streaming = %d", d->streaming);
+    if (d->streaming == LBM_STREAMING_INPLACE && d->lattice != LBM_D2Q9 && d->storage == LBM_F64)
+        return fail(LBM_ENOTSUP, "3D float64 streams ping-pong only");
 
     L->q = d->lattice;
     L->dim = dim;
@@ -224,9 +228,13 @@ namespace {
 // most 512 MiB, so that the working set of a step can stay in the Infinity
 // Cache; ping-pong above, where the two are on par and ping-pong streams its
 // stores non-temporally.  3D float64 always uses ping-pong (its z-march
-// kernel).  LBM_STREAMING=pingpong|inplace overrides the choice for tests.
+// kernel).  An explicit choice in the descriptor wins; under
+// LBM_STREAMING_AUTO the environment variable LBM_STREAMING=pingpong|inplace
+// overrides the size rule (tests run both schemes that way).
 bool inplace_setting(const lbm_desc *d, const Layout &L) {
     if (d->lattice != LBM_D2Q9 && d->storage == LBM_F64) return false;
+    if (d->streaming == LBM_STREAMING_PINGPONG) return false;
+    if (d->streaming == LBM_STREAMING_INPLACE) return true;
     const char *s = std::getenv("LBM_STREAMING");
     if (s && std::strcmp(s, "pingpong") == 0) return false;
     if (s && std::strcmp(s, "inplace") == 0) return true;
@@ -766,6 +774,61 @@ lbm_status lbm_conservation(lbm_blocks *h, double out[4]) {
     return LBM_OK;
 }
 
+lbm_status lbm_autotune(lbm_blocks *h, int32_t reps, int32_t *tile_x) {
+    lbm_status st = check_handle(h);
+    if (st != LBM_OK) return st;
+    if (reps < 1) return fail(LBM_EINVAL, "reps = %d < 1", reps);
+    const bool zm = h->d.lattice != LBM_D2Q9 && h->d.storage == LBM_F64;
+    if (zm) {   // the z-march kernel has one tile shape
+        if (tile_x) *tile_x = 64;
+        return LBM_OK;
+    }
+    // Timed launches must leave the state alone.  Ping-pong: they read the
+    // state and write the other buffer.  In place: they run on a copy of F_A
+    // in F_B (the staging buffer), with the two buffers exchanged meanwhile.
+    const size_t bytes = (size_t)h->L.q * h->L.pitch * h->L.elem;
+    if (h->inplace) {
+        HIP_TRY(hipMemcpyAsync(h->d.buf[LBM_BUF_F_B], h->d.buf[LBM_BUF_F_A], bytes, hipMemcpyDeviceToDevice,
+                               h->stream));
+        std::swap(h->d.buf[LBM_BUF_F_A], h->d.buf[LBM_BUF_F_B]);
+    }
+    const int saved_tile = h->tile_x, saved_phase = h->phase;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_tile = saved_tile;
+    hipError_t e = hipSuccess;
+    for (int tx : {32, 64, 128}) {
+        h->tile_x = tx;
+        auto one = [&]() {
+            launch_step_any(h, false);
+            if (h->inplace) h->phase ^= 1;
+        };
+        one();
+        one();   // warm-up (both halves of the in-place pair)
+        e = hipEventRecord(e0, h->stream);
+        for (int r = 0; r < 2 * reps && e == hipSuccess; ++r) one();
+        if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) break;
+        if (ms < best) {
+            best = ms;
+            best_tile = tx;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (h->inplace) std::swap(h->d.buf[LBM_BUF_F_A], h->d.buf[LBM_BUF_F_B]);
+    h->phase = saved_phase;
+    h->tile_x = (e == hipSuccess) ? best_tile : saved_tile;
+    if (e != hipSuccess) return fail(LBM_EHIP, "autotune: %s", hipGetErrorString(e));
+    if (tile_x) *tile_x = h->tile_x;
+    return LBM_OK;
+}
+
 lbm_status lbm_tau_from_reynolds(double u, double n_across, double re, double *tau) {
     if (!tau) return fail(LBM_EINVAL, "tau is NULL");
     if (!is_fin(u) || !is_fin(n_across) || !is_fin(re) || !(re > 0.0) || !(n_across > 0.0))
@@ -785,3 +848,6 @@ void lbm_destroy(lbm_blocks *h) {
 const char *lbm_last_error(void) { return g_error.c_str(); }
 
 }  // extern "C"
+
+// The two-level patch hierarchy (lbm_create_hierarchy and friends).
+#include "hierarchy_host.hpp"

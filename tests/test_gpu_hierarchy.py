@@ -1,0 +1,165 @@
+"""The two-level patch hierarchy on the GPU against its FP64 oracle
+(oracle/hier.py): coarse and fine populations, fine sensor block maxima and
+flags after several coarse steps, for D3Q19 and D3Q27, float64 and shifted
+float32; graph replay against launch-by-launch stepping; the autotuners
+leave results unchanged.
+
+Tolerances: float64 populations 1e-13 absolute (values ~0.01-0.3), block
+maxima 1e-11 relative; shifted float32 populations 2e-7 absolute, fields as
+in the single-grid parity tests (1e-5 relative), block maxima 2e-5 relative
+to max(M, 1e-3)."""
+import numpy as np
+import pytest
+
+from lbm_inputs import WALL
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1507_06767_amd as lbm
+    return torch, lbm
+
+
+def _lid(u):
+    w = [[0.0] * 3 for _ in range(6)]
+    w[3][0] = u
+    return w
+
+
+# three patches: two abutting along x, one apart (coarse boxes [lo, hi))
+_BOXES = [((4, 4, 4), (8, 8, 12)), ((8, 4, 4), (12, 8, 12)), ((14, 10, 6), (22, 18, 10))]
+_N = (24, 20, 16)
+
+
+def _make(torch, lbm, q, storage, use_graph, tau=0.6, boxes=_BOXES):
+    desc = lbm.make_desc(q, _N, (WALL,) * 6, tau, storage=storage, wall_u=_lid(0.06),
+                         streaming=lbm.LBM_STREAMING_PINGPONG)
+    blk = lbm.Blocks(desc, stream=torch.cuda.Stream())
+    H = lbm.Hierarchy(blk, boxes, use_graph=use_graph)
+    return blk, H
+
+
+@pytest.mark.parametrize("storage", [0, 2], ids=["f64", "f32s"])
+@pytest.mark.parametrize("q", [19, 27])
+def test_hierarchy_matches_oracle(env, orc, q, storage):
+    torch, lbm = env
+    from oracle.hier import Hierarchy as OH
+    print(f"\n[case] hierarchy q={q} storage={storage}", flush=True)
+    blk, H = _make(torch, lbm, q, storage, use_graph=True)
+    G = orc.Grid(q=q, n=_N, bc=(WALL,) * 6, wall_u=_lid(0.06), tau=0.6)
+    O = OH(G, _BOXES)
+    S = G.equilibrium_state()
+    O.init_from(S)
+    steps = 12
+    H.step_n(steps, steps)
+    bmax_ref = None
+    for k in range(steps):
+        S, bm = O.step(S, k, sensor=(k == steps - 1))
+        if bm is not None:
+            bmax_ref = np.concatenate([b.ravel() for b in bm])
+    bm_gpu, fl_gpu, kk = H.sensor()
+    assert kk == steps
+    tol_f = 1e-13 if storage == 0 else 2e-7
+    ec = np.abs(blk.populations() - S).max()
+    ef = max(np.abs(H.patch_fields(p)[2] - O.patch_fields(p)[2]).max() for p in range(len(_BOXES)))
+    eb = float((np.abs(bm_gpu - bmax_ref) / np.maximum(bmax_ref, 1e-3)).max())
+    print(f"hierarchy q={q} storage={storage}: coarse pop err {ec:.2e}, fine pop err {ef:.2e}, "
+          f"fine block max rel err {eb:.2e}, max M {bmax_ref.max():.3e}")
+    assert ec < tol_f and ef < tol_f and eb < (1e-11 if storage == 0 else 2e-5)
+    ref_flags = np.where(bmax_ref > 1e-3, 1, np.where(bmax_ref < 5e-4, -1, 0))
+    near = (np.abs(bmax_ref - 1e-3) <= 2e-5 * 1e-3) | (np.abs(bmax_ref - 5e-4) <= 2e-5 * 5e-4)
+    assert not ((fl_gpu != ref_flags) & ~near).any()
+    info = H.info()
+    assert info["fine_cells"] == sum(8 * np.prod([hi[a] - lo[a] for a in range(3)]) for lo, hi in _BOXES)
+    assert info["n_eff"] == 0.5 * np.prod(_N) + info["fine_cells"]
+    H.close()
+    blk.close()
+
+
+def test_graph_replay_matches_launches(env):
+    """Steps replayed from the captured graph (in several calls, with host
+    reads in between) give the same bits as launch-by-launch stepping."""
+    torch, lbm = env
+    print("\n[case] hierarchy graph vs eager", flush=True)
+    out = {}
+    for use_graph in (True, False):
+        blk, H = _make(torch, lbm, 19, 2, use_graph)
+        for n in (4, 3, 5, 2):
+            H.step_n(n, 0)
+            _ = H.patch_fields(0)          # eager work and a synchronisation between replays
+        out[use_graph] = (blk.populations(), [H.patch_fields(p)[2] for p in range(len(_BOXES))])
+        H.close()
+        blk.close()
+    assert np.array_equal(out[True][0], out[False][0])
+    for a, b in zip(out[True][1], out[False][1]):
+        assert np.array_equal(a, b)
+
+
+def test_hierarchy_autotune_keeps_results(env):
+    torch, lbm = env
+    print("\n[case] hierarchy autotune", flush=True)
+    res = []
+    for tune in (False, True):
+        blk, H = _make(torch, lbm, 19, 2, use_graph=True)
+        H.step_n(3, 0)
+        if tune:
+            tz, wg = H.autotune(3)
+            print(f"autotune picked tile 8x8x{tz}, {wg} workgroups")
+            assert tz in (2, 4, 8) and wg >= 1
+        H.step_n(5, 0)
+        res.append((blk.populations(), H.patch_fields(2)[2]))
+        H.close()
+        blk.close()
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+
+
+@pytest.mark.parametrize("streaming", ["pingpong", "inplace"])
+def test_single_grid_autotune_keeps_results(env, streaming):
+    """lbm_autotune times the tile widths without changing the state, and
+    every width gives the same bits."""
+    torch, lbm = env
+    print(f"\n[case] autotune 64^3 {streaming}", flush=True)
+    mode = lbm.LBM_STREAMING_PINGPONG if streaming == "pingpong" else lbm.LBM_STREAMING_INPLACE
+    res = []
+    for tune in (False, True):
+        desc = lbm.make_desc(19, (64, 64, 64), (WALL,) * 6, 0.55, storage=lbm.LBM_F32_SHIFTED, wall_u=_lid(0.05),
+                             streaming=mode)
+        blk = lbm.Blocks(desc)
+        blk.step_n(7, 7)
+        if tune:
+            before = blk.populations()
+            tx = blk.autotune(3)
+            print(f"autotune picked tile width {tx}")
+            assert tx in (32, 64, 128) and blk.scheme()["tile_x"] == tx
+            assert np.array_equal(before, blk.populations())
+        blk.step_n(9, 8)
+        res.append((blk.populations(), blk.sensor_flags()[0]))
+        blk.close()
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+
+
+def test_hierarchy_rejects_bad_boxes(env):
+    torch, lbm = env
+    print("\n[case] hierarchy argument checks", flush=True)
+    desc = lbm.make_desc(19, _N, (WALL,) * 6, 0.6, storage=lbm.LBM_F32_SHIFTED, wall_u=_lid(0.06),
+                         streaming=lbm.LBM_STREAMING_PINGPONG)
+    blk = lbm.Blocks(desc)
+    bad = [
+        [((0, 4, 4), (4, 8, 8))],                              # touches the domain face
+        [((4, 4, 4), (7, 8, 8))],                              # extent not a multiple of 4
+        [((4, 4, 4), (8, 8, 8)), ((6, 4, 4), (10, 8, 8))],     # overlap
+    ]
+    for boxes in bad:
+        st, _ = lbm.lbm_hierarchy_required_bytes(blk.h, boxes)
+        assert st == lbm.LBM_EINVAL, boxes
+    blk.close()
+    desc = lbm.make_desc(19, _N, (WALL,) * 6, 0.6, storage=lbm.LBM_F32_SHIFTED, wall_u=_lid(0.06),
+                         streaming=lbm.LBM_STREAMING_INPLACE)
+    blk = lbm.Blocks(desc)
+    st, _ = lbm.lbm_hierarchy_required_bytes(blk.h, _BOXES)
+    assert st == lbm.LBM_ENOTSUP                               # the coarse grid must stream ping-pong
+    blk.close()
