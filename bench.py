@@ -5,7 +5,7 @@ Re 1000, halfway bounce-back walls), with the sensor, its 8^3 block maxima
 and the refine/coarsen flags evaluated at every step.  A "step" is one
 launch of the fused kernel over the whole grid.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--workload cavity128|cavity256|channel256]
+  python bench.py [--steps K] [--warmup W] [--workload cavity128|cavity256|channel256|refined256]
                   [--storage f32|f32s|f64|f16s|bf16s|f16sr|bf16sr] [--lattice 19|27]
                   [--smagorinsky C] [--no-cpu-baseline]
 
@@ -20,6 +20,15 @@ per_kernel_us; "kernel" names the slower one, whose figure is "achieved".
 committed rocprofv3 counter summary, when it was taken on the current kernel
 source.  The CPU baseline is the FP64 oracle timed on the host on a short run
 of the same workload.
+
+--workload refined256: the two-level patch hierarchy.  A 256^3 D3Q19
+cavity (Re 1000) runs 1000 coarse steps, up to 400 cubic patches with fine
+edges from {16, 24, 32, 48} are placed on the blocks its sensor flags
+(seeded), and K coarse steps (2K fine steps, graph-replayed) are timed.
+The value counts lattice updates of both levels; the roofline entry prices
+the fine step (all patches, one persistent launch, timed by the
+hierarchy's autotuner with HIP events) at one read and one write of every
+population of every fine cell.
 """
 import argparse
 import hashlib
@@ -27,6 +36,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -105,6 +116,67 @@ def cpu_baseline(w, tau, sample_steps):
                       f"sensor every step, {dt:.1f} s"}
 
 
+def run_refined(args, lbm, torch):
+    """The two-level hierarchy over the 256^3 cavity; returns the JSON dict."""
+    import lbm_inputs
+    storage = {"f32": lbm.LBM_F32, "f32s": lbm.LBM_F32_SHIFTED, "f64": lbm.LBM_F64}[args.storage]
+    w = lbm_inputs.cavity3d(n=256, storage=args.storage)
+    st, tau = lbm.lbm_tau_from_reynolds(w.lid_speed, w.n_across, w.reynolds)
+    desc = lbm.make_desc(19, w.n, w.bc, tau, storage=storage, wall_u=w.wall_u,
+                         streaming=lbm.LBM_STREAMING_PINGPONG)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    blk = lbm.Blocks(desc, device="cuda:0", stream=stream)
+    blk.step_n(1000, 1000)
+    bm, fl, _, _ = blk.sensor_flags()
+    boxes = lbm_inputs.place_patches(fl == 1, 8, w.n, count=400, seed=7)
+    H = lbm.Hierarchy(blk, boxes, use_graph=True)
+    tx, wg, fine_us = H.autotune(5)
+    H.step_n(args.warmup, 0)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    H.step_n(args.steps, 0)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    H.step_n(2, 2)
+    fbm, ffl, _ = H.sensor()
+    rho, u = blk.macros()
+    info = H.info()
+    coarse_cells, fine_cells = w.cells, info["fine_cells"]
+    updates = (coarse_cells + 2 * fine_cells) * args.steps
+    elem = 8 if storage == lbm.LBM_F64 else 4
+    fine_bytes = 2 * 19 * elem * fine_cells
+    achieved = fine_bytes / (fine_us * 1e-6) / 1e9
+    uniform_fine_updates = 2 * 8 * coarse_cells            # a uniform 512^3 grid, 2 steps per coarse step
+    result = {
+        "metric": "MLUPS (both levels) of the two-level patch hierarchy over the 256^3 cavity",
+        "value": round(updates / (ms * 1e-3) / 1e6, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.storage, "data": "synthetic",
+        "config": {"workload": "refined cavity3d_d3q19_256^3 + fine patches", "patches": len(boxes),
+                   "patch_edges_fine": sorted({2 * (hi[0] - lo[0]) for lo, hi in boxes}),
+                   "fine_cells": fine_cells, "coarse_cells": coarse_cells, "n_eff": info["n_eff"],
+                   "uniform_fine_equivalent_cells": 8 * coarse_cells, "tau_coarse": tau,
+                   "tau_fine": info["tau_fine"], "fine_tile_max": [tx, 8, 8], "fine_workgroups": wg,
+                   "work_vs_uniform_fine": round((coarse_cells + 2 * fine_cells) / uniform_fine_updates, 4)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "patch_step (all patches, one persistent launch)",
+                     "algorithmic_bytes_per_launch": fine_bytes, "per_kernel_us": {"patch_step": round(fine_us, 2)}},
+        "fine_refine_blocks": int((ffl == 1).sum()),
+        "nonfinite": bool(not np.isfinite(rho).all()),
+    }
+    H.close()
+    blk.close()
+    return result
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +200,11 @@ def main():
 
     import torch
     import paper_1507_06767_amd as lbm
+
+    if args.workload == "refined256":
+        result = run_refined(args, lbm, torch)
+        print(json.dumps(result), flush=True)
+        return
 
     storage = {"f32": lbm.LBM_F32, "f32s": lbm.LBM_F32_SHIFTED, "f64": lbm.LBM_F64,
                "f16s": lbm.LBM_F16_SHIFTED, "bf16s": lbm.LBM_BF16_SHIFTED,

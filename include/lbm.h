@@ -328,15 +328,20 @@ lbm_status lbm_hierarchy_patch_fields(lbm_hierarchy *H, int32_t patch, double *r
 
 /* Fine cells and blocks, effective cells N_eff = n_coarse / 2 + n_fine (the
  * cost measure of Sec. 5.2: cells of level i weighted by their update rate),
- * tau_f, and the fine step's tile depth and persistent workgroup count.
+ * tau_f, and the fine step's widest tile and persistent workgroup count.
  * Any pointer may be NULL. */
 lbm_status lbm_hierarchy_info(lbm_hierarchy *H, int64_t *fine_cells, int64_t *fine_blocks, double *n_eff,
-                              double *tau_fine, int32_t *tile_z, int32_t *workgroups);
+                              double *tau_fine, int32_t *tile_x, int32_t *workgroups);
 
-/* Picks the fine step's tile (8 x 8 x tile_z threads, tile_z in 2, 4, 8) and
+/* Picks the fine step's tiling (tiles of W x 8 x 8 cells, 512 threads, W the
+ * widest of 8, 16, 32 not above tile_x that fits the patch row) and its
  * persistent workgroup count (2 to 16 per compute unit) by timing `reps`
- * launches of each; the state is not changed.  Synchronises. */
-lbm_status lbm_hierarchy_autotune(lbm_hierarchy *H, int32_t reps, int32_t *tile_z, int32_t *workgroups);
+ * launches of each with HIP events on the handle's stream; the state is not
+ * changed.  step_us (NULL allowed) receives the chosen configuration's mean
+ * duration of one fine step over all patches, in microseconds.
+ * Synchronises. */
+lbm_status lbm_hierarchy_autotune(lbm_hierarchy *H, int32_t reps, int32_t *tile_x, int32_t *workgroups,
+                                  double *step_us);
 
 /* Releases the hierarchy (host memory and graphs); buffers are untouched. */
 void lbm_destroy_hierarchy(lbm_hierarchy *H);

@@ -152,3 +152,42 @@ def predictor_cavities(count: int, seed: int, n: int = 128, re_range=(1000.0, 50
         lid = lid_range[0] + (lid_range[1] - lid_range[0]) * r[2 * k + 1]
         out.append(cavity3d(n=n, lid=lid, re=re, sensor_every=64, storage=storage))
     return out
+
+
+def place_patches(flagged, block, n, count=400, edges=(16, 24, 32, 48), seed=7, margin=1):
+    """Up to ``count`` non-overlapping cubic patch boxes for a two-level run,
+    placed where a coarse run's sensor flags refinement.  ``flagged`` is the
+    boolean block mask [nbz][nby][nbx] of the coarse grid (blocks of edge
+    ``block``, grid extent ``n`` = (nx, ny, nz)).  Patch k has fine edge
+    edges[r] (r from the stream ``seed``), i.e. a coarse edge of half that,
+    and is centred on a flagged block taken in a seeded order; a box that
+    would overlap an earlier one or come within ``margin`` cells of the
+    domain faces is skipped.  Returns [((lo_x, lo_y, lo_z), (hi_x, hi_y, hi_z))]
+    in coarse cells."""
+    blocks = np.argwhere(np.asarray(flagged, dtype=bool))      # (z, y, x) block indices
+    if len(blocks) == 0:
+        return []
+    order = np.argsort(uniform(seed, len(blocks)), kind="stable")
+    pick = (uniform(seed + 1, len(blocks)) * len(edges)).astype(np.int64)
+    taken = np.zeros((n[2], n[1], n[0]), dtype=bool)
+    boxes = []
+    for k, idx in enumerate(order):
+        ce = edges[pick[k]] // 2
+        bz, by, bx = (int(v) for v in blocks[idx])
+        ce = int(ce)
+        centre = (bx * block + block // 2, by * block + block // 2, bz * block + block // 2)
+        # box origins on multiples of 4 coarse cells, clamped inside the margin
+        lo_min = 4 * ((margin + 3) // 4)
+        lo = [min(max(4 * ((c - ce // 2) // 4), lo_min), 4 * ((n[a] - margin - ce) // 4))
+              for a, c in enumerate(centre)]
+        hi = [lo[a] + ce for a in range(3)]
+        if any(lo[a] < margin or hi[a] > n[a] - margin for a in range(3)):
+            continue
+        sl = (slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
+        if taken[sl].any():
+            continue
+        taken[sl] = True
+        boxes.append((tuple(lo), tuple(hi)))
+        if len(boxes) == count:
+            break
+    return boxes

@@ -118,7 +118,7 @@ def _load_library():
         "lbm_hierarchy_sensor": [H, dp, ctypes.POINTER(ctypes.c_int8), i64p],
         "lbm_hierarchy_patch_fields": [H, ctypes.c_int32, dp, dp, dp],
         "lbm_hierarchy_info": [H, i64p, i64p, dp, dp, i32p, i32p],
-        "lbm_hierarchy_autotune": [H, ctypes.c_int32, i32p, i32p],
+        "lbm_hierarchy_autotune": [H, ctypes.c_int32, i32p, i32p, dp],
     })
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -345,9 +345,10 @@ def lbm_hierarchy_info(H):
 
 
 def lbm_hierarchy_autotune(H, reps: int):
-    tz, wg = ctypes.c_int32(0), ctypes.c_int32(0)
-    st = _lib.lbm_hierarchy_autotune(H, int(reps), ctypes.byref(tz), ctypes.byref(wg))
-    return st, tz.value, wg.value
+    """(status, tile_x, workgroups, fine step microseconds)."""
+    tz, wg, us = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0.0)
+    st = _lib.lbm_hierarchy_autotune(H, int(reps), ctypes.byref(tz), ctypes.byref(wg), ctypes.byref(us))
+    return st, tz.value, wg.value, us.value
 
 
 def lbm_destroy_hierarchy(H):

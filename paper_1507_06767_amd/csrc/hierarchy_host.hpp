@@ -11,7 +11,9 @@
 //   6. restriction: covered coarse cells of Y from the fine state A.
 // Steps 1-6 of two consecutive coarse steps are captured once into a HIP
 // graph per coarse parity and replayed (the kernels' arguments repeat every
-// two coarse steps).
+// two coarse steps).  The fine step walks a tile list, the ghost fill a
+// ghost list and the restriction a list of covered coarse cells, all built
+// here on the host at creation.
 
 #include "patch_kernels.hpp"
 
@@ -24,12 +26,15 @@ struct lbm_hierarchy {
     int64_t total_padded, covered, nblocks, fine_cells, max_patch_cells;
     int64_t pitch;            // elements between fine planes
     size_t elem;              // bytes per stored value
-    size_t meta_patch, meta_blk, meta_cover, meta_stage;   // offsets inside META
+    size_t meta_patch, meta_tile, meta_cover, meta_gdst, meta_gsrc, meta_rc, meta_rf, meta_rp,
+        meta_stage;           // offsets inside META
+    int64_t nghost, ntiles;   // ghost cells; tiles of the current tile list
+    std::vector<PatchTile> tiles;
     size_t bytes[LBM_NHBUF];
     void *buf[LBM_NHBUF];
     int cur;                  // fine state in F_A (0) or F_B (1)
     double tau_f, alpha;
-    int bz, nwg;              // tile depth and persistent workgroups of the fine step
+    int wmax, nwg;            // widest fine tile (8, 16, 32) and persistent workgroups
     bool use_graph;
     hipGraphExec_t graph[2];  // two coarse steps, by the coarse buffer parity
     int64_t step;             // coarse steps taken through the hierarchy
@@ -92,7 +97,8 @@ lbm_status hier_layout(const lbm_blocks *h, int32_t nbox, const lbm_box *boxes, 
         cov += cells / 8;
         maxc = std::max(maxc, cells);
     }
-    if (padded >= (int64_t(1) << 31)) return fail(LBM_ENOTSUP, "patches hold more than 2^31 padded cells");
+    // the ghost list packs a padded index and three interpolation bits in 32 bits
+    if (padded >= (int64_t(1) << 29)) return fail(LBM_ENOTSUP, "patches hold more than 2^29 padded cells");
     H->total_padded = padded;
     H->nblocks = blocks;
     H->covered = cov;
@@ -105,10 +111,16 @@ lbm_status hier_layout(const lbm_blocks *h, int32_t nbox, const lbm_box *boxes, 
     H->bytes[LBM_HBUF_F_A] = H->bytes[LBM_HBUF_F_B] = round_up((size_t)H->q * H->pitch * H->elem, kAlign);
     H->bytes[LBM_HBUF_BLOCK_MAX] = round_up((size_t)blocks * h->L.cbytes, kAlign);
     H->bytes[LBM_HBUF_FLAGS] = round_up((size_t)blocks, kAlign);
+    H->nghost = padded - 8 * cov;
     H->meta_patch = 0;
-    H->meta_blk = round_up((size_t)nbox * sizeof(PatchRec), kAlign);
-    H->meta_cover = H->meta_blk + round_up((size_t)blocks * 4, kAlign);
-    H->meta_stage = H->meta_cover + round_up((size_t)h->L.cells * 4, kAlign);
+    H->meta_tile = round_up((size_t)nbox * sizeof(PatchRec), kAlign);
+    H->meta_cover = H->meta_tile + round_up((size_t)blocks * sizeof(PatchTile), kAlign);   // <= one tile per block
+    H->meta_gdst = H->meta_cover + round_up((size_t)h->L.cells * 4, kAlign);
+    H->meta_gsrc = H->meta_gdst + round_up((size_t)H->nghost * 4, kAlign);
+    H->meta_rc = H->meta_gsrc + round_up((size_t)H->nghost * 4, kAlign);
+    H->meta_rf = H->meta_rc + round_up((size_t)cov * 4, kAlign);
+    H->meta_rp = H->meta_rf + round_up((size_t)cov * 4, kAlign);
+    H->meta_stage = H->meta_rp + round_up((size_t)cov * 4, kAlign);
     H->bytes[LBM_HBUF_META] = H->meta_stage + round_up((size_t)maxc * (H->q + 4) * 8, kAlign);
     H->bmax_host.assign((size_t)blocks * h->L.cbytes, 0);
     return LBM_OK;
@@ -123,9 +135,9 @@ PatchArgs<C> patch_args(lbm_hierarchy *H, const void *src, void *dst) {
     a.pitch = H->pitch;
     char *meta = static_cast<char *>(H->buf[LBM_HBUF_META]);
     a.patch = reinterpret_cast<const PatchRec *>(meta + H->meta_patch);
-    a.blk_patch = reinterpret_cast<const int *>(meta + H->meta_blk);
+    a.tile = reinterpret_cast<const PatchTile *>(meta + H->meta_tile);
     a.npatch = H->npatch;
-    a.nblocks = (int)H->nblocks;
+    a.ntiles = (int)H->ntiles;
     for (int i = 0; i < kMaxQ; ++i) a.shift[i] = C(0);
     auto fill_shift = [&]<int Q>() {
         static_for<0, Q>([&](auto ic) {
@@ -176,17 +188,63 @@ void with_hier_types(lbm_hierarchy *H, F &&f) {
 
 void *fine_buf(lbm_hierarchy *H, int which) { return H->buf[which ? LBM_HBUF_F_B : LBM_HBUF_F_A]; }
 
+PatchLists patch_lists(lbm_hierarchy *H) {
+    char *meta = static_cast<char *>(H->buf[LBM_HBUF_META]);
+    PatchLists L;
+    L.gdst = reinterpret_cast<const uint32_t *>(meta + H->meta_gdst);
+    L.gsrc = reinterpret_cast<const int *>(meta + H->meta_gsrc);
+    L.nghost = H->nghost;
+    L.rc = reinterpret_cast<const int *>(meta + H->meta_rc);
+    L.rf = reinterpret_cast<const int *>(meta + H->meta_rf);
+    L.rp = reinterpret_cast<const int *>(meta + H->meta_rp);
+    L.covered = H->covered;
+    return L;
+}
+
+// Tiles of the fine step: per patch, rows of 8 x 8 x 8 blocks cut along x
+// into the widest of 32, 16, 8 cells (at most wmax) that still fit.
+void build_tiles(lbm_hierarchy *H, int wmax) {
+    H->tiles.clear();
+    for (int p = 0; p < H->npatch; ++p) {
+        const PatchRec &r = H->rec[p];
+        const int nbx = r.e[0] / 8, nby = r.e[1] / 8;
+        for (int bz = 0; bz < r.e[2] / 8; ++bz)
+            for (int by = 0; by < nby; ++by)
+                for (int x0 = 0; x0 < r.e[0];) {
+                    const int left = r.e[0] - x0;
+                    const int w = (wmax >= 32 && left >= 32) ? 32 : ((wmax >= 16 && left >= 16) ? 16 : 8);
+                    PatchTile t{};
+                    t.patch = p;
+                    t.x0 = x0;
+                    t.y0 = 8 * by;
+                    t.z0 = 8 * bz;
+                    t.w = w;
+                    t.blk = r.blk0 + (bz * nby + by) * nbx + x0 / 8;
+                    H->tiles.push_back(t);
+                    x0 += w;
+                }
+    }
+    H->ntiles = (int64_t)H->tiles.size();
+    H->wmax = wmax;
+}
+
+hipError_t upload_tiles(lbm_hierarchy *H) {
+    char *meta = static_cast<char *>(H->buf[LBM_HBUF_META]);
+    return hipMemcpyAsync(meta + H->meta_tile, H->tiles.data(), H->tiles.size() * sizeof(PatchTile),
+                          hipMemcpyHostToDevice, H->coarse->stream);
+}
+
 void hier_fine_step(lbm_hierarchy *H, const void *src, void *dst, bool sensor) {
     with_hier_types(H, [&]<int Q, typename T, typename C, bool SH>() {
-        PatchLaunch l{H->coarse->stream, sensor, H->coarse->d.sensor_kind, H->bz, H->nwg};
+        PatchLaunch l{H->coarse->stream, sensor, H->coarse->d.sensor_kind, H->nwg};
         launch_patch_step<Q, T, C, SH>(patch_args<C>(H, src, dst), l);
     });
 }
 
-void hier_fill(lbm_hierarchy *H, void *state, const void *s0, const void *s1, double w1, bool all_cells) {
+void hier_ghosts(lbm_hierarchy *H, void *state, const void *s0, const void *s1, double w1) {
     with_hier_types(H, [&]<int Q, typename T, typename C, bool SH>() {
-        launch_patch_fill<Q, T, C, SH>(patch_args<C>(H, state, state), coarse_view<C>(H, s0, s1, w1, nullptr),
-                                       state, H->total_padded, all_cells, H->coarse->stream);
+        launch_patch_ghosts<Q, T, C, SH>(patch_args<C>(H, state, state), coarse_view<C>(H, s0, s1, w1, nullptr),
+                                         state, patch_lists(H), H->coarse->stream);
     });
 }
 
@@ -196,18 +254,18 @@ void hier_coarse_step(lbm_hierarchy *H, bool sens) {
     void *X = state_ptr(h);
     void *Y = h->d.buf[h->cur ? LBM_BUF_F_A : LBM_BUF_F_B];
     void *A = fine_buf(H, H->cur), *B = fine_buf(H, H->cur ^ 1);
-    hier_fill(H, A, X, X, 0.0, false);
+    hier_ghosts(H, A, X, X, 0.0);
     hier_fine_step(H, A, B, false);
     const int64_t step = h->step + 1;
     launch_step_any(h, sens);
     h->cur ^= 1;
     h->step = step;
     if (sens) h->last_sensor_step = step;
-    hier_fill(H, B, X, Y, 0.5, false);
+    hier_ghosts(H, B, X, Y, 0.5);
     hier_fine_step(H, B, A, sens);
     with_hier_types(H, [&]<int Q, typename T, typename C, bool SH>() {
         launch_patch_restrict<Q, T, C, SH>(patch_args<C>(H, A, A), coarse_view<C>(H, Y, Y, 0.0, Y), A,
-                                           H->covered, h->stream);
+                                           patch_lists(H), h->stream);
     });
     H->step += 1;
     if (sens) H->last_sensor_step = H->step;
@@ -276,39 +334,94 @@ lbm_status lbm_create_hierarchy(lbm_blocks *coarse, int32_t nbox, const lbm_box 
     }
     H->coarse = coarse;
     H->cur = 0;
-    H->bz = 8;
-    H->nwg = (int)std::min<int64_t>(H->nblocks, 8 * kHierCUs);
+    build_tiles(H, 32);
+    H->nwg = (int)std::min<int64_t>(H->ntiles, 8 * kHierCUs);
     H->use_graph = use_graph != 0 && coarse->stream != nullptr;
     H->graph[0] = H->graph[1] = nullptr;
     H->step = 0;
     H->last_sensor_step = -1;
-    // tables: patch records, block -> patch, coarse cover map
-    std::vector<int> blk((size_t)H->nblocks);
-    for (int p = 0; p < H->npatch; ++p) {
-        const PatchRec &r = H->rec[p];
-        const int64_t nb = (int64_t)r.e[0] * r.e[1] * r.e[2] / 512;
-        for (int64_t k = 0; k < nb; ++k) blk[r.blk0 + k] = p;
-    }
+    // coarse cover map
+    const int nx = coarse->d.extent[0], ny = coarse->d.extent[1];
     std::vector<int> cover((size_t)coarse->L.cells, -1);
     for (int p = 0; p < H->npatch; ++p) {
         const lbm_box &b = H->boxes[p];
         for (int z = b.lo[2]; z < b.hi[2]; ++z)
             for (int y = b.lo[1]; y < b.hi[1]; ++y)
-                for (int x = b.lo[0]; x < b.hi[0]; ++x)
-                    cover[((size_t)z * coarse->d.extent[1] + y) * coarse->d.extent[0] + x] = p;
+                for (int x = b.lo[0]; x < b.hi[0]; ++x) cover[((size_t)z * ny + y) * nx + x] = p;
+    }
+    // ghost list: copy from the patch that holds the cell, else the low corner
+    // of the coarse interpolation stencil and the 3/4-weight bits
+    std::vector<uint32_t> gdst;
+    std::vector<int> gsrc;
+    gdst.reserve(H->nghost);
+    gsrc.reserve(H->nghost);
+    for (int p = 0; p < H->npatch; ++p) {
+        const PatchRec &r = H->rec[p];
+        const int P[3] = {r.e[0] + 2, r.e[1] + 2, r.e[2] + 2};
+        for (int pz = 0; pz < P[2]; ++pz)
+            for (int py = 0; py < P[1]; ++py)
+                for (int px = 0; px < P[0]; ++px) {
+                    const bool ghost = px == 0 || py == 0 || pz == 0 || px == P[0] - 1 || py == P[1] - 1 ||
+                                       pz == P[2] - 1;
+                    if (!ghost) continue;
+                    const int g[3] = {r.o[0] + px - 1, r.o[1] + py - 1, r.o[2] + pz - 1};
+                    const uint32_t dst = (uint32_t)(r.off + ((int64_t)pz * P[1] + py) * P[0] + px);
+                    const int owner = cover[((size_t)(g[2] >> 1) * ny + (g[1] >> 1)) * nx + (g[0] >> 1)];
+                    if (owner >= 0) {
+                        const PatchRec &o = H->rec[owner];
+                        const int64_t src = o.off + ((int64_t)(g[2] - o.o[2] + 1) * (o.e[1] + 2) + (g[1] - o.o[1] + 1)) *
+                                                        (o.e[0] + 2) + (g[0] - o.o[0] + 1);
+                        gdst.push_back(dst);
+                        gsrc.push_back((int)src);
+                    } else {
+                        // centre (g + 1/2) / 2 - 1/2: even g -> g/2 - 1 + 3/4, odd g -> (g - 1)/2 + 1/4
+                        uint32_t code = 0;
+                        int b[3];
+                        for (int a = 0; a < 3; ++a) {
+                            const bool even = (g[a] & 1) == 0;
+                            b[a] = even ? g[a] / 2 - 1 : (g[a] - 1) / 2;
+                            if (even) code |= 1u << (29 + a);
+                        }
+                        const int64_t base = ((int64_t)b[2] * ny + b[1]) * nx + b[0];
+                        gdst.push_back(dst | code);
+                        gsrc.push_back((int)(-base - 1));
+                    }
+                }
+    }
+    // restriction list: each covered coarse cell, its fine group and patch
+    std::vector<int> rc, rf, rp;
+    for (int p = 0; p < H->npatch; ++p) {
+        const PatchRec &r = H->rec[p];
+        const lbm_box &b = H->boxes[p];
+        for (int z = b.lo[2]; z < b.hi[2]; ++z)
+            for (int y = b.lo[1]; y < b.hi[1]; ++y)
+                for (int x = b.lo[0]; x < b.hi[0]; ++x) {
+                    rc.push_back((int)(((int64_t)z * ny + y) * nx + x));
+                    const int fx = 2 * (x - b.lo[0]) + 1, fy = 2 * (y - b.lo[1]) + 1, fz = 2 * (z - b.lo[2]) + 1;
+                    rf.push_back((int)(r.off + ((int64_t)fz * (r.e[1] + 2) + fy) * (r.e[0] + 2) + fx));
+                    rp.push_back(p);
+                }
     }
     char *meta = static_cast<char *>(H->buf[LBM_HBUF_META]);
     hipStream_t s = coarse->stream;
     hipError_t e = hipMemcpyAsync(meta + H->meta_patch, H->rec.data(), H->rec.size() * sizeof(PatchRec),
                                   hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(meta + H->meta_blk, blk.data(), blk.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = upload_tiles(H);
     if (e == hipSuccess)
         e = hipMemcpyAsync(meta + H->meta_cover, cover.data(), cover.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(meta + H->meta_gdst, gdst.data(), gdst.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(meta + H->meta_gsrc, gsrc.data(), gsrc.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(meta + H->meta_rc, rc.data(), rc.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(meta + H->meta_rf, rf.data(), rf.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(meta + H->meta_rp, rp.data(), rp.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && (int64_t)gdst.size() != H->nghost) e = hipErrorInvalidValue;
     if (e == hipSuccess) {
         // the initial fine state: every padded cell interpolated from the coarse state
         void *X = state_ptr(coarse);
-        hier_fill(H, fine_buf(H, 0), X, X, 0.0, true);
+        with_hier_types(H, [&]<int Q, typename T, typename C, bool SH>() {
+            launch_patch_init<Q, T, C, SH>(patch_args<C>(H, fine_buf(H, 0), fine_buf(H, 0)),
+                                           coarse_view<C>(H, X, X, 0.0, nullptr), fine_buf(H, 0), H->total_padded, s);
+        });
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -393,7 +506,7 @@ lbm_status lbm_hierarchy_patch_fields(lbm_hierarchy *H, int32_t patch, double *r
 }
 
 lbm_status lbm_hierarchy_info(lbm_hierarchy *H, int64_t *fine_cells, int64_t *fine_blocks, double *n_eff,
-                              double *tau_fine, int32_t *tile_z, int32_t *workgroups) {
+                              double *tau_fine, int32_t *tile_x, int32_t *workgroups) {
     lbm_status st = hier_check(H);
     if (st != LBM_OK) return st;
     if (fine_cells) *fine_cells = H->fine_cells;
@@ -402,12 +515,13 @@ lbm_status lbm_hierarchy_info(lbm_hierarchy *H, int64_t *fine_cells, int64_t *fi
     // coarse level (i = 0) steps once per two fine steps (L = 1)
     if (n_eff) *n_eff = 0.5 * (double)H->coarse->L.cells + (double)H->fine_cells;
     if (tau_fine) *tau_fine = H->tau_f;
-    if (tile_z) *tile_z = H->bz;
+    if (tile_x) *tile_x = H->wmax;
     if (workgroups) *workgroups = H->nwg;
     return LBM_OK;
 }
 
-lbm_status lbm_hierarchy_autotune(lbm_hierarchy *H, int32_t reps, int32_t *tile_z, int32_t *workgroups) {
+lbm_status lbm_hierarchy_autotune(lbm_hierarchy *H, int32_t reps, int32_t *tile_x, int32_t *workgroups,
+                                  double *step_us) {
     lbm_status st = hier_check(H);
     if (st != LBM_OK) return st;
     if (reps < 1) return fail(LBM_EINVAL, "reps = %d < 1", reps);
@@ -420,14 +534,15 @@ lbm_status lbm_hierarchy_autotune(lbm_hierarchy *H, int32_t reps, int32_t *tile_
     const void *src = fine_buf(H, H->cur);
     void *dst = fine_buf(H, H->cur ^ 1);
     float best = 1e30f;
-    int best_bz = H->bz, best_nwg = H->nwg;
-    const int bzs[3] = {2, 4, 8};
+    int best_w = H->wmax, best_nwg = H->nwg;
     const int per_cu[4] = {2, 4, 8, 16};
     hipError_t e = hipSuccess;
-    for (int bz : bzs) {
+    for (int w : {8, 16, 32}) {
+        build_tiles(H, w);
+        e = upload_tiles(H);
+        if (e != hipSuccess) break;
         for (int pc : per_cu) {
-            H->bz = bz;
-            H->nwg = (int)std::min<int64_t>(H->nblocks, (int64_t)pc * kHierCUs);
+            H->nwg = (int)std::min<int64_t>(H->ntiles, (int64_t)pc * kHierCUs);
             hier_fine_step(H, src, dst, false);   // warm-up
             e = hipEventRecord(e0, s);
             for (int r = 0; r < reps && e == hipSuccess; ++r) hier_fine_step(H, src, dst, false);
@@ -438,7 +553,7 @@ lbm_status lbm_hierarchy_autotune(lbm_hierarchy *H, int32_t reps, int32_t *tile_
             if (e != hipSuccess) break;
             if (ms < best) {
                 best = ms;
-                best_bz = bz;
+                best_w = w;
                 best_nwg = H->nwg;
             }
         }
@@ -446,17 +561,20 @@ lbm_status lbm_hierarchy_autotune(lbm_hierarchy *H, int32_t reps, int32_t *tile_
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    H->bz = best_bz;
+    build_tiles(H, best_w);
+    if (e == hipSuccess) e = upload_tiles(H);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     H->nwg = best_nwg;
-    // graphs captured with the old tile shape are stale
+    // graphs captured with the old tile list are stale
     for (int p = 0; p < 2; ++p)
         if (H->graph[p]) {
             hipGraphExecDestroy(H->graph[p]);
             H->graph[p] = nullptr;
         }
     if (e != hipSuccess) return fail(LBM_EHIP, "autotune: %s", hipGetErrorString(e));
-    if (tile_z) *tile_z = H->bz;
+    if (tile_x) *tile_x = H->wmax;
     if (workgroups) *workgroups = H->nwg;
+    if (step_us) *step_us = 1e3 * (double)best / reps;
     return LBM_OK;
 }
 

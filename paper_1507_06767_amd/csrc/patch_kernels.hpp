@@ -39,14 +39,25 @@ struct PatchRec {
 };
 static_assert(sizeof(PatchRec) == 48, "PatchRec layout");
 
+// A tile of the fine step: W x 8 x 8 cells (W = 8, 16 or 32) of one patch,
+// i.e. W/8 sensor blocks side by side along x.
+struct PatchTile {
+    int patch;      // patch index
+    int x0, y0, z0; // first interior cell (multiples of 8; x0 + W <= e_x)
+    int w;          // W
+    int blk;        // sensor block of the tile's first 8 x-cells
+    int pad[2];
+};
+static_assert(sizeof(PatchTile) == 32, "PatchTile layout");
+
 template <typename C>
 struct PatchArgs {
     const void *src;          // fine state read by the step (padded planes)
     void *dst;                // fine state written by the step
     int64_t pitch;            // elements between fine planes
     const PatchRec *patch;    // [npatch]
-    const int *blk_patch;     // [nblocks]: patch of each sensor block
-    int npatch, nblocks;
+    const PatchTile *tile;    // [ntiles]
+    int npatch, ntiles;
     C shift[kMaxQ];           // w_i rho0 in C
     C rho0, omega;            // fine relaxation rate 1 / tau_f
     double theta_r, theta_c;
@@ -118,27 +129,29 @@ __device__ __forceinline__ int64_t padded_index(const PatchRec &p, int x, int y,
     return (int64_t)p.off + ((int64_t)(z + 1) * (p.e[1] + 2) + (y + 1)) * (p.e[0] + 2) + (x + 1);
 }
 
-// One fine step of every patch.  A workgroup of 8 x 8 x BZ threads owns one
-// 8^3 sensor block at a time (each thread marches 8/BZ z-slices) and loops
-// over the blocks of all patches with a fixed stride (a persistent launch of
-// fewer workgroups than blocks): pull-stream from the padded neighbours,
-// BGK collision, and on sensor steps the block maximum and flag, reduced in
-// the workgroup without atomics.
-template <int Q, typename T, typename C, bool SH, bool SENSOR, int SKIND, int BZ>
-__global__ __launch_bounds__(64 * BZ) void patch_step(const PatchArgs<C> a) {
-    static_assert(Lattice<Q>::D == 3 && 8 % BZ == 0, "3D patches, BZ divides 8");
-    const int tx = threadIdx.x & 7, ty = (threadIdx.x >> 3) & 7, tz = threadIdx.x >> 6;
-    __shared__ C red[BZ];
-    for (int b = blockIdx.x; b < a.nblocks; b += gridDim.x) {
-        const PatchRec p = a.patch[a.blk_patch[b]];
-        const int lb = b - p.blk0;
-        const int nbx = p.e[0] >> 3, nby = p.e[1] >> 3;
-        const int bx = lb % nbx, by = (lb / nbx) % nby, bz = lb / (nbx * nby);
+// One fine step of every patch.  A workgroup of 512 threads owns one tile
+// (W x 8 x 8 cells) at a time: thread t takes x = t mod W, y = (t / W) mod 8
+// and marches z from t / 8W in steps of 64 / W, so a wave reads W
+// consecutive cells of 64 / W rows (rows of up to 128 bytes in float32).  It
+// loops over the tiles of all patches with a fixed stride (a persistent
+// launch of fewer workgroups than tiles): pull-stream from the padded
+// neighbours, BGK collision, and on sensor steps the maxima and flags of the
+// tile's W/8 blocks, reduced in the workgroup without atomics.
+template <int Q, typename T, typename C, bool SH, bool SENSOR, int SKIND>
+__global__ __launch_bounds__(512) void patch_step(const PatchArgs<C> a) {
+    static_assert(Lattice<Q>::D == 3, "3D patches");
+    __shared__ C red[8][4];      // [wave][block of the tile]
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    for (int k = blockIdx.x; k < a.ntiles; k += gridDim.x) {
+        const PatchTile tl = a.tile[k];
+        const PatchRec p = a.patch[tl.patch];
+        const int W = tl.w;
+        const int x = t % W, y = (t / W) & 7, zstep = 64 / W;
         const int64_t sy = p.e[0] + 2, sz = sy * (p.e[1] + 2);
         C m = C(0);
 #pragma unroll 1
-        for (int zz = tz; zz < 8; zz += BZ) {
-            const int64_t c = padded_index(p, 8 * bx + tx, 8 * by + ty, 8 * bz + zz);
+        for (int zz = t / (8 * W); zz < 8; zz += zstep) {
+            const int64_t c = padded_index(p, tl.x0 + x, tl.y0 + y, tl.z0 + zz);
             C d[Q];
             static_for<0, Q>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
@@ -166,18 +179,21 @@ __global__ __launch_bounds__(64 * BZ) void patch_step(const PatchArgs<C> a) {
             if constexpr (SENSOR) m = nan_max(m, SKIND == kSensorL2 ? num / den : kkn * C(1.0 / Q));
         }
         if constexpr (SENSOR) {
-            // a wave is one 8 x 8 slice: reduce it with shuffles, then the BZ waves in LDS
+            // lane bits 3.. log2(W)-1 number the block of the lane's x: reduce
+            // over every other lane bit, then over the 8 waves in LDS
 #pragma unroll
-            for (int s = 1; s < 64; s <<= 1) m = nan_max(m, static_cast<C>(__shfl_xor(m, s)));
-            if ((threadIdx.x & 63) == 0) red[tz] = m;
+            for (int s = 1; s < 64; s <<= 1)
+                if ((s & (W - 8)) == 0) m = nan_max(m, static_cast<C>(__shfl_xor(m, s)));
+            if ((lane & 7) == 0 && lane < W) red[wave][lane >> 3] = m;
             __syncthreads();
-            if (threadIdx.x == 0) {
-                C M = red[0];
-                for (int k = 1; k < BZ; ++k) M = nan_max(M, red[k]);
+            if (t < W / 8) {
+                C M = red[0][t];
+                for (int w = 1; w < 8; ++w) M = nan_max(M, red[w][t]);
                 M = finish<SKIND>(M);
-                a.block_max[b] = M;
+                a.block_max[tl.blk + t] = M;
                 const double Md = static_cast<double>(M);
-                a.flags[b] = (!(Md == Md) || Md == HUGE_VAL) ? 2 : (Md > a.theta_r ? 1 : (Md < a.theta_c ? -1 : 0));
+                a.flags[tl.blk + t] =
+                    (!(Md == Md) || Md == HUGE_VAL) ? 2 : (Md > a.theta_r ? 1 : (Md < a.theta_c ? -1 : 0));
             }
             __syncthreads();
         }
@@ -193,7 +209,9 @@ __device__ __forceinline__ void coarse_to_fine(const CoarseView<C> &v, const C (
     const int x0 = (int)floor(px), y0 = (int)floor(py), z0 = (int)floor(pz);
     const C fx = px - C(x0), fy = py - C(y0), fz = pz - C(z0);
     static_for<0, Q>([&](auto ic) { d[decltype(ic)::value] = C(0); });
-#pragma unroll
+    // corners one at a time: q accumulators and q loads in flight keep the
+    // register count (and so the occupancy) of this gather-bound loop moderate
+#pragma unroll 1
     for (int k = 0; k < 8; ++k) {
         const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
         const C w = (dx ? fx : C(1) - fx) * (dy ? fy : C(1) - fy) * (dz ? fz : C(1) - fz);
@@ -213,12 +231,44 @@ __device__ __forceinline__ void coarse_to_fine(const CoarseView<C> &v, const C (
     });
 }
 
-// Ghost layer of every patch (or, with all_cells, every padded cell: the
-// initial state).  One thread per padded cell; a ghost cell copies from the
-// patch whose interior holds it, else interpolates the coarse level.
+// Ghost layers from the precomputed list: entry k fills padded cell
+// gdst[k] & 0x1FFFFFFF; gsrc[k] >= 0 is the padded cell of an abutting
+// patch to copy, else -gsrc[k] - 1 is the coarse cell at the low corner of
+// the interpolation stencil, and bit 29 + a of gdst[k] is set when the
+// weight of the upper neighbour along axis a is 3/4 (else 1/4).
 template <int Q, typename T, typename C, bool SH>
-__global__ __launch_bounds__(256) void patch_fill(const PatchArgs<C> a, const CoarseView<C> v, void *state, int64_t total_padded,
-                           int all_cells) {
+__global__ __launch_bounds__(256) void patch_ghosts(const PatchArgs<C> a, const CoarseView<C> v, void *state,
+                                                    const uint32_t *gdst, const int *gsrc, int64_t nghost) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nghost) return;
+    const uint32_t code = gdst[k];
+    const int64_t g = code & 0x1FFFFFFFu;
+    const int src = gsrc[k];
+    if (src >= 0) {
+        static_for<0, Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            static_cast<T *>(state)[i * a.pitch + g] = static_cast<const T *>(state)[i * a.pitch + src];
+        });
+        return;
+    }
+    const int64_t base = -(int64_t)src - 1;
+    const int x0 = (int)(base % v.nx), y0 = (int)((base / v.nx) % v.ny), z0 = (int)(base / ((int64_t)v.nx * v.ny));
+    const C fx = (code >> 29) & 1u ? C(0.75) : C(0.25);
+    const C fy = (code >> 30) & 1u ? C(0.75) : C(0.25);
+    const C fz = (code >> 31) & 1u ? C(0.75) : C(0.25);
+    C d[Q];
+    coarse_to_fine<Q, T, C, SH>(v, a.shift, a.rho0, C(x0) + fx, C(y0) + fy, C(z0) + fz, d);
+    static_for<0, Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        store_dev<T>(state, i * a.pitch + g, d[i], a.shift[i], SH);
+    });
+}
+
+// Every padded cell of every patch interpolated from the coarse level: the
+// initial fine state.  One thread per padded cell.
+template <int Q, typename T, typename C, bool SH>
+__global__ __launch_bounds__(256) void patch_init(const PatchArgs<C> a, const CoarseView<C> v, void *state,
+                                                  int64_t total_padded) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= total_padded) return;
     int lo = 0, hi = a.npatch - 1;               // last patch with off <= g
@@ -230,21 +280,7 @@ __global__ __launch_bounds__(256) void patch_fill(const PatchArgs<C> a, const Co
     const int64_t r = g - p.off;
     const int px = (int)(r % (p.e[0] + 2)), py = (int)((r / (p.e[0] + 2)) % (p.e[1] + 2));
     const int pz = (int)(r / ((int64_t)(p.e[0] + 2) * (p.e[1] + 2)));
-    const bool ghost = px == 0 || py == 0 || pz == 0 || px == p.e[0] + 1 || py == p.e[1] + 1 || pz == p.e[2] + 1;
-    if (!ghost && !all_cells) return;
     const int gx = p.o[0] + px - 1, gy = p.o[1] + py - 1, gz = p.o[2] + pz - 1;   // global fine cell
-    if (ghost && !all_cells) {
-        const int owner = v.cover[((int64_t)(gz >> 1) * v.ny + (gy >> 1)) * v.nx + (gx >> 1)];
-        if (owner >= 0) {
-            const PatchRec q = a.patch[owner];
-            const int64_t from = padded_index(q, gx - q.o[0], gy - q.o[1], gz - q.o[2]);
-            static_for<0, Q>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                static_cast<T *>(state)[i * a.pitch + g] = static_cast<const T *>(state)[i * a.pitch + from];
-            });
-            return;
-        }
-    }
     // fine cell centre in coarse-index coordinates: (g + 1/2) / 2 - 1/2
     C d[Q];
     coarse_to_fine<Q, T, C, SH>(v, a.shift, a.rho0, C(0.5) * C(gx) - C(0.25), C(0.5) * C(gy) - C(0.25),
@@ -257,25 +293,22 @@ __global__ __launch_bounds__(256) void patch_fill(const PatchArgs<C> a, const Co
 
 // Restriction: every coarse cell covered by a patch takes the mean of its 8
 // fine cells, rescaled to the coarse level: d_c = deq + (d - deq) / alpha.
-// One thread per covered coarse cell.
+// One thread per entry of the precomputed list: coarse cell rc[k], padded
+// cell rf[k] of the fine group's low corner, patch rp[k].
 template <int Q, typename T, typename C, bool SH>
-__global__ __launch_bounds__(256) void patch_restrict(const PatchArgs<C> a, const CoarseView<C> v, const void *fine, int64_t covered) {
+__global__ __launch_bounds__(256) void patch_restrict(const PatchArgs<C> a, const CoarseView<C> v, const void *fine,
+                                                      const int *rc, const int *rf, const int *rp,
+                                                      int64_t covered) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= covered) return;
-    int lo = 0, hi = a.npatch - 1;               // last patch with coff <= t
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (a.patch[mid].coff <= t) lo = mid; else hi = mid - 1;
-    }
-    const PatchRec p = a.patch[lo];
-    const int64_t r = t - p.coff;
-    const int cex = p.e[0] >> 1, cey = p.e[1] >> 1;
-    const int cx = (int)(r % cex), cy = (int)((r / cex) % cey), cz = (int)(r / ((int64_t)cex * cey));
+    const PatchRec &p = a.patch[rp[t]];
+    const int64_t sy = p.e[0] + 2, sz = sy * (p.e[1] + 2);
+    const int64_t c0 = rf[t];
     C d[Q];
     static_for<0, Q>([&](auto ic) { d[decltype(ic)::value] = C(0); });
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const int64_t c = padded_index(p, 2 * cx + (k & 1), 2 * cy + ((k >> 1) & 1), 2 * cz + (k >> 2));
+        const int64_t c = c0 + (k & 1) + ((k >> 1) & 1) * sy + (k >> 2) * sz;
         static_for<0, Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             d[i] += load_dev<T>(fine, i * a.pitch + c, a.shift[i], SH);
@@ -283,7 +316,7 @@ __global__ __launch_bounds__(256) void patch_restrict(const PatchArgs<C> a, cons
     }
     static_for<0, Q>([&](auto ic) { d[decltype(ic)::value] *= C(0.125); });
     const Moments<Q, C> mo = moments_of<Q>(d, a.rho0);
-    const int64_t cc = ((int64_t)(p.o[2] / 2 + cz) * v.ny + (p.o[1] / 2 + cy)) * v.nx + (p.o[0] / 2 + cx);
+    const int64_t cc = rc[t];
     const C inv_alpha = C(1) / v.alpha;
     static_for<0, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
@@ -332,51 +365,62 @@ struct PatchLaunch {
     hipStream_t stream;
     bool sensor;
     int sensor_kind;
-    int bz;          // tile depth: 8 x 8 x bz threads per workgroup
     int nwg;         // workgroups of the persistent launch
+};
+
+// Lists the fine step and the coupling kernels read (device pointers).
+struct PatchLists {
+    const uint32_t *gdst;
+    const int *gsrc;
+    int64_t nghost;
+    const int *rc, *rf, *rp;
+    int64_t covered;
 };
 
 template <int Q, typename T, typename C, bool SH>
 void launch_patch_step(const PatchArgs<C> &a, const PatchLaunch &l);
 template <int Q, typename T, typename C, bool SH>
-void launch_patch_fill(const PatchArgs<C> &a, const CoarseView<C> &v, void *state, int64_t total_padded,
-                       bool all_cells, hipStream_t st);
+void launch_patch_init(const PatchArgs<C> &a, const CoarseView<C> &v, void *state, int64_t total_padded,
+                       hipStream_t st);
 template <int Q, typename T, typename C, bool SH>
-void launch_patch_restrict(const PatchArgs<C> &a, const CoarseView<C> &v, const void *fine, int64_t covered,
+void launch_patch_ghosts(const PatchArgs<C> &a, const CoarseView<C> &v, void *state, const PatchLists &L,
+                         hipStream_t st);
+template <int Q, typename T, typename C, bool SH>
+void launch_patch_restrict(const PatchArgs<C> &a, const CoarseView<C> &v, const void *fine, const PatchLists &L,
                            hipStream_t st);
 template <int Q, typename T, typename C, bool SH>
 void launch_patch_macros(const PatchArgs<C> &a, const void *state, int patch, int64_t cells, double *rho,
                          double *u, double *f, hipStream_t st);
 
 #ifdef LBM_PATCH_DEFINITIONS
-template <int Q, typename T, typename C, bool SH, bool S, int K>
-void launch_patch_bz(const PatchArgs<C> &a, const PatchLaunch &l) {
-    switch (l.bz) {
-        case 2: hipLaunchKernelGGL((patch_step<Q, T, C, SH, S, K, 2>), dim3(l.nwg), dim3(128), 0, l.stream, a); break;
-        case 4: hipLaunchKernelGGL((patch_step<Q, T, C, SH, S, K, 4>), dim3(l.nwg), dim3(256), 0, l.stream, a); break;
-        default: hipLaunchKernelGGL((patch_step<Q, T, C, SH, S, K, 8>), dim3(l.nwg), dim3(512), 0, l.stream, a); break;
-    }
-}
-
 template <int Q, typename T, typename C, bool SH>
 void launch_patch_step(const PatchArgs<C> &a, const PatchLaunch &l) {
-    if (!l.sensor) launch_patch_bz<Q, T, C, SH, false, kSensorL2>(a, l);
-    else if (l.sensor_kind == kSensorL2) launch_patch_bz<Q, T, C, SH, true, kSensorL2>(a, l);
-    else launch_patch_bz<Q, T, C, SH, true, kSensorKKn>(a, l);
+    const dim3 g(l.nwg), b(512);
+    if (!l.sensor) hipLaunchKernelGGL((patch_step<Q, T, C, SH, false, kSensorL2>), g, b, 0, l.stream, a);
+    else if (l.sensor_kind == kSensorL2) hipLaunchKernelGGL((patch_step<Q, T, C, SH, true, kSensorL2>), g, b, 0, l.stream, a);
+    else hipLaunchKernelGGL((patch_step<Q, T, C, SH, true, kSensorKKn>), g, b, 0, l.stream, a);
 }
 
 template <int Q, typename T, typename C, bool SH>
-void launch_patch_fill(const PatchArgs<C> &a, const CoarseView<C> &v, void *state, int64_t total_padded,
-                       bool all_cells, hipStream_t st) {
-    hipLaunchKernelGGL((patch_fill<Q, T, C, SH>), dim3((unsigned)((total_padded + 255) / 256)), dim3(256), 0, st,
-                       a, v, state, total_padded, all_cells ? 1 : 0);
+void launch_patch_init(const PatchArgs<C> &a, const CoarseView<C> &v, void *state, int64_t total_padded,
+                       hipStream_t st) {
+    hipLaunchKernelGGL((patch_init<Q, T, C, SH>), dim3((unsigned)((total_padded + 255) / 256)), dim3(256), 0, st,
+                       a, v, state, total_padded);
 }
 
 template <int Q, typename T, typename C, bool SH>
-void launch_patch_restrict(const PatchArgs<C> &a, const CoarseView<C> &v, const void *fine, int64_t covered,
+void launch_patch_ghosts(const PatchArgs<C> &a, const CoarseView<C> &v, void *state, const PatchLists &L,
+                         hipStream_t st) {
+    if (L.nghost == 0) return;
+    hipLaunchKernelGGL((patch_ghosts<Q, T, C, SH>), dim3((unsigned)((L.nghost + 255) / 256)), dim3(256), 0, st,
+                       a, v, state, L.gdst, L.gsrc, L.nghost);
+}
+
+template <int Q, typename T, typename C, bool SH>
+void launch_patch_restrict(const PatchArgs<C> &a, const CoarseView<C> &v, const void *fine, const PatchLists &L,
                            hipStream_t st) {
-    hipLaunchKernelGGL((patch_restrict<Q, T, C, SH>), dim3((unsigned)((covered + 255) / 256)), dim3(256), 0, st,
-                       a, v, fine, covered);
+    hipLaunchKernelGGL((patch_restrict<Q, T, C, SH>), dim3((unsigned)((L.covered + 255) / 256)), dim3(256), 0, st,
+                       a, v, fine, L.rc, L.rf, L.rp, L.covered);
 }
 
 template <int Q, typename T, typename C, bool SH>
@@ -388,10 +432,12 @@ void launch_patch_macros(const PatchArgs<C> &a, const void *state, int patch, in
 
 #define LBM_INSTANTIATE_PATCH(Q, T, C, SH)                                                                   \
     template void launch_patch_step<Q, T, C, SH>(const PatchArgs<C> &, const PatchLaunch &);                 \
-    template void launch_patch_fill<Q, T, C, SH>(const PatchArgs<C> &, const CoarseView<C> &, void *, int64_t, \
-                                                 bool, hipStream_t);                                         \
+    template void launch_patch_init<Q, T, C, SH>(const PatchArgs<C> &, const CoarseView<C> &, void *, int64_t, \
+                                                 hipStream_t);                                               \
+    template void launch_patch_ghosts<Q, T, C, SH>(const PatchArgs<C> &, const CoarseView<C> &, void *,      \
+                                                   const PatchLists &, hipStream_t);                         \
     template void launch_patch_restrict<Q, T, C, SH>(const PatchArgs<C> &, const CoarseView<C> &,            \
-                                                     const void *, int64_t, hipStream_t);                    \
+                                                     const void *, const PatchLists &, hipStream_t);         \
     template void launch_patch_macros<Q, T, C, SH>(const PatchArgs<C> &, const void *, int, int64_t, double *, \
                                                    double *, double *, hipStream_t);
 #endif

@@ -60,13 +60,15 @@ class Hierarchy:
     def info(self):
         st, fc, fb, ne, tf, tz, wg = abi.lbm_hierarchy_info(self.h)
         _check(st)
-        return {"fine_cells": fc, "fine_blocks": fb, "n_eff": ne, "tau_fine": tf, "tile_z": tz,
+        return {"fine_cells": fc, "fine_blocks": fb, "n_eff": ne, "tau_fine": tf, "tile_x": tz,
                 "workgroups": wg}
 
     def autotune(self, reps: int = 5):
-        st, tz, wg = abi.lbm_hierarchy_autotune(self.h, reps)
+        """(widest tile, workgroups, microseconds per fine step) of the
+        fastest fine-step configuration, which is kept."""
+        st, tz, wg, us = abi.lbm_hierarchy_autotune(self.h, reps)
         _check(st)
-        return tz, wg
+        return tz, wg, us
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value is not None:

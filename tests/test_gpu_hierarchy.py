@@ -107,9 +107,9 @@ def test_hierarchy_autotune_keeps_results(env):
         blk, H = _make(torch, lbm, 19, 2, use_graph=True)
         H.step_n(3, 0)
         if tune:
-            tz, wg = H.autotune(3)
-            print(f"autotune picked tile 8x8x{tz}, {wg} workgroups")
-            assert tz in (2, 4, 8) and wg >= 1
+            tx, wg, us = H.autotune(3)
+            print(f"autotune picked tiles up to {tx}x8x8, {wg} workgroups ({us:.1f} us per fine step)")
+            assert tx in (8, 16, 32) and wg >= 1
         H.step_n(5, 0)
         res.append((blk.populations(), H.patch_fields(2)[2]))
         H.close()
