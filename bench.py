@@ -5,7 +5,8 @@ Re 1000, halfway bounce-back walls), with the sensor, its 8^3 block maxima
 and the refine/coarsen flags evaluated at every step.  A "step" is one
 launch of the fused kernel over the whole grid.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--workload cavity128|cavity256|channel256|refined256]
+  python bench.py [--steps K] [--warmup W]
+                  [--workload cavity128|cavity256|channel256|refined256|predictor]
                   [--storage f32|f32s|f64|f16s|bf16s|f16sr|bf16sr] [--lattice 19|27]
                   [--smagorinsky C] [--no-cpu-baseline]
 
@@ -29,6 +30,11 @@ The value counts lattice updates of both levels; the roofline entry prices
 the fine step (all patches, one persistent launch, timed by the
 hierarchy's autotuner with HIP events) at one read and one write of every
 population of every fine cell.
+
+--workload predictor: K training iterations (forward, backward, Adam) of
+the flag predictor on a seeded batch of 8 block grids of 16^3; the roofline
+entry prices one 16 -> 16 channel convolution at its algorithmic flops
+against the dense BF16 matrix-core peak.
 """
 import argparse
 import hashlib
@@ -177,6 +183,59 @@ def run_refined(args, lbm, torch):
     return result
 
 
+def run_predictor(args, lbm, torch):
+    """Training iterations of the flag predictor on a seeded synthetic batch
+    of 8 block grids (16^3 blocks, 6 input channels); returns the JSON dict."""
+    import lbm_inputs
+    from paper_1507_06767_amd import cnn
+    from paper_1507_06767_amd.predictor import FlagPredictor
+    torch.cuda.set_device(0)
+    shape = (8, 16, 16, 16)
+    nv = int(np.prod(shape))
+    x = (2.0 * lbm_inputs.uniform(11, nv * 6) - 1.0).reshape(shape + (6,))
+    t = (2.0 * lbm_inputs.uniform(12, nv) - 1.0).reshape(shape)
+    net = FlagPredictor(seed=0)
+    for _ in range(args.warmup):
+        net.loss_and_grads(x, t)
+        net.adam_step(1e-3)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    a.record()
+    for _ in range(args.steps):
+        net.loss_and_grads(x, t)
+        net.adam_step(1e-3)
+    b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = a.elapsed_time(b)
+    # one 16 -> 16 forward convolution, single launches bracketed by events
+    L = net.layers[1]
+    B = net._buffers(shape)
+    reps = 50
+    a.record()
+    for _ in range(reps):
+        assert cnn.lbm_cnn_conv3d_forward(B["acts"][0], *shape, L.ci, L.packed, L.co, L.b, 1, B["acts"][1]) == 0
+    b.record()
+    torch.cuda.synchronize()
+    conv_us = a.elapsed_time(b) / reps * 1e3
+    flops = 2.0 * nv * L.co * 27 * L.ci
+    achieved = flops / (conv_us * 1e-6) / 1e12
+    return {
+        "metric": "training iterations per second of the flag predictor (4 conv3d layers, BF16 MFMA)",
+        "value": round(args.steps / (ms * 1e-3), 1), "unit": "iterations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (fp32 accumulate)",
+        "data": "synthetic", "wall_s": round(wall, 3),
+        "config": {"workload": "flag predictor 6-16-16-16-1, batch 8 x 16^3 blocks", "voxels": nv},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": round(achieved / 2500.0, 6), "traffic": None,
+                     "kernel": "conv3d_forward 16->16 (one launch)", "flops_per_launch": flops,
+                     "per_kernel_us": {"conv3d_forward_16x16": round(conv_us, 2)}},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,9 +260,9 @@ def main():
     import torch
     import paper_1507_06767_amd as lbm
 
-    if args.workload == "refined256":
-        result = run_refined(args, lbm, torch)
-        print(json.dumps(result), flush=True)
+    if args.workload in ("refined256", "predictor"):
+        run = run_refined if args.workload == "refined256" else run_predictor
+        print(json.dumps(run(args, lbm, torch)), flush=True)
         return
 
     storage = {"f32": lbm.LBM_F32, "f32s": lbm.LBM_F32_SHIFTED, "f64": lbm.LBM_F64,

@@ -52,9 +52,10 @@ int64_t lbm_cnn_wgrad_workspace(int32_t n, int32_t d, int32_t h, int32_t wd, int
 
 /* Weight and bias gradients of the convolution:
  *   gw[co][tap][ci] = sum_{n, v} gz[n][v][co] x[n][v + tap - 13][ci],
- *   gb[co] = sum_{n, v} gz[n][v][co]  (gb may be NULL).
- * Deterministic: per-workgroup partial sums in `work`, folded in a fixed
- * order. */
+ *   gb[co] = sum_{n, v} gz[n][v][co]  (gb may be NULL; summed in float32
+ *   from the unrounded gz).
+ * Deterministic: per-workgroup partial sums (chunks of 1024 voxels) in
+ * `work`, folded in a fixed order. */
 int32_t lbm_cnn_conv3d_wgrad(const float *x, const float *gz, int32_t n, int32_t d, int32_t h, int32_t wd,
                              int32_t ci, int32_t co, float *work, float *gw, float *gb, void *stream);
 
@@ -63,7 +64,10 @@ int32_t lbm_cnn_relu_backward(const float *a, float *g, int64_t count, void *str
 
 /* Mean squared error of channel 0 of y (channel stride ystride) against
  * target[v], v < count: loss[0] = mean (y - t)^2 (float32, written on the
- * device), g[v][0] = 2 (y - t) / count and g's other channels 0. */
+ * device), g[v][0] = 2 (y - t) / count and g's other channels 0.  loss
+ * must hold LBM_CNN_LOSS_FLOATS floats: loss[1..] receive per-workgroup
+ * partial sums, folded in a fixed order (deterministic). */
+#define LBM_CNN_LOSS_FLOATS 257
 int32_t lbm_cnn_mse(const float *y, int32_t ystride, const float *target, int64_t count, float *g,
                     float *loss, void *stream);
 

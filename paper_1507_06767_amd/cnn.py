@@ -15,6 +15,7 @@ import torch
 from . import abi
 
 LBM_CNN_TAPS = 27
+LBM_CNN_LOSS_FLOATS = 257
 
 _lib = abi._lib
 _P = ctypes.c_void_p
@@ -98,7 +99,8 @@ def lbm_cnn_relu_backward(a, g, count, stream=None):
 def lbm_cnn_mse(y, ystride, target, count, g, loss, stream=None):
     return _lib.lbm_cnn_mse(_ptr(y, torch.float32, count * ystride, "y"), int(ystride),
                             _ptr(target, torch.float32, count, "target"), int(count),
-                            _ptr(g, torch.float32, count * ystride, "g"), _ptr(loss, torch.float32, 1, "loss"),
+                            _ptr(g, torch.float32, count * ystride, "g"),
+                            _ptr(loss, torch.float32, LBM_CNN_LOSS_FLOATS, "loss"),
                             _stream(stream))
 
 

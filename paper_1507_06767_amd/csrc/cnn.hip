@@ -18,6 +18,8 @@
 
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "lbm_cnn.h"
 
 namespace {
@@ -26,7 +28,8 @@ typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTaps = 27;
-constexpr int kWgradVoxels = 4096;   // voxels per weight-gradient workgroup
+constexpr int kWgradVoxels = 1024;   // voxels per weight-gradient workgroup
+constexpr int kLossBlocks = 256;     // workgroups of the loss kernel (partial sums in loss[1..])
 
 __host__ __device__ inline int pad4(int c) { return (c + 3) / 4 * 4; }
 __host__ __device__ inline int pad16(int k) { return (k + 15) / 16 * 16; }
@@ -122,7 +125,9 @@ __global__ __launch_bounds__(256) void conv_forward_kernel(const float *x, int n
 // Weight gradient partials.  Workgroup (chunk, kt, ct): output channels
 // 16*ct.., reduction columns 16*kt.. over the chunk's voxels; each wave takes a
 // quarter of the voxels, the four wave tiles are summed in LDS in a fixed
-// order into work[chunk][co][k].
+// order into work[chunk][co][k].  The workgroups of column tile 0 also sum
+// the float32 output gradient per channel (the bias gradient) into
+// work[nchunk * co16 * k16 + chunk * co16 + co].
 __global__ __launch_bounds__(256) void conv_wgrad_kernel(const float *x, const float *gz, int n, int d, int h,
                                                          int w, int ci, int co, float *work) {
     const int ci4 = pad4(ci), co4 = pad4(co), k16 = pad16(kTaps * ci4), co16 = pad16(co);
@@ -136,6 +141,7 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(const float *x, const f
     const int ocol = c0 + r;                       // this lane's A row (output channel)
     const bool row_ok = ocol < co;
     f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    float bsum = 0.0f;
     const int vbeg = chunk * kWgradVoxels + wave * (kWgradVoxels / 4);
     const int vend = min(vbeg + kWgradVoxels / 4, nv);
     for (int v0 = vbeg; v0 < vend; v0 += 16) {
@@ -153,17 +159,26 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(const float *x, const f
                 }
             }
         }
+        bsum += ((a[0] + a[1]) + a[2]) + a[3];
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(to_bf16x4(a[0], a[1], a[2], a[3]),
                                                         to_bf16x4(b[0], b[1], b[2], b[3]), acc, 0, 0, 0);
     }
     __shared__ float tile[4][16][16];
+    __shared__ float bias[4][4][16];   // [wave][lane group][channel]
 #pragma unroll
     for (int j = 0; j < 4; ++j) tile[wave][4 * kg + j][r] = acc[j];
+    bias[wave][kg][r] = bsum;
     __syncthreads();
     const int t = threadIdx.x;   // 256 threads = one 16x16 tile
     const int row = t / 16, col = t % 16;
     const float s = ((tile[0][row][col] + tile[1][row][col]) + tile[2][row][col]) + tile[3][row][col];
     work[((int64_t)chunk * co16 + c0 + row) * k16 + k0 + col] = s;
+    if (blockIdx.y == 0 && t < 16) {
+        float b = 0.0f;
+        for (int wv = 0; wv < 4; ++wv)
+            for (int g = 0; g < 4; ++g) b += bias[wv][g][t];
+        work[(int64_t)gridDim.x * co16 * k16 + (int64_t)chunk * co16 + c0 + t] = b;
+    }
 }
 
 // gw[co][tap][ci] = sum over chunks (in order) of the partials.
@@ -178,19 +193,13 @@ __global__ void wgrad_fold_kernel(const float *work, int nchunk, int ci, int co,
     gw[idx] = s;
 }
 
-// gb[co] = sum_v gz[v][co]: one workgroup per channel, fixed-order tree.
-__global__ __launch_bounds__(256) void bias_grad_kernel(const float *gz, int64_t nv, int co4, float *gb) {
-    __shared__ float sh[256];
-    const int o = blockIdx.x;
+// gb[co] = sum over chunks (in order) of the per-chunk channel sums.
+__global__ void bias_fold_kernel(const float *part, int nchunk, int co, int co16, float *gb) {
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= co) return;
     float s = 0.0f;
-    for (int64_t v = threadIdx.x; v < nv; v += 256) s += gz[v * co4 + o];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int k = 128; k > 0; k >>= 1) {
-        if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) gb[o] = sh[0];
+    for (int ch = 0; ch < nchunk; ++ch) s += part[(int64_t)ch * co16 + o];
+    gb[o] = s;
 }
 
 __global__ void relu_backward_kernel(const float *a, float *g, int64_t count) {
@@ -198,12 +207,14 @@ __global__ void relu_backward_kernel(const float *a, float *g, int64_t count) {
     if (i < count && !(a[i] > 0.0f)) g[i] = 0.0f;
 }
 
+// Squared errors of channel 0 and the output gradient; workgroup b writes
+// its partial sum of squares to loss[1 + b] (fixed-order tree).
 __global__ __launch_bounds__(256) void mse_kernel(const float *y, int ys, const float *t, int64_t count, float *g,
                                                   float *loss) {
     __shared__ float sh[256];
     float s = 0.0f;
     const float scale = 2.0f / (float)count;
-    for (int64_t v = threadIdx.x; v < count; v += 256) {
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < count; v += (int64_t)gridDim.x * 256) {
         const float e = y[v * ys] - t[v];
         s += e * e;
         g[v * ys] = scale * e;
@@ -215,7 +226,15 @@ __global__ __launch_bounds__(256) void mse_kernel(const float *y, int ys, const 
         if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
         __syncthreads();
     }
-    if (threadIdx.x == 0) loss[0] = sh[0] / (float)count;
+    if (threadIdx.x == 0) loss[1 + blockIdx.x] = sh[0];
+}
+
+// loss[0] = (sum of the partials, in order) / count.
+__global__ void mse_fold_kernel(float *loss, int nblocks, int64_t count) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    float s = 0.0f;
+    for (int b = 0; b < nblocks; ++b) s += loss[1 + b];
+    loss[0] = s / (float)count;
 }
 
 __global__ void adam_kernel(float *w, const float *g, float *m, float *v, int64_t count, float lr, float b1,
@@ -270,7 +289,7 @@ int64_t lbm_cnn_wgrad_workspace(int32_t n, int32_t d, int32_t h, int32_t wd, int
     if (n < 1 || d < 1 || h < 1 || wd < 1 || ci < 1 || co < 1) return -1;
     const int64_t nv = (int64_t)n * d * h * wd;
     const int64_t nchunk = (nv + kWgradVoxels - 1) / kWgradVoxels;
-    return nchunk * pad16(co) * pad16(kTaps * pad4(ci)) * (int64_t)sizeof(float);
+    return nchunk * pad16(co) * (pad16(kTaps * pad4(ci)) + 1) * (int64_t)sizeof(float);
 }
 
 int32_t lbm_cnn_conv3d_wgrad(const float *x, const float *gz, int32_t n, int32_t d, int32_t h, int32_t wd,
@@ -284,7 +303,9 @@ int32_t lbm_cnn_conv3d_wgrad(const float *x, const float *gz, int32_t n, int32_t
     hipLaunchKernelGGL(conv_wgrad_kernel, grid, dim3(256), 0, st, x, gz, n, d, h, wd, ci, co, work);
     hipLaunchKernelGGL(wgrad_fold_kernel, dim3(blocks_for((int64_t)co * kTaps * ci, 256)), dim3(256), 0, st,
                        work, nchunk, ci, co, gw);
-    if (gb) hipLaunchKernelGGL(bias_grad_kernel, dim3(co), dim3(256), 0, st, gz, nv, pad4(co), gb);
+    if (gb)
+        hipLaunchKernelGGL(bias_fold_kernel, dim3(blocks_for(co, 64)), dim3(64), 0, st,
+                           work + (int64_t)nchunk * pad16(co) * pad16(kTaps * pad4(ci)), nchunk, co, pad16(co), gb);
     return launched();
 }
 
@@ -299,8 +320,9 @@ int32_t lbm_cnn_relu_backward(const float *a, float *g, int64_t count, void *str
 int32_t lbm_cnn_mse(const float *y, int32_t ystride, const float *target, int64_t count, float *g,
                     float *loss, void *stream) {
     if (!y || !target || !g || !loss || ystride < 1 || count < 1) return -1;
-    hipLaunchKernelGGL(mse_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, y, ystride, target, count, g,
-                       loss);
+    const int nb = (int)std::min<int64_t>(kLossBlocks, (count + 255) / 256);
+    hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, (hipStream_t)stream, y, ystride, target, count, g, loss);
+    hipLaunchKernelGGL(mse_fold_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, loss, nb, count);
     return launched();
 }
 

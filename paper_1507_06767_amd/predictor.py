@@ -112,7 +112,8 @@ class FlagPredictor:
             self._bufs[shape] = dict(x=z(self.channels[0]), acts=acts, grads=grads,
                                      work=torch.zeros(ws, dtype=torch.float32, device=self.device),
                                      target=torch.zeros(nv, dtype=torch.float32, device=self.device),
-                                     loss=torch.zeros(1, dtype=torch.float32, device=self.device))
+                                     loss=torch.zeros(cnn.LBM_CNN_LOSS_FLOATS, dtype=torch.float32,
+                                                      device=self.device))
         return self._bufs[shape]
 
     def load_input(self, x, shape):
@@ -166,7 +167,7 @@ class FlagPredictor:
         _check(cnn.lbm_cnn_mse(y, cnn.pad4(self.channels[-1]), B["target"], nv, B["grads"][-1], B["loss"],
                                self.stream), "mse")
         self.backward_device(shape)
-        return B["loss"]
+        return B["loss"][0]
 
     def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         self.t += 1

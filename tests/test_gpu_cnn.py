@@ -152,12 +152,12 @@ def test_relu_backward_mse_adam(env):
     y = rng.standard_normal((nv, 4)).astype(np.float32)
     t = rng.standard_normal(nv).astype(np.float32)
     gy = torch.full((nv * 4,), float("nan"), dtype=torch.float32, device="cuda")
-    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(cnn.LBM_CNN_LOSS_FLOATS, dtype=torch.float32, device="cuda")
     assert cnn.lbm_cnn_mse(_dev(torch, y), 4, _dev(torch, t), nv, gy, loss) == 0
     torch.cuda.synchronize()
     ref_l, ref_g = ocnn.mse(y[:, 0], t)
     gy = gy.cpu().numpy().reshape(nv, 4)
-    assert abs(loss.item() - ref_l) <= 1e-5 * ref_l
+    assert abs(loss[0].item() - ref_l) <= 1e-5 * ref_l
     assert np.allclose(gy[:, 0], ref_g, rtol=1e-6, atol=0) and (gy[:, 1:] == 0).all()
     # Adam, 5 steps
     w0 = rng.standard_normal(777)
