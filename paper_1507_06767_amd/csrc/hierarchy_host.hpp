@@ -15,6 +15,8 @@
 // ghost list and the restriction a list of covered coarse cells, all built
 // here on the host at creation.
 
+#include <array>
+
 #include "patch_kernels.hpp"
 
 struct lbm_hierarchy {
@@ -26,9 +28,11 @@ struct lbm_hierarchy {
     int64_t total_padded, covered, nblocks, fine_cells, max_patch_cells;
     int64_t pitch;            // elements between fine planes
     size_t elem;              // bytes per stored value
-    size_t meta_patch, meta_tile, meta_cover, meta_gdst, meta_gsrc, meta_rc, meta_rf, meta_rp,
+    size_t meta_patch, meta_tile, meta_cover, meta_gdst, meta_gsrc, meta_gloc, meta_gmask, meta_gtile, meta_rc,
+        meta_rf, meta_rp,
         meta_stage;           // offsets inside META
     int64_t nghost, ntiles;   // ghost cells; tiles of the current tile list
+    int64_t ngtile, ngtile_max;   // ghost tiles in use (0: list-only ghost kernel); their bound
     std::vector<PatchTile> tiles;
     size_t bytes[LBM_NHBUF];
     void *buf[LBM_NHBUF];
@@ -117,7 +121,19 @@ lbm_status hier_layout(const lbm_blocks *h, int32_t nbox, const lbm_box *boxes, 
     H->meta_cover = H->meta_tile + round_up((size_t)blocks * sizeof(PatchTile), kAlign);   // <= one tile per block
     H->meta_gdst = H->meta_cover + round_up((size_t)h->L.cells * 4, kAlign);
     H->meta_gsrc = H->meta_gdst + round_up((size_t)H->nghost * 4, kAlign);
-    H->meta_rc = H->meta_gsrc + round_up((size_t)H->nghost * 4, kAlign);
+    // ghost tiles: 16 x 16 pieces of the six faces of every patch
+    int64_t ngt = 0;
+    for (int p = 0; p < nbox; ++p) {
+        const PatchRec &r = H->rec[p];
+        const int64_t P0 = r.e[0] + 2, P1 = r.e[1] + 2, P2 = r.e[2] + 2;
+        auto t16 = [](int64_t m) { return (m + 15) / 16; };
+        ngt += 2 * (t16(P1) * t16(P2) + t16(P0 - 2) * t16(P2) + t16(P0 - 2) * t16(P1 - 2));
+    }
+    H->ngtile_max = ngt;
+    H->meta_gloc = H->meta_gsrc + round_up((size_t)H->nghost * 4, kAlign);
+    H->meta_gmask = H->meta_gloc + round_up((size_t)H->nghost * 4, kAlign);
+    H->meta_gtile = H->meta_gmask + round_up((size_t)H->nghost * 4, kAlign);
+    H->meta_rc = H->meta_gtile + round_up((size_t)ngt * sizeof(GhostTile), kAlign);
     H->meta_rf = H->meta_rc + round_up((size_t)cov * 4, kAlign);
     H->meta_rp = H->meta_rf + round_up((size_t)cov * 4, kAlign);
     H->meta_stage = H->meta_rp + round_up((size_t)cov * 4, kAlign);
@@ -193,7 +209,11 @@ PatchLists patch_lists(lbm_hierarchy *H) {
     PatchLists L;
     L.gdst = reinterpret_cast<const uint32_t *>(meta + H->meta_gdst);
     L.gsrc = reinterpret_cast<const int *>(meta + H->meta_gsrc);
+    L.gloc = reinterpret_cast<const int *>(meta + H->meta_gloc);
+    L.gmask = reinterpret_cast<const uint32_t *>(meta + H->meta_gmask);
     L.nghost = H->nghost;
+    L.gtile = H->ngtile > 0 ? reinterpret_cast<const GhostTile *>(meta + H->meta_gtile) : nullptr;
+    L.ngtile = H->ngtile;
     L.rc = reinterpret_cast<const int *>(meta + H->meta_rc);
     L.rf = reinterpret_cast<const int *>(meta + H->meta_rf);
     L.rp = reinterpret_cast<const int *>(meta + H->meta_rp);
@@ -349,45 +369,99 @@ lbm_status lbm_create_hierarchy(lbm_blocks *coarse, int32_t nbox, const lbm_box 
             for (int y = b.lo[1]; y < b.hi[1]; ++y)
                 for (int x = b.lo[0]; x < b.hi[0]; ++x) cover[((size_t)z * ny + y) * nx + x] = p;
     }
-    // ghost list: copy from the patch that holds the cell, else the low corner
-    // of the coarse interpolation stencil and the 3/4-weight bits
+    // ghost list, grouped into tiles of at most 16 x 16 cells of one face: a
+    // ghost copies from the patch that holds its cell, else it carries the low
+    // corner of its coarse interpolation stencil and the 3/4-weight bits.
+    // Faces own their cells without overlap: x faces whole, y faces without
+    // the x rims, z faces without the x and y rims.
     std::vector<uint32_t> gdst;
     std::vector<int> gsrc;
+    std::vector<GhostTile> gtiles;
+    std::vector<int> gloc;
+    std::vector<uint32_t> gmask;
+    gloc.reserve(H->nghost);
+    gmask.reserve(H->nghost);
+    // velocity table of the lattice (interface order)
+    const int(*vel)[3] = (H->q == 19) ? Lattice<19>::c : Lattice<27>::c;
     gdst.reserve(H->nghost);
     gsrc.reserve(H->nghost);
+    bool tiles_ok = true;
     for (int p = 0; p < H->npatch; ++p) {
         const PatchRec &r = H->rec[p];
         const int P[3] = {r.e[0] + 2, r.e[1] + 2, r.e[2] + 2};
-        for (int pz = 0; pz < P[2]; ++pz)
-            for (int py = 0; py < P[1]; ++py)
-                for (int px = 0; px < P[0]; ++px) {
-                    const bool ghost = px == 0 || py == 0 || pz == 0 || px == P[0] - 1 || py == P[1] - 1 ||
-                                       pz == P[2] - 1;
-                    if (!ghost) continue;
-                    const int g[3] = {r.o[0] + px - 1, r.o[1] + py - 1, r.o[2] + pz - 1};
-                    const uint32_t dst = (uint32_t)(r.off + ((int64_t)pz * P[1] + py) * P[0] + px);
-                    const int owner = cover[((size_t)(g[2] >> 1) * ny + (g[1] >> 1)) * nx + (g[0] >> 1)];
-                    if (owner >= 0) {
-                        const PatchRec &o = H->rec[owner];
-                        const int64_t src = o.off + ((int64_t)(g[2] - o.o[2] + 1) * (o.e[1] + 2) + (g[1] - o.o[1] + 1)) *
-                                                        (o.e[0] + 2) + (g[0] - o.o[0] + 1);
-                        gdst.push_back(dst);
-                        gsrc.push_back((int)src);
-                    } else {
-                        // centre (g + 1/2) / 2 - 1/2: even g -> g/2 - 1 + 3/4, odd g -> (g - 1)/2 + 1/4
-                        uint32_t code = 0;
-                        int b[3];
-                        for (int a = 0; a < 3; ++a) {
-                            const bool even = (g[a] & 1) == 0;
-                            b[a] = even ? g[a] / 2 - 1 : (g[a] - 1) / 2;
-                            if (even) code |= 1u << (29 + a);
+        for (int f = 0; f < 6; ++f) {
+            const int na = f / 2, ua = (na == 0) ? 1 : 0, va = (na == 2) ? 1 : 2;
+            const int pn = (f & 1) ? P[na] - 1 : 0;
+            const int ulo = (na == 0) ? 0 : 1, uhi = (na == 0) ? P[1] : P[0] - 1;
+            const int vlo = (na == 2) ? 1 : 0, vhi = (na == 2) ? P[1] - 1 : P[2];
+            for (int v0 = vlo; v0 < vhi; v0 += 16)
+                for (int u0 = ulo; u0 < uhi; u0 += 16) {
+                    GhostTile t{};
+                    t.k0 = (int)gdst.size();
+                    std::vector<std::array<int, 3>> corner;   // stencil corner of each entry (-1: copy)
+                    int bmin[3] = {1 << 30, 1 << 30, 1 << 30}, bmax[3] = {-1, -1, -1};
+                    for (int vv = v0; vv < std::min(v0 + 16, vhi); ++vv)
+                        for (int uu = u0; uu < std::min(u0 + 16, uhi); ++uu) {
+                            int pc[3];
+                            pc[na] = pn;
+                            pc[ua] = uu;
+                            pc[va] = vv;
+                            const int g[3] = {r.o[0] + pc[0] - 1, r.o[1] + pc[1] - 1, r.o[2] + pc[2] - 1};
+                            const uint32_t dst = (uint32_t)(r.off + ((int64_t)pc[2] * P[1] + pc[1]) * P[0] + pc[0]);
+                            uint32_t need = 0;   // populations an interior cell pulls from this ghost
+                            for (int i = 0; i < H->q; ++i) {
+                                bool in = true;
+                                for (int a = 0; a < 3; ++a) {
+                                    const int t2 = pc[a] + vel[i][a];
+                                    in = in && t2 >= 1 && t2 <= P[a] - 2;
+                                }
+                                if (in) need |= 1u << i;
+                            }
+                            gmask.push_back(need);
+                            const int owner = cover[((size_t)(g[2] >> 1) * ny + (g[1] >> 1)) * nx + (g[0] >> 1)];
+                            if (owner >= 0) {
+                                const PatchRec &o = H->rec[owner];
+                                const int64_t src =
+                                    o.off + ((int64_t)(g[2] - o.o[2] + 1) * (o.e[1] + 2) + (g[1] - o.o[1] + 1)) *
+                                                (o.e[0] + 2) + (g[0] - o.o[0] + 1);
+                                gdst.push_back(dst);
+                                gsrc.push_back((int)src);
+                                corner.push_back({-1, -1, -1});
+                                continue;
+                            }
+                            // centre (g + 1/2) / 2 - 1/2: even g -> g/2 - 1 + 3/4, odd g -> (g - 1)/2 + 1/4
+                            uint32_t code = 0;
+                            int b[3];
+                            for (int a = 0; a < 3; ++a) {
+                                const bool even = (g[a] & 1) == 0;
+                                b[a] = even ? g[a] / 2 - 1 : (g[a] - 1) / 2;
+                                if (even) code |= 1u << (29 + a);
+                                bmin[a] = std::min(bmin[a], b[a]);
+                                bmax[a] = std::max(bmax[a], b[a] + 1);
+                            }
+                            gdst.push_back(dst | code);
+                            gsrc.push_back((int)(-(((int64_t)b[2] * ny + b[1]) * nx + b[0]) - 1));
+                            corner.push_back({b[0], b[1], b[2]});
                         }
-                        const int64_t base = ((int64_t)b[2] * ny + b[1]) * nx + b[0];
-                        gdst.push_back(dst | code);
-                        gsrc.push_back((int)(-base - 1));
+                    t.n = (int)gdst.size() - t.k0;
+                    if (bmax[0] >= 0) {
+                        t.ox = bmin[0];
+                        t.oy = bmin[1];
+                        t.oz = bmin[2];
+                        t.dx = bmax[0] - bmin[0] + 1;
+                        t.dy = bmax[1] - bmin[1] + 1;
+                        t.dz = bmax[2] - bmin[2] + 1;
+                        if (t.dx * t.dy * t.dz > kGhostBox || t.n > 256) tiles_ok = false;
                     }
+                    for (const auto &c : corner)
+                        gloc.push_back(c[0] < 0 ? 0 : ((c[2] - t.oz) * t.dy + (c[1] - t.oy)) * t.dx + (c[0] - t.ox));
+                    gtiles.push_back(t);
                 }
+        }
     }
+    H->ngtile = tiles_ok ? (int64_t)gtiles.size() : 0;
+    const char *gmode = std::getenv("LBM_HIER_GHOSTS");
+    if (gmode && std::strcmp(gmode, "plain") == 0) H->ngtile = 0;   // the list-only kernel (tests compare both)
     // restriction list: each covered coarse cell, its fine group and patch
     std::vector<int> rc, rf, rp;
     for (int p = 0; p < H->npatch; ++p) {
@@ -411,6 +485,13 @@ lbm_status lbm_create_hierarchy(lbm_blocks *coarse, int32_t nbox, const lbm_box 
         e = hipMemcpyAsync(meta + H->meta_cover, cover.data(), cover.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(meta + H->meta_gdst, gdst.data(), gdst.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(meta + H->meta_gsrc, gsrc.data(), gsrc.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && (int64_t)gtiles.size() > H->ngtile_max) e = hipErrorInvalidValue;   // before the copy
+    if (e == hipSuccess && (gloc.size() != gdst.size() || gmask.size() != gdst.size())) e = hipErrorInvalidValue;
+    if (e == hipSuccess) e = hipMemcpyAsync(meta + H->meta_gmask, gmask.data(), gmask.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(meta + H->meta_gloc, gloc.data(), gloc.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && H->ngtile > 0)
+        e = hipMemcpyAsync(meta + H->meta_gtile, gtiles.data(), gtiles.size() * sizeof(GhostTile),
+                           hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(meta + H->meta_rc, rc.data(), rc.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(meta + H->meta_rf, rf.data(), rf.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(meta + H->meta_rp, rp.data(), rp.size() * 4, hipMemcpyHostToDevice, s);

@@ -50,6 +50,19 @@ struct PatchTile {
 };
 static_assert(sizeof(PatchTile) == 32, "PatchTile layout");
 
+// A tile of the ghost fill: up to 256 ghost cells of one face of one patch
+// (a 16 x 16 piece of the face), entries k0 .. k0+n-1 of the ghost list, and
+// the box of coarse cells their interpolation stencils cover (origin o,
+// extent dx x dy x dz <= kGhostBox cells; extent 0 when every ghost of the
+// tile copies from an abutting patch).
+constexpr int kGhostBox = 200;
+struct GhostTile {
+    int k0, n;
+    int ox, oy, oz;
+    int dx, dy, dz;
+};
+static_assert(sizeof(GhostTile) == 32, "GhostTile layout");
+
 template <typename C>
 struct PatchArgs {
     const void *src;          // fine state read by the step (padded planes)
@@ -235,24 +248,30 @@ __device__ __forceinline__ void coarse_to_fine(const CoarseView<C> &v, const C (
 // gdst[k] & 0x1FFFFFFF; gsrc[k] >= 0 is the padded cell of an abutting
 // patch to copy, else -gsrc[k] - 1 is the coarse cell at the low corner of
 // the interpolation stencil, and bit 29 + a of gdst[k] is set when the
-// weight of the upper neighbour along axis a is 3/4 (else 1/4).
+// weight of the upper neighbour along axis a is 3/4 (else 1/4).  Only the
+// populations some interior cell pulls from the ghost (bit i of gmask[k]:
+// ghost + xi_i is an interior cell) are written; the rest of a ghost cell
+// is never read.
 template <int Q, typename T, typename C, bool SH>
 __global__ __launch_bounds__(256) void patch_ghosts(const PatchArgs<C> a, const CoarseView<C> v, void *state,
-                                                    const uint32_t *gdst, const int *gsrc, int64_t nghost) {
+                                                    const uint32_t *gdst, const int *gsrc, const uint32_t *gmask,
+                                                    int64_t nghost) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nghost) return;
     const uint32_t code = gdst[k];
     const int64_t g = code & 0x1FFFFFFFu;
     const int src = gsrc[k];
+    const uint32_t need = gmask[k];
     if (src >= 0) {
         static_for<0, Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            static_cast<T *>(state)[i * a.pitch + g] = static_cast<const T *>(state)[i * a.pitch + src];
+            if ((need >> i) & 1u)
+                static_cast<T *>(state)[i * a.pitch + g] = static_cast<const T *>(state)[i * a.pitch + src];
         });
         return;
     }
-    const int64_t base = -(int64_t)src - 1;
-    const int x0 = (int)(base % v.nx), y0 = (int)((base / v.nx) % v.ny), z0 = (int)(base / ((int64_t)v.nx * v.ny));
+    const int base = -src - 1;               // coarse cells < 2^31
+    const int x0 = base % v.nx, y0 = (base / v.nx) % v.ny, z0 = base / (v.nx * v.ny);
     const C fx = (code >> 29) & 1u ? C(0.75) : C(0.25);
     const C fy = (code >> 30) & 1u ? C(0.75) : C(0.25);
     const C fz = (code >> 31) & 1u ? C(0.75) : C(0.25);
@@ -260,7 +279,70 @@ __global__ __launch_bounds__(256) void patch_ghosts(const PatchArgs<C> a, const 
     coarse_to_fine<Q, T, C, SH>(v, a.shift, a.rho0, C(x0) + fx, C(y0) + fy, C(z0) + fz, d);
     static_for<0, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        store_dev<T>(state, i * a.pitch + g, d[i], a.shift[i], SH);
+        if ((need >> i) & 1u) store_dev<T>(state, i * a.pitch + g, d[i], a.shift[i], SH);
+    });
+}
+
+// The same ghost fill, one workgroup per ghost tile: the tile's coarse box,
+// interpolated in time, is staged once in LDS ([population][cell]) and every
+// ghost of the tile interpolates from there, so each coarse value is read
+// from memory once per tile instead of up to eight times per ghost.  Same
+// arithmetic, in the same order, as patch_ghosts.
+template <int Q, typename T, typename C, bool SH>
+__global__ __launch_bounds__(256) void patch_ghosts_lds(const PatchArgs<C> a, const CoarseView<C> v, void *state,
+                                                        const GhostTile *tiles, const uint32_t *gdst,
+                                                        const int *gsrc, const int *gloc, const uint32_t *gmask) {
+    static_assert(kGhostBox <= 256, "one box cell per thread");
+    __shared__ C box[Q * kGhostBox];
+    const GhostTile tl = tiles[blockIdx.x];
+    const int ncell = tl.dx * tl.dy * tl.dz;
+    if ((int)threadIdx.x < ncell) {
+        const int cell = threadIdx.x;
+        const int lx = cell % tl.dx, ly = (cell / tl.dx) % tl.dy, lz = cell / (tl.dx * tl.dy);
+        const int64_t cc = ((int64_t)(tl.oz + lz) * v.ny + (tl.oy + ly)) * v.nx + (tl.ox + lx);
+        static_for<0, Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            C sv = load_dev<T>(v.s0, i * v.pitch + cc, a.shift[i], SH);
+            if (v.w1 != C(0)) sv += v.w1 * (load_dev<T>(v.s1, i * v.pitch + cc, a.shift[i], SH) - sv);
+            box[i * kGhostBox + cell] = sv;
+        });
+    }
+    __syncthreads();
+    if ((int)threadIdx.x >= tl.n) return;
+    const int64_t k = (int64_t)tl.k0 + threadIdx.x;
+    const uint32_t code = gdst[k];
+    const int64_t g = code & 0x1FFFFFFFu;
+    const int src = gsrc[k];
+    const uint32_t need = gmask[k];
+    if (src >= 0) {
+        static_for<0, Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            if ((need >> i) & 1u)
+                static_cast<T *>(state)[i * a.pitch + g] = static_cast<const T *>(state)[i * a.pitch + src];
+        });
+        return;
+    }
+    const int c0 = gloc[k];                  // low stencil corner inside the tile's box
+    const C fx = (code >> 29) & 1u ? C(0.75) : C(0.25);
+    const C fy = (code >> 30) & 1u ? C(0.75) : C(0.25);
+    const C fz = (code >> 31) & 1u ? C(0.75) : C(0.25);
+    C d[Q];
+    static_for<0, Q>([&](auto ic) { d[decltype(ic)::value] = C(0); });
+#pragma unroll 1
+    for (int c = 0; c < 8; ++c) {
+        const int ddx = c & 1, ddy = (c >> 1) & 1, ddz = c >> 2;
+        const C w = (ddx ? fx : C(1) - fx) * (ddy ? fy : C(1) - fy) * (ddz ? fz : C(1) - fz);
+        const int cell = c0 + (ddz * tl.dy + ddy) * tl.dx + ddx;
+        static_for<0, Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            d[i] += w * box[i * kGhostBox + cell];
+        });
+    }
+    const Moments<Q, C> mo = moments_of<Q>(d, a.rho0);
+    static_for<0, Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        const C deq = deq_of<Q, i>(mo, a.rho0);
+        if ((need >> i) & 1u) store_dev<T>(state, i * a.pitch + g, deq + v.alpha * (d[i] - deq), a.shift[i], SH);
     });
 }
 
@@ -372,7 +454,11 @@ struct PatchLaunch {
 struct PatchLists {
     const uint32_t *gdst;
     const int *gsrc;
+    const int *gloc;        // per ghost: low stencil corner inside its tile's box (LDS path)
+    const uint32_t *gmask;  // per ghost: populations some interior cell pulls from it
     int64_t nghost;
+    const GhostTile *gtile;
+    int64_t ngtile;
     const int *rc, *rf, *rp;
     int64_t covered;
 };
@@ -412,8 +498,12 @@ template <int Q, typename T, typename C, bool SH>
 void launch_patch_ghosts(const PatchArgs<C> &a, const CoarseView<C> &v, void *state, const PatchLists &L,
                          hipStream_t st) {
     if (L.nghost == 0) return;
-    hipLaunchKernelGGL((patch_ghosts<Q, T, C, SH>), dim3((unsigned)((L.nghost + 255) / 256)), dim3(256), 0, st,
-                       a, v, state, L.gdst, L.gsrc, L.nghost);
+    if (L.gtile)
+        hipLaunchKernelGGL((patch_ghosts_lds<Q, T, C, SH>), dim3((unsigned)L.ngtile), dim3(256), 0, st, a, v, state,
+                           L.gtile, L.gdst, L.gsrc, L.gloc, L.gmask);
+    else
+        hipLaunchKernelGGL((patch_ghosts<Q, T, C, SH>), dim3((unsigned)((L.nghost + 255) / 256)), dim3(256), 0,
+                           st, a, v, state, L.gdst, L.gsrc, L.gmask, L.nghost);
 }
 
 template <int Q, typename T, typename C, bool SH>

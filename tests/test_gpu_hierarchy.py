@@ -163,3 +163,22 @@ def test_hierarchy_rejects_bad_boxes(env):
     st, _ = lbm.lbm_hierarchy_required_bytes(blk.h, _BOXES)
     assert st == lbm.LBM_ENOTSUP                               # the coarse grid must stream ping-pong
     blk.close()
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_lds_ghost_fill_matches_list_fill(env, monkeypatch, q):
+    """The ghost fill staged in LDS per face tile and the plain list-driven
+    one perform the same arithmetic in the same order: identical bits."""
+    torch, lbm = env
+    print(f"\n[case] hierarchy ghost fill LDS vs plain q={q}", flush=True)
+    out = {}
+    for mode in ("lds", "plain"):
+        monkeypatch.setenv("LBM_HIER_GHOSTS", mode)
+        blk, H = _make(torch, lbm, q, 2, use_graph=True)
+        H.step_n(7, 7)
+        out[mode] = (blk.populations(), [H.patch_fields(p)[2] for p in range(len(_BOXES))], H.sensor()[0])
+        H.close()
+        blk.close()
+    assert np.array_equal(out["lds"][0], out["plain"][0]) and np.array_equal(out["lds"][2], out["plain"][2])
+    for a, b in zip(out["lds"][1], out["plain"][1]):
+        assert np.array_equal(a, b)
