@@ -6,7 +6,7 @@ and the refine/coarsen flags evaluated at every step.  A "step" is one
 launch of the fused kernel over the whole grid.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W]
-                  [--workload cavity128|cavity256|channel256|refined256|predictor]
+                  [--workload cavity128|cavity256|channel256|refined256|predictor|cavity64_2d]
                   [--storage f32|f32s|f64|f16s|bf16s|f16sr|bf16sr] [--lattice 19|27]
                   [--smagorinsky C] [--no-cpu-baseline]
 
@@ -30,6 +30,10 @@ The value counts lattice updates of both levels; the roofline entry prices
 the fine step (all patches, one persistent launch, timed by the
 hierarchy's autotuner with HIP events) at one read and one write of every
 population of every fine cell.
+
+--workload cavity64_2d: the 64^2 D2Q9 float64 cavity (Re 100, 2000 steps,
+sensor every 100), whose steps are bound by launch overhead: timed launching
+every step and replaying runs of 98 steps from HIP graphs (lbm_use_graphs).
 
 --workload predictor: K training iterations (forward, backward, Adam) of
 the flag predictor on a seeded batch of 8 block grids of 16^3; the roofline
@@ -183,6 +187,44 @@ def run_refined(args, lbm, torch):
     return result
 
 
+def run_cavity2d(args, lbm, torch):
+    """The 64^2 D2Q9 float64 cavity (Re 100, sensor every 100 steps):
+    launch-bound, timed launching every step and replaying runs of 98 steps
+    from HIP graphs; returns the JSON dict."""
+    import lbm_inputs
+    w = lbm_inputs.cavity2d()
+    st, tau = lbm.lbm_tau_from_reynolds(w.lid_speed, w.n_across, w.reynolds)
+    torch.cuda.set_device(0)
+    out = {}
+    for chunk in (0, 98):
+        desc = lbm.make_desc(9, w.n, w.bc, tau, storage=lbm.LBM_F64, wall_u=w.wall_u)
+        stream = torch.cuda.Stream()
+        blk = lbm.Blocks(desc, device="cuda:0", stream=stream)
+        blk.use_graphs(chunk)
+        blk.step_n(args.warmup, w.sensor_every)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        blk.step_n(w.steps, w.sensor_every)
+        b.record(stream)
+        torch.cuda.synchronize()
+        out[chunk] = a.elapsed_time(b) / w.steps * 1e3
+        blk.close()
+    us = out[98]
+    return {
+        "metric": "us per step of the 64^2 D2Q9 FP64 cavity (step + sensor every 100 steps)",
+        "value": round(w.cells / (us * 1e-6) / 1e6, 1), "unit": "MLUPS",
+        "n_gpus": 1, "steps": w.steps, "warmup": args.warmup, "ms_per_step": round(us / 1e3, 6),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "lattice": "D2Q9", "extent": list(w.n), "tau": tau,
+                   "sensor_every": w.sensor_every},
+        "us_per_step": {"graph_chunk_98": round(out[98], 3), "launch_per_step": round(out[0], 3)},
+        "roofline": {"bound": "launch", "achieved": None, "peak": None, "unit": None, "frac": None,
+                     "traffic": None, "kernel": "step_cells<9, double, ...> (4096 cells: launch bound)"},
+    }
+
+
 def run_predictor(args, lbm, torch):
     """Training iterations of the flag predictor on a seeded synthetic batch
     of 8 block grids (16^3 blocks, 6 input channels); returns the JSON dict."""
@@ -260,8 +302,8 @@ def main():
     import torch
     import paper_1507_06767_amd as lbm
 
-    if args.workload in ("refined256", "predictor"):
-        run = run_refined if args.workload == "refined256" else run_predictor
+    if args.workload in ("refined256", "predictor", "cavity64_2d"):
+        run = {"refined256": run_refined, "predictor": run_predictor, "cavity64_2d": run_cavity2d}[args.workload]
         print(json.dumps(run(args, lbm, torch)), flush=True)
         return
 

@@ -172,6 +172,16 @@ lbm_status lbm_create_blocks(const lbm_desc *d, const double *f0_host, lbm_block
  * Asynchronous: returns once the launches are enqueued. */
 lbm_status lbm_step_n(lbm_blocks *h, int64_t n, int32_t sensor_every);
 
+/* Replays runs of `chunk` sensor-free steps (an even number; 0 switches it
+ * off, the default) in lbm_step_n from a HIP graph captured once per buffer
+ * parity, instead of launching each step: for small grids, whose steps are
+ * bound by launch overhead.  Steps whose run would contain a sensor step,
+ * and all steps while the time average is on, are launched one by one.
+ * Results are identical bit for bit.  Needs a non-NULL stream
+ * (LBM_ENOTSUP otherwise) and is refused for stochastic rounding (its
+ * random bits depend on the step index).  Synchronises the stream. */
+lbm_status lbm_use_graphs(lbm_blocks *h, int32_t chunk);
+
 /* Synchronises the stream and returns the block maxima (as float64) and the
  * flags of the latest step that evaluated the sensor, and that step's index.
  * Any of the host pointers may be NULL.  Blocks are ordered [nbz][nby][nbx].

@@ -111,6 +111,7 @@ def _load_library():
     BP = ctypes.POINTER(lbm_box)
     sig.update({
         "lbm_autotune": [H, ctypes.c_int32, i32p],
+        "lbm_use_graphs": [H, ctypes.c_int32],
         "lbm_hierarchy_required_bytes": [H, ctypes.c_int32, BP, ctypes.POINTER(ctypes.c_size_t)],
         "lbm_create_hierarchy": [H, ctypes.c_int32, BP, ctypes.POINTER(ctypes.c_void_p),
                                  ctypes.POINTER(ctypes.c_size_t), ctypes.c_int32, ctypes.POINTER(H)],
@@ -284,6 +285,10 @@ def lbm_tau_from_reynolds(u: float, n_across: float, re: float):
 
 def lbm_destroy(h):
     _lib.lbm_destroy(h)
+
+
+def lbm_use_graphs(h, chunk: int):
+    return _lib.lbm_use_graphs(h, int(chunk))
 
 
 def lbm_autotune(h, reps: int):

@@ -124,6 +124,10 @@ class Blocks:
     def step(self, value: int):
         _check(abi.lbm_set_step(self.h, value))
 
+    def use_graphs(self, chunk: int):
+        """Replay runs of `chunk` (even) sensor-free steps from HIP graphs."""
+        _check(abi.lbm_use_graphs(self.h, chunk))
+
     def autotune(self, reps: int = 5):
         """Times the tile widths of the step kernel and keeps the fastest."""
         st, tx = abi.lbm_autotune(self.h, reps)

@@ -218,6 +218,8 @@ struct lbm_blocks {
     bool avg_started;         // the sums were cleared by lbm_sensor_average_begin
     int64_t avg_samples;      // sensor steps summed since averaging began
     uint32_t wall_mask;
+    int graph_chunk;          // steps per graph replay (even), 0: launch step by step
+    hipGraphExec_t graph[2];  // graph_chunk steps, by buffer parity
     std::vector<int8_t> flags_host;
     std::vector<unsigned char> bmax_host;
 };
@@ -420,6 +422,43 @@ void launch_step_any(lbm_blocks *h, bool sens) {
     else launch_step_q<27>(h, sens);
 }
 
+void drop_graphs(lbm_blocks *h) {
+    for (int p = 0; p < 2; ++p)
+        if (h->graph[p]) {
+            (void)hipGraphExecDestroy(h->graph[p]);
+            h->graph[p] = nullptr;
+        }
+}
+
+// One step with the usual bookkeeping (no graph).
+void step_once(lbm_blocks *h, int32_t sensor_every) {
+    const int64_t step = h->step + 1;
+    const bool sens = sensor_every > 0 && step % sensor_every == 0;
+    launch_step_any(h, sens);
+    if (h->inplace) h->phase ^= 1;
+    else h->cur ^= 1;
+    h->step = step;
+    if (sens) h->last_sensor_step = step;
+    if (sens && h->averaging) ++h->avg_samples;
+}
+
+// Captures graph_chunk sensor-free steps for the current buffer parity.
+lbm_status capture_steps(lbm_blocks *h, int parity) {
+    const int64_t s0 = h->step;
+    HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < h->graph_chunk; ++k) step_once(h, 0);
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamEndCapture(h->stream, &g));
+    h->step = s0;   // captured, not run; an even chunk leaves the parity as it was
+    hipError_t e = hipGraphInstantiate(&h->graph[parity], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        h->graph[parity] = nullptr;
+        return fail(LBM_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    return LBM_OK;
+}
+
 lbm_status check_handle(lbm_blocks *h) {
     if (!h) return fail(LBM_EINVAL, "handle is NULL");
     int dev = -1;
@@ -489,6 +528,8 @@ lbm_status lbm_create_blocks(const lbm_desc *d, const double *f0_host, lbm_block
     h->avg_samples = 0;
     h->has_force = d->force[0] != 0.0 || d->force[1] != 0.0 || d->force[2] != 0.0;
     h->wall_mask = 0;
+    h->graph_chunk = 0;
+    h->graph[0] = h->graph[1] = nullptr;
     for (int f = 0; f < 6; ++f)
         if (d->face_bc[f] == LBM_BC_WALL) h->wall_mask |= 1u << f;
     h->flags_host.resize(L.nblocks);
@@ -524,17 +565,40 @@ lbm_status lbm_step_n(lbm_blocks *h, int64_t n, int32_t sensor_every) {
     if (st != LBM_OK) return st;
     if (n < 0) return fail(LBM_EINVAL, "n = %lld < 0", (long long)n);
     if (sensor_every < 0) return fail(LBM_EINVAL, "sensor_every = %d < 0", sensor_every);
-    for (int64_t k = 0; k < n; ++k) {
-        const int64_t step = h->step + 1;
-        const bool sens = sensor_every > 0 && step % sensor_every == 0;
-        launch_step_any(h, sens);
-        if (h->inplace) h->phase ^= 1;
-        else h->cur ^= 1;
-        h->step = step;
-        if (sens) h->last_sensor_step = step;
-        if (sens && h->averaging) ++h->avg_samples;
+    int64_t k = 0;
+    while (k < n) {
+        const int64_t c = h->graph_chunk;
+        // a graph replay covers steps step+1 .. step+c when none of them is a sensor step
+        const bool free = c > 0 && n - k >= c && !h->averaging &&
+                          (sensor_every == 0 || (h->step + c) / sensor_every == h->step / sensor_every);
+        if (free) {
+            const int parity = h->inplace ? h->phase : h->cur;
+            if (!h->graph[parity]) {
+                st = capture_steps(h, parity);
+                if (st != LBM_OK) return st;
+            }
+            HIP_TRY(hipGraphLaunch(h->graph[parity], h->stream));
+            h->step += c;
+            k += c;
+            continue;
+        }
+        step_once(h, sensor_every);
+        ++k;
     }
     HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
+lbm_status lbm_use_graphs(lbm_blocks *h, int32_t chunk) {
+    lbm_status st = check_handle(h);
+    if (st != LBM_OK) return st;
+    if (chunk < 0 || chunk % 2) return fail(LBM_EINVAL, "chunk = %d must be an even number >= 0", chunk);
+    if (chunk > 0 && !h->stream) return fail(LBM_ENOTSUP, "graphs need a non-NULL stream");
+    if (chunk > 0 && (h->d.storage == LBM_F16_SHIFTED_SR || h->d.storage == LBM_BF16_SHIFTED_SR))
+        return fail(LBM_ENOTSUP, "stochastic rounding keys on the step index: no graph replay");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    drop_graphs(h);
+    h->graph_chunk = chunk;
     return LBM_OK;
 }
 
@@ -596,6 +660,7 @@ lbm_status lbm_sensor_average_begin(lbm_blocks *h) {
     hipLaunchKernelGGL(zero_words_kernel, dim3(grid_for((int64_t)(bytes / 8))), dim3(kAuxThreads), 0,
                        h->stream, reinterpret_cast<unsigned long long *>(p), (int)(bytes / 8));
     HIP_TRY(hipGetLastError());
+    drop_graphs(h);   // the step kernels take the averaging pointer
     h->averaging = true;
     h->avg_started = true;
     h->avg_samples = 0;
@@ -824,6 +889,7 @@ lbm_status lbm_autotune(lbm_blocks *h, int32_t reps, int32_t *tile_x) {
     if (h->inplace) std::swap(h->d.buf[LBM_BUF_F_A], h->d.buf[LBM_BUF_F_B]);
     h->phase = saved_phase;
     h->tile_x = (e == hipSuccess) ? best_tile : saved_tile;
+    if (h->tile_x != saved_tile) drop_graphs(h);   // captured with the old tiling
     if (e != hipSuccess) return fail(LBM_EHIP, "autotune: %s", hipGetErrorString(e));
     if (tile_x) *tile_x = h->tile_x;
     return LBM_OK;
@@ -842,6 +908,7 @@ lbm_status lbm_tau_from_reynolds(double u, double n_across, double re, double *t
 void lbm_destroy(lbm_blocks *h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->stream);
+    drop_graphs(h);
     delete h;
 }
 

@@ -417,3 +417,34 @@ def test_channel256_against_1d_reduction(lbm, orc):
         bm_ref = hist[0][1][0, :, 0]
         assert np.abs(bm[0, :, 0] - bm_ref).max() <= EPS_S[storage] * max(bm_ref.max(), 1e-3) * 10
         blk.close()
+
+
+_GRAPH_CASES = [
+    ("cav2d_f64", 9, (64, 64, 1), (WALL, WALL, WALL, WALL, PERIODIC, PERIODIC), 0),
+    ("cav3d_f32s", 19, (40, 24, 20), (WALL,) * 6, 2),
+    ("cav3d_f64", 19, (24, 20, 18), (WALL,) * 6, 0),
+]
+
+
+@pytest.mark.parametrize("case", _GRAPH_CASES, ids=[c[0] for c in _GRAPH_CASES])
+def test_graph_replay_matches_launches(lbm, case, scheme):
+    """lbm_use_graphs: runs of steps replayed from captured graphs (several
+    calls, sensor steps in between, host reads between replays) give the
+    same bits as launching every step."""
+    import torch
+    name, q, n, bc, storage = case
+    print(f"\n[case] graph replay {name} {scheme}", flush=True)
+    out = []
+    for chunk in (0, 6):
+        desc = lbm.make_desc(q, n, bc, 0.6, storage=storage, wall_u=_wall(0.08))
+        blk = lbm.Blocks(desc, stream=torch.cuda.Stream())
+        blk.use_graphs(chunk)
+        res = []
+        for steps, every in ((25, 10), (13, 0), (40, 20), (7, 7)):
+            blk.step_n(steps, every)
+            res.append(blk.sensor_flags()[0])
+        res.append(blk.populations())
+        out.append(res)
+        blk.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
