@@ -111,19 +111,28 @@ def copy_calibration(nbytes=1 << 30, reps=20):
 
 
 def cpu_baseline(w, tau, sample_steps):
-    """The FP64 oracle on the same workload, all host threads, a short run."""
+    """The FP64 oracle on the same workload, all host threads, a short run;
+    also one thread on a shorter run."""
     import oracle
     G = oracle.Grid(q=w.q, n=w.n, bc=w.bc, wall_u=w.wall_u, tau=tau, force=w.force)
     S = G.equilibrium_state()
     S, _ = G.run(S, 0, 1, 1)                   # first touch of the work arrays
+    threads = oracle.threads()
     t0 = time.perf_counter()
     S, _ = G.run(S, 1, sample_steps, w.sensor_every)
     dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    one_steps = max(1, sample_steps // 10)
+    prev = oracle.set_threads(1)
+    t1 = time.perf_counter()
+    S, _ = G.run(S, 1 + sample_steps, one_steps, w.sensor_every)
+    dt1 = time.perf_counter() - t1
+    oracle.set_threads(prev)
     return {"value": round(w.cells * sample_steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
             "sample": f"{sample_steps} steps of the same {w.n[0]}x{w.n[1]}x{w.n[2]} workload in FP64, "
-                      f"sensor every step, {dt:.1f} s"}
+                      f"sensor every step, {dt:.1f} s",
+            "one_core": {"value": round(w.cells * one_steps / dt1 / 1e6, 3), "unit": "MLUPS",
+                         "sample": f"{one_steps} steps, {dt1:.1f} s"}}
 
 
 def run_refined(args, lbm, torch):

@@ -321,6 +321,19 @@ class Grid:
         return self.to_abi(S), history
 
 
+def threads() -> int:
+    """Threads the oracle's OpenMP loops currently use."""
+    return int(_load().orc_max_threads())
+
+
+def set_threads(n: int) -> int:
+    """Threads the oracle's OpenMP loops use from now on; returns the previous count."""
+    lib = _load()
+    prev = lib.orc_max_threads()
+    assert lib.orc_set_threads(int(n)) == 0
+    return prev
+
+
 def tau_from_reynolds(u: float, n_cells: float, re: float) -> float:
     """tau = nu / c_s^2 + 1/2 with nu = u N / Re (Eq. nu_omega, c_s^2 = 1/3)."""
     nu = u * n_cells / re

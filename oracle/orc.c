@@ -39,6 +39,7 @@
  *     (M < theta_c), 0 keep.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -532,3 +533,13 @@ int orc_levels(const orc_params *p, const double *bmax, double a, double b, int 
     free(raw);
     return 0;
 }
+
+/* Threads of the OpenMP loops (timing the oracle on one core or all). */
+int orc_set_threads(int n)
+{
+    if (n < 1) return -1;
+    omp_set_num_threads(n);
+    return 0;
+}
+
+int orc_max_threads(void) { return omp_get_max_threads(); }
