@@ -88,6 +88,20 @@ def _traffic_from_profile(kernel_tag):
         return None
 
 
+def host_env():
+    """GPU, HIP and torch versions and host CPU of this run."""
+    import torch
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    p = torch.cuda.get_device_properties(0)
+    return {"gpu": p.name, "gcn_arch": getattr(p, "gcnArchName", ""), "cus": p.multi_processor_count,
+            "hip": torch.version.hip, "torch": torch.__version__, "cpu": cpu, "cpu_count": os.cpu_count()}
+
+
 def copy_calibration(nbytes=1 << 30, reps=20):
     """Device-to-device copy bandwidth of torch's copy kernel on nbytes
     (read + write counted), the practical ceiling of a streaming kernel; also
@@ -300,8 +314,8 @@ def main():
     ap.add_argument("--cpu-sample-steps", type=int, default=20)
     ap.add_argument("--kernel-samples", type=int, default=200,
                     help="single launches timed one by one for the per-kernel durations")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also time a 1 GiB device copy (reported as copy_gbs)")
+    ap.add_argument("--no-copy-calibration", action="store_true",
+                    help="skip timing a 1 GiB device copy (reported as copy_calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -407,9 +421,10 @@ def main():
         "refine_blocks": int((fl == 1).sum()),
         "nonfinite": bool(nonfinite),
         "wall_s": round(t_wall, 3),
+        "env": host_env(),
     }
     blk.close()
-    if args.copy_calibration:
+    if not args.no_copy_calibration:
         cal = copy_calibration()
         result["copy_calibration"] = cal
         result["roofline"]["frac_of_copy"] = round(achieved / cal["gbs"], 4)

@@ -6,8 +6,10 @@ predictor kernels, one object per step-kernel instantiation (lattice x
 storage type, all from step_inst.hip) and the patch-hierarchy kernels per
 lattice (patch_inst.hip) are compiled in parallel and linked into one shared
 library.  Flags: -O3, C++20, no fast-math (division and
-square root stay correctly rounded), and the packed FP32 instructions
-disabled for the device code.
+square root stay correctly rounded), multiply-adds fused only within one
+source expression (-ffp-contract=on: kernels that spell the same arithmetic
+round the same way, whatever code surrounds it), and the packed FP32
+instructions disabled for the device code.
 """
 from __future__ import annotations
 
@@ -35,7 +37,7 @@ SOURCES = sorted({u[0] for u in UNITS})
 OUT = os.path.join(HERE, "liblbm.so")
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC",
+    "--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC", "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"),
 ]

@@ -89,7 +89,7 @@ struct StepArgs {
     int nbx, nby;           // sensor blocks along x, y
     uint32_t wall;          // bit f set: face f (-x,+x,-y,+y,-z,+z) is a wall
     C wcorr[kMaxQ][6];      // 6 w_i rho0 (xi_i . u_face): moving-wall term per face
-    uint32_t profile;       // bit f set: face f's velocity is smoothed (wall_factor)
+    uint32_t profile;       // bit f set: face f's velocity is smoothed (axis_profile)
     C shift[kMaxQ];         // w_i rho0 rounded to C
     C omega;                // 1 / tau
     C guo;                  // 1 - 1 / (2 tau)
@@ -115,20 +115,71 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
     return xcd * q + min(xcd, r) + local;
 }
 
+// threadIdx.y of a BX x 8 workgroup.  When BX is a multiple of the wave
+// width every wave lies in one row, so the value is read once per wave into
+// a scalar register and everything derived from y stays scalar.
+template <int BX>
+__device__ __forceinline__ int wave_row() {
+    if constexpr (BX % 64 == 0) return __builtin_amdgcn_readfirstlane((int)threadIdx.y);
+    else return (int)threadIdx.y;
+}
+
 // Maximum that propagates NaN from either side.
 template <typename C>
 __device__ __forceinline__ C nan_max(C a, C b) {
     return (a != a || b > a || b != b) ? ((a != a) ? a : b) : a;
 }
 
+// xi_I . v, summed over the non-zero components of xi_I only (IEEE rules
+// keep a compiler from dropping an addition of +0, so none is written).
 template <int Q, int I, typename C>
 __device__ __forceinline__ C dot_c(const C (&u)[3]) {
-    using V = Vel<Q, I>;
-    C s = C(0);
-    if constexpr (V::x != 0) s += C(V::x) * u[0];
-    if constexpr (V::y != 0) s += C(V::y) * u[1];
-    if constexpr (V::z != 0) s += C(V::z) * u[2];
-    return s;
+    constexpr int c[3] = {Vel<Q, I>::x, Vel<Q, I>::y, Vel<Q, I>::z};
+    constexpr int f = c[0] ? 0 : (c[1] ? 1 : (c[2] ? 2 : 3));
+    if constexpr (f == 3) {
+        return C(0);
+    } else {
+        C s = (c[f] > 0) ? u[f] : -u[f];
+        static_for<f + 1, 3>([&](auto ac) {
+            constexpr int k = decltype(ac)::value;
+            if constexpr (c[k] > 0) s += u[k];
+            else if constexpr (c[k] < 0) s -= u[k];
+        });
+        return s;
+    }
+}
+
+// First population with a non-zero component along axis A, or Q if none.
+template <int Q, int A>
+constexpr int first_on_axis() {
+    for (int i = 1; i < Q; ++i)
+        if (Lattice<Q>::c[i][A] != 0) return i;
+    return Q;
+}
+
+// Density offset rho - rho0 and momentum sum_i xi_i d_i of the shifted
+// populations, each summed in population order starting from its first
+// term.  (Pairing opposite populations, d_I - d_opp(I), would save a few
+// additions but biases float32 rounding of the momentum: in a force-driven
+// channel the drift of the velocity profile grows threefold.)
+template <int Q, typename C>
+__device__ __forceinline__ void cell_moments(const C (&d)[Q], C &drho, C (&m)[3]) {
+    drho = d[0];
+    m[0] = m[1] = m[2] = C(0);
+    static_for<1, Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        using V = Vel<Q, i>;
+        drho += d[i];
+        constexpr int c[3] = {V::x, V::y, V::z};
+        static_for<0, 3>([&](auto ac) {
+            constexpr int k = decltype(ac)::value;
+            if constexpr (c[k] != 0) {
+                const C t = (c[k] > 0) ? d[i] : -d[i];
+                if constexpr (i == first_on_axis<Q, k>()) m[k] = t;
+                else m[k] += t;
+            }
+        });
+    });
 }
 
 // x * w for a lattice weight w known at compile time.  In float the weight
@@ -145,68 +196,77 @@ __device__ __forceinline__ C wmul(C x) {
     }
 }
 
-// Neighbourhood of one cell: the pull source coordinate along each axis for
-// a population moving in +axis ("m", coordinate - 1) and in -axis ("p",
-// coordinate + 1), with periodic wrap, and whether that source lies beyond
-// a wall face.
+// Wall-velocity factor of a smoothed face along one in-plane axis (the lid
+// profile of Sec. 5.1): (1 - s^18)^2 with s = (2 c + 1 - n) / n the cell
+// centre mapped to (-1, 1).  An axis of one cell has s = 0, factor 1.
+template <typename C>
+__device__ __forceinline__ C axis_profile(int c, int n) {
+    const C s = C(2 * c + 1 - n) / C(n);
+    const C s2 = s * s, s4 = s2 * s2, s8 = s4 * s4;
+    const C t = C(1) - s8 * s8 * s2;
+    return t * t;
+}
+
+// Neighbourhood of one cell: the element offsets from the cell to its x - 1
+// ("m") and x + 1 ("p") neighbours along each axis, with periodic wrap,
+// whether that neighbour lies beyond a wall face, and per face the factor of
+// that face's wall velocity at the cell: 0 off the face, 1 next to it, or for
+// a smoothed face the product of axis_profile over the face's in-plane axes.
+// Formed once per cell, so that every link is a sum of offsets and a
+// branch-free moving-wall term.  When y and z are the same across a wave
+// (one grid row per wave) their offsets and flags are wave-uniform and live
+// in scalar registers.
+template <typename C>
 struct Geo {
     int x, y, z;
-    int xm, xp, ym, yp, zm, zp;
-    bool wxm, wxp, wym, wyp, wzm, wzp;
     uint32_t cell;
+    int dxm, dxp, dym, dyp, dzm, dzp;
+    bool wxm, wxp, wym, wyp, wzm, wzp;
+    C fw[6];
 };
 
 template <int D, typename C>
-__device__ __forceinline__ Geo make_geo(const StepArgs<C> &a, int x, int y, int z) {
-    Geo g;
+__device__ __forceinline__ Geo<C> make_geo(const StepArgs<C> &a, int x, int y, int z) {
+    Geo<C> g;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int row = nx, slab = nx * ny;
     g.x = x; g.y = y; g.z = z;
     g.wxm = (x == 0) && (a.wall & 1u);
     g.wxp = (x == nx - 1) && (a.wall & 2u);
     g.wym = (y == 0) && (a.wall & 4u);
     g.wyp = (y == ny - 1) && (a.wall & 8u);
-    g.xm = (x == 0) ? nx - 1 : x - 1;
-    g.xp = (x == nx - 1) ? 0 : x + 1;
-    g.ym = (y == 0) ? ny - 1 : y - 1;
-    g.yp = (y == ny - 1) ? 0 : y + 1;
+    g.dxm = (x == 0) ? nx - 1 : -1;
+    g.dxp = (x == nx - 1) ? 1 - nx : 1;
+    g.dym = (y == 0) ? (ny - 1) * row : -row;
+    g.dyp = (y == ny - 1) ? (1 - ny) * row : row;
     g.wzm = g.wzp = false;
-    g.zm = g.zp = z;
+    g.dzm = g.dzp = 0;
     if constexpr (D == 3) {
         g.wzm = (z == 0) && (a.wall & 16u);
         g.wzp = (z == nz - 1) && (a.wall & 32u);
-        g.zm = (z == 0) ? nz - 1 : z - 1;
-        g.zp = (z == nz - 1) ? 0 : z + 1;
+        g.dzm = (z == 0) ? (nz - 1) * slab : -slab;
+        g.dzp = (z == nz - 1) ? (1 - nz) * slab : slab;
     }
-    g.cell = (uint32_t)((z * ny + y) * nx + x);
-    return g;
-}
-
-// Factor of face F's wall velocity at the cell: 1, or for a smoothed face
-// (the lid profile of Sec. 5.1) the product over the face's in-plane axes of
-// (1 - s^18)^2, s = (2 x + 1 - n) / n the cell centre mapped to (-1, 1).  An
-// axis of one cell has s = 0.
-template <int F, typename C>
-__device__ __forceinline__ C wall_factor(const StepArgs<C> &a, const Geo &g) {
-    if (!((a.profile >> F) & 1u)) return C(1);
-    const int coord[3] = {g.x, g.y, g.z};
-    const int ext[3] = {a.nx, a.ny, a.nz};
-    C r = C(1);
+    g.cell = (uint32_t)(z * slab + y * row + x);
+    C pf[6] = {C(1), C(1), C(1), C(1), C(1), C(1)};
+    if (a.profile) {
+        const C t[3] = {axis_profile<C>(x, nx), axis_profile<C>(y, ny), axis_profile<C>(z, nz)};
+        const C face[3] = {t[1] * t[2], t[0] * t[2], t[0] * t[1]};
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        if (ax == F / 2) continue;
-        const C s = C(2 * coord[ax] + 1 - ext[ax]) / C(ext[ax]);
-        const C s2 = s * s, s4 = s2 * s2, s8 = s4 * s4;
-        const C t = C(1) - s8 * s8 * s2;
-        r *= t * t;
+        for (int f = 0; f < 6; ++f)
+            if ((a.profile >> f) & 1u) pf[f] = face[f / 2];
     }
-    return r;
+    const bool on[6] = {g.wxm, g.wxp, g.wym, g.wyp, g.wzm, g.wzp};
+#pragma unroll
+    for (int f = 0; f < 6; ++f) g.fw[f] = on[f] ? pf[f] : C(0);
+    return g;
 }
 
 // The pull link of population I at the cell: its source cell x - xi_I (after
 // periodic wrap), whether the source lies beyond a wall (then the link is
 // bounced), and the moving-wall term 6 w_I rho0 (xi_I . u_w) summed over the
-// wall faces crossed, each face's velocity times its wall_factor (0 off
-// walls).
+// faces xi_I crosses, each face's velocity times its factor at the cell (0
+// off walls).
 template <typename C>
 struct Link {
     bool wall;
@@ -215,21 +275,27 @@ struct Link {
 };
 
 template <int Q, int I, typename C>
-__device__ __forceinline__ Link<C> link(const StepArgs<C> &a, const Geo &g) {
+__device__ __forceinline__ Link<C> link(const StepArgs<C> &a, const Geo<C> &g) {
     using V = Vel<Q, I>;
-    const int sx = (V::x > 0) ? g.xm : ((V::x < 0) ? g.xp : g.x);
-    const int sy = (V::y > 0) ? g.ym : ((V::y < 0) ? g.yp : g.y);
-    const int sz = (V::z > 0) ? g.zm : ((V::z < 0) ? g.zp : g.z);
+    // offset to x - xi_I: the row and slab parts first (wave-uniform when y, z are)
+    int dyz = 0;
+    if constexpr (V::y > 0) dyz += g.dym;
+    if constexpr (V::y < 0) dyz += g.dyp;
+    if constexpr (V::z > 0) dyz += g.dzm;
+    if constexpr (V::z < 0) dyz += g.dzp;
+    int dx = 0;
+    if constexpr (V::x > 0) dx = g.dxm;
+    if constexpr (V::x < 0) dx = g.dxp;
     Link<C> l;
     l.wall = false;
     l.corr = C(0);
-    if constexpr (V::x > 0) { l.wall = l.wall || g.wxm; if (g.wxm) l.corr += a.wcorr[I][0] * wall_factor<0>(a, g); }
-    if constexpr (V::x < 0) { l.wall = l.wall || g.wxp; if (g.wxp) l.corr += a.wcorr[I][1] * wall_factor<1>(a, g); }
-    if constexpr (V::y > 0) { l.wall = l.wall || g.wym; if (g.wym) l.corr += a.wcorr[I][2] * wall_factor<2>(a, g); }
-    if constexpr (V::y < 0) { l.wall = l.wall || g.wyp; if (g.wyp) l.corr += a.wcorr[I][3] * wall_factor<3>(a, g); }
-    if constexpr (V::z > 0) { l.wall = l.wall || g.wzm; if (g.wzm) l.corr += a.wcorr[I][4] * wall_factor<4>(a, g); }
-    if constexpr (V::z < 0) { l.wall = l.wall || g.wzp; if (g.wzp) l.corr += a.wcorr[I][5] * wall_factor<5>(a, g); }
-    l.src = (uint32_t)((sz * a.ny + sy) * a.nx + sx);
+    if constexpr (V::x > 0) { l.wall = l.wall || g.wxm; l.corr += a.wcorr[I][0] * g.fw[0]; }
+    if constexpr (V::x < 0) { l.wall = l.wall || g.wxp; l.corr += a.wcorr[I][1] * g.fw[1]; }
+    if constexpr (V::y > 0) { l.wall = l.wall || g.wym; l.corr += a.wcorr[I][2] * g.fw[2]; }
+    if constexpr (V::y < 0) { l.wall = l.wall || g.wyp; l.corr += a.wcorr[I][3] * g.fw[3]; }
+    if constexpr (V::z > 0) { l.wall = l.wall || g.wzm; l.corr += a.wcorr[I][4] * g.fw[4]; }
+    if constexpr (V::z < 0) { l.wall = l.wall || g.wzp; l.corr += a.wcorr[I][5] * g.fw[5]; }
+    l.src = g.cell + (uint32_t)(dx + dyz);
     return l;
 }
 
@@ -307,16 +373,34 @@ __device__ __forceinline__ typename Storage<T>::raw to_storage(C x, uint32_t key
     }
 }
 
-// Element address inside planes {I, opp(I)}: both candidates of every access
-// lie in those two planes, so they are addressed from the lower of the two
-// with a non-negative 32-bit offset.
+// Planes {I, opp(I)} hold both candidates of every access of population I,
+// so an access is the base of the lower of the two planes (wave-uniform)
+// plus a 32-bit byte offset: plane_of(I, plane) * pitch + cell elements,
+// where plane_of is 0 for the lower plane and 1 for the upper one.  Choosing
+// between a bounced and a streamed source is then a select of two offsets.
+template <int Q, int I, typename T>
+__device__ __forceinline__ typename Storage<T>::raw *pair_base(void *buf, uint32_t pitch) {
+    using R = typename Storage<T>::raw;
+    constexpr int lo = (Vel<Q, I>::opp < I) ? Vel<Q, I>::opp : I;
+    return reinterpret_cast<R *>(static_cast<char *>(buf) + (size_t)lo * pitch * sizeof(R));
+}
+
+template <int Q, int I, typename T>
+__device__ __forceinline__ uint32_t pair_off(uint32_t pitch, int plane, uint32_t cell) {
+    using R = typename Storage<T>::raw;
+    constexpr int lo = (Vel<Q, I>::opp < I) ? Vel<Q, I>::opp : I;
+    return ((uint32_t)(plane - lo) * pitch + cell) * (uint32_t)sizeof(R);
+}
+
+template <typename R>
+__device__ __forceinline__ R *at_byte(R *base, uint32_t off) {
+    return reinterpret_cast<R *>(reinterpret_cast<char *>(base) + off);
+}
+
 template <int Q, int I, typename T>
 __device__ __forceinline__ typename Storage<T>::raw *pair_addr(void *buf, uint32_t pitch, int plane,
                                                                 uint32_t cell) {
-    using R = typename Storage<T>::raw;
-    constexpr int lo = (Vel<Q, I>::opp < I) ? Vel<Q, I>::opp : I;
-    const uint32_t boff = ((uint32_t)(plane - lo) * pitch + cell) * (uint32_t)sizeof(R);
-    return reinterpret_cast<R *>(static_cast<char *>(buf) + (size_t)lo * pitch * sizeof(R) + boff);
+    return at_byte(pair_base<Q, I, T>(buf, pitch), pair_off<Q, I, T>(pitch, plane, cell));
 }
 
 // The q pre-collision populations of the cell as shifted values
@@ -326,25 +410,27 @@ __device__ __forceinline__ typename Storage<T>::raw *pair_addr(void *buf, uint32
 //              buffer (S_i(y) is kept in slot opp(i) of y);
 //   kLocal   : f_i is in slot i of the cell itself.
 template <int Q, typename T, typename C, bool SHIFTED, int SCHEME>
-__device__ __forceinline__ void load_cell(const StepArgs<C> &a, const Geo &g, C (&d)[Q]) {
+__device__ __forceinline__ void load_cell(const StepArgs<C> &a, const Geo<C> &g, C (&d)[Q]) {
     void *src = const_cast<void *>(a.src);
     static_for<0, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         constexpr int o = Vel<Q, i>::opp;
-        C v, corr = C(0);
-        if constexpr (SCHEME == kLocal) {
-            v = static_cast<C>(*pair_addr<Q, i, T>(src, a.pitch, i, g.cell));
+        if constexpr (SCHEME == kLocal || i == 0) {
+            // no link crosses a face: the value is the cell's own
+            const int plane = (SCHEME == kStream) ? o : i;
+            C v = static_cast<C>(*pair_addr<Q, i, T>(src, a.pitch, plane, g.cell));
+            if constexpr (!SHIFTED) v -= a.shift[i];
+            d[i] = v;
         } else {
             const Link<C> l = link<Q, i>(a, g);
             const int plane_pull = (SCHEME == kPingPong) ? i : o;
             const int plane_bounce = (SCHEME == kPingPong) ? o : i;
-            const auto *p = l.wall ? pair_addr<Q, i, T>(src, a.pitch, plane_bounce, g.cell)
-                                   : pair_addr<Q, i, T>(src, a.pitch, plane_pull, l.src);
-            v = static_cast<C>(*p);
-            corr = l.corr;
+            const uint32_t off = l.wall ? pair_off<Q, i, T>(a.pitch, plane_bounce, g.cell)
+                                        : pair_off<Q, i, T>(a.pitch, plane_pull, l.src);
+            C v = static_cast<C>(*at_byte(pair_base<Q, i, T>(src, a.pitch), off));
+            if constexpr (!SHIFTED) v -= a.shift[i];   // shift[i] == shift[opp(i)]
+            d[i] = v + l.corr;
         }
-        if constexpr (!SHIFTED) v -= a.shift[i];   // shift[i] == shift[opp(i)]
-        d[i] = v + corr;
     });
 }
 
@@ -355,19 +441,18 @@ __device__ __forceinline__ void load_cell(const StepArgs<C> &a, const Geo &g, C 
 //              the next step; if x + xi_I lies beyond a wall the value
 //              returns to the cell as opp(I) with the moving-wall term.
 template <int Q, int I, typename T, typename C, int SCHEME>
-__device__ __forceinline__ void store_pop(const StepArgs<C> &a, const Geo &g, C out, uint32_t ckey) {
+__device__ __forceinline__ void store_pop(const StepArgs<C> &a, const Geo<C> &g, C out, uint32_t ckey) {
     constexpr int o = Vel<Q, I>::opp;
     const uint32_t key = Storage<T>::sr ? round_key(ckey, I) : 0u;
     if constexpr (SCHEME == kPingPong) {
         __builtin_nontemporal_store(to_storage<T>(out, key), pair_addr<Q, I, T>(a.dst, a.pitch, I, g.cell));
-    } else if constexpr (SCHEME == kLocal) {
+    } else if constexpr (SCHEME == kLocal || I == 0) {
         *pair_addr<Q, I, T>(a.dst, a.pitch, o, g.cell) = to_storage<T>(out, key);
     } else {
         // the scatter link of I is the pull link of opp(I) read backwards
         const Link<C> l = link<Q, o>(a, g);
-        auto *p = l.wall ? pair_addr<Q, I, T>(a.dst, a.pitch, o, g.cell)
-                         : pair_addr<Q, I, T>(a.dst, a.pitch, I, l.src);
-        *p = to_storage<T>(out + l.corr, key);
+        const uint32_t off = l.wall ? pair_off<Q, I, T>(a.pitch, o, g.cell) : pair_off<Q, I, T>(a.pitch, I, l.src);
+        *at_byte(pair_base<Q, I, T>(a.dst, a.pitch), off) = to_storage<T>(out + l.corr, key);
     }
 }
 
@@ -375,22 +460,14 @@ __device__ __forceinline__ void store_pop(const StepArgs<C> &a, const Geo &g, C 
 // cell.  Returns the cell's sensor value: ||f^neq||^2 / ||f^eq||^2 (L2; the
 // square root is taken once per block) or K_Kn.
 template <int Q, typename T, typename C, bool SHIFTED, bool SENSOR, int SKIND, int MODEL, int SCHEME>
-__device__ __forceinline__ C collide_store(const StepArgs<C> &a, const Geo &g, const C (&d)[Q]) {
+__device__ __forceinline__ C collide_store(const StepArgs<C> &a, const Geo<C> &g, const C (&d)[Q]) {
     constexpr bool FORCE = (MODEL & kModelForce) != 0;
     constexpr bool SMAG = (MODEL & kModelSmag) != 0;
     // moments (Eqs. rho and u), Guo's half-force shift
-    C drho = C(0), mx = C(0), my = C(0), mz = C(0);
-    static_for<0, Q>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        using V = Vel<Q, i>;
-        drho += d[i];
-        if constexpr (V::x != 0) mx += C(V::x) * d[i];
-        if constexpr (V::y != 0) my += C(V::y) * d[i];
-        if constexpr (V::z != 0) mz += C(V::z) * d[i];
-    });
+    C drho, j[3];   // rho - rho0, rho u
+    cell_moments<Q>(d, drho, j);
     const C rho = a.rho0 + drho;
     const C inv_rho = C(1) / rho;
-    C j[3] = {mx, my, mz};   // rho u
     if constexpr (FORCE) {
         j[0] += C(0.5) * a.F[0];
         j[1] += C(0.5) * a.F[1];
@@ -429,15 +506,12 @@ __device__ __forceinline__ C collide_store(const StepArgs<C> &a, const Geo &g, c
 
     C num = C(0), den = C(0), kkn = C(0);
     const uint32_t ckey = Storage<T>::sr ? cell_key(g.cell, a.step) : 0u;
-    static_for<0, Q>([&](auto ic) {
+    const C m15usq = C(-1.5) * usq;
+    // Relaxation of population I given the bracket of its equilibrium,
+    // f^eq_I - w_I rho0 = w_I [ (rho - rho0) + 3 xi_I.(rho u) + rho (9/2 (xi_I.u)^2 - 3/2 u^2) ].
+    auto relax = [&](auto ic, C br, C cu) {
         constexpr int i = decltype(ic)::value;
         using V = Vel<Q, i>;
-        const C cu = dot_c<Q, i>(u);
-        const C cj = dot_c<Q, i>(j);
-        // f^eq_i - w_i rho0 = w_i [ (rho - rho0) + 3 xi.(rho u) + rho (9/2 cu^2 - 3/2 u^2) ],
-        // rho (...) taken as rho0 (...) + (rho - rho0) (...)
-        const C p2 = C(4.5) * cu * cu - C(1.5) * usq;
-        const C br = drho + C(3) * cj + (a.rho0 * p2 + drho * p2);
         const C deq = wmul<C, V::w>(br);
         const C fneq = d[i] - deq;
         if constexpr (SENSOR) {
@@ -459,6 +533,19 @@ __device__ __forceinline__ C collide_store(const StepArgs<C> &a, const Geo &g, c
         }
         if constexpr (!SHIFTED) out += a.shift[i];
         store_pop<Q, i, T, C, SCHEME>(a, g, out, ckey);
+    };
+    // rest population: xi = 0
+    relax(std::integral_constant<int, 0>{}, drho + (a.rho0 * m15usq + drho * m15usq), C(0));
+    // opposite pairs I, I + 1 share (xi.u)^2 and so the even part of the bracket,
+    // rho - rho0 + rho (9/2 (xi.u)^2 - 3/2 u^2), with rho taken as rho0 + (rho - rho0)
+    static_for<0, (Q - 1) / 2>([&](auto kc) {
+        constexpr int i = 2 * decltype(kc)::value + 1;
+        const C cu = dot_c<Q, i>(u);
+        const C cj = dot_c<Q, i>(j);
+        const C p2 = C(4.5) * cu * cu + m15usq;
+        const C even = drho + (a.rho0 * p2 + drho * p2);
+        relax(std::integral_constant<int, i>{}, even + C(3) * cj, cu);
+        relax(std::integral_constant<int, i + 1>{}, even - C(3) * cj, -cu);
     });
     if constexpr (SENSOR) {
         if constexpr (SKIND == kSensorL2) return num / den;
@@ -524,11 +611,11 @@ __global__ __launch_bounds__(BX *kTileY) void step_cells(const StepArgs<C> a) {
     const int tiy = rest % a.nty;
     const int z = rest / a.nty;
     const int x = tix * BX + (int)threadIdx.x;
-    const int y = tiy * kTileY + (int)threadIdx.y;
+    const int y = tiy * kTileY + wave_row<BX>();
 
     C s = C(0);
     if (x < a.nx && y < a.ny) {
-        const Geo g = make_geo<D>(a, x, y, z);
+        const Geo<C> g = make_geo<D>(a, x, y, z);
         C d[Q];
         load_cell<Q, T, C, SHIFTED, SCHEME>(a, g, d);
         s = collide_store<Q, T, C, SHIFTED, SENSOR, SKIND, MODEL, SCHEME>(a, g, d);
@@ -574,7 +661,7 @@ __global__ __launch_bounds__(BX *kTileY) void step_zmarch(const StepArgs<C> a) {
     const int tiy = rest % a.nty;
     const int tiz = rest / a.nty;
     const int x = tix * BX + (int)threadIdx.x;
-    const int y = tiy * kTileY + (int)threadIdx.y;
+    const int y = tiy * kTileY + wave_row<BX>();
     const int z0 = tiz * kBlockEdge;
 
     C m = C(0);
@@ -582,7 +669,7 @@ __global__ __launch_bounds__(BX *kTileY) void step_zmarch(const StepArgs<C> a) {
         const int zend = min(z0 + kBlockEdge, a.nz);
 #pragma unroll 1
         for (int z = z0; z < zend; ++z) {
-            const Geo g = make_geo<3>(a, x, y, z);
+            const Geo<C> g = make_geo<3>(a, x, y, z);
             C d[Q];
             load_cell<Q, T, C, SHIFTED, kPingPong>(a, g, d);
             const C s = collide_store<Q, T, C, SHIFTED, SENSOR, SKIND, MODEL, kPingPong>(a, g, d);
@@ -614,7 +701,7 @@ __global__ void unstream_kernel(const StepArgs<C> a, T *out) {
     const int x = c % a.nx;
     const int y = (c / a.nx) % a.ny;
     const int z = c / (a.nx * a.ny);
-    const Geo g = make_geo<D>(a, x, y, z);
+    const Geo<C> g = make_geo<D>(a, x, y, z);
     void *src = const_cast<void *>(a.src);
     static_for<0, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
