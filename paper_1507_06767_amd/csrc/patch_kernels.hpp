@@ -146,37 +146,69 @@ __device__ __forceinline__ int64_t padded_index(const PatchRec &p, int x, int y,
 // (W x 8 x 8 cells) at a time: thread t takes x = t mod W, y = (t / W) mod 8
 // and marches z from t / 8W in steps of 64 / W, so a wave reads W
 // consecutive cells of 64 / W rows (rows of up to 128 bytes in float32).  It
-// loops over the tiles of all patches with a fixed stride (a persistent
-// launch of fewer workgroups than tiles): pull-stream from the padded
+// loops over the tiles of all patches (a persistent launch of fewer
+// workgroups than tiles, each XCD taking a contiguous part of the list):
+// pull-stream from the padded
 // neighbours, BGK collision, and on sensor steps the maxima and flags of the
 // tile's W/8 blocks, reduced in the workgroup without atomics.
+//
+// Addressing: the pull source of population i is the cell's padded index c
+// minus delta_i = xi_x + xi_y sy + xi_z sz, the same for every cell of a
+// patch, so it is folded into the population's plane base (one scalar
+// address per population and tile) and every load and store of the cell
+// uses the one 32-bit byte offset c * sizeof(T).  The collision is the step
+// kernel's: moments in population order, the even part of the equilibrium
+// shared by each opposite pair.
 template <int Q, typename T, typename C, bool SH, bool SENSOR, int SKIND>
 __global__ __launch_bounds__(512) void patch_step(const PatchArgs<C> a) {
     static_assert(Lattice<Q>::D == 3, "3D patches");
     __shared__ C red[8][4];      // [wave][block of the tile]
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    for (int k = blockIdx.x; k < a.ntiles; k += gridDim.x) {
+    const char *src = static_cast<const char *>(a.src);
+    char *dst = static_cast<char *>(a.dst);
+    const int64_t plane_bytes = a.pitch * (int64_t)sizeof(T);
+    // Workgroups are dealt to the 8 XCDs round-robin by id.  With at least 8
+    // workgroups, XCD j works through the j-th eighth of the tile list (tiles
+    // are listed x fastest, patch by patch), so that tiles sharing halo lines
+    // are fetched into one L2; every tile is visited exactly once either way.
+    int k0 = blockIdx.x, k1 = a.ntiles, kstep = gridDim.x;
+    if (gridDim.x >= 8) {
+        const int xcd = blockIdx.x & 7;
+        k0 = (int)((int64_t)a.ntiles * xcd / 8) + (int)(blockIdx.x >> 3);
+        k1 = (int)((int64_t)a.ntiles * (xcd + 1) / 8);
+        kstep = (int)((gridDim.x - xcd + 7) >> 3);
+    }
+    for (int k = k0; k < k1; k += kstep) {
         const PatchTile tl = a.tile[k];
         const PatchRec p = a.patch[tl.patch];
         const int W = tl.w;
         const int x = t % W, y = (t / W) & 7, zstep = 64 / W;
-        const int64_t sy = p.e[0] + 2, sz = sy * (p.e[1] + 2);
+        const int sy = p.e[0] + 2, sz = sy * (p.e[1] + 2);
         C m = C(0);
 #pragma unroll 1
         for (int zz = t / (8 * W); zz < 8; zz += zstep) {
-            const int64_t c = padded_index(p, tl.x0 + x, tl.y0 + y, tl.z0 + zz);
+            // padded cell index (< 2^29, checked on the host) as a byte offset
+            const uint32_t cb = (uint32_t)(p.off + (tl.z0 + zz + 1) * sz + (tl.y0 + y + 1) * sy + (tl.x0 + x + 1)) *
+                                (uint32_t)sizeof(T);
             C d[Q];
             static_for<0, Q>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
                 using V = Vel<Q, i>;
-                const int64_t from = c - (V::x + V::y * sy + V::z * sz);
-                d[i] = load_dev<T>(a.src, i * a.pitch + from, a.shift[i], SH);
+                const int64_t delta = V::x + (int64_t)V::y * sy + (int64_t)V::z * sz;
+                const char *base = src + i * plane_bytes - delta * (int64_t)sizeof(T);
+                const C v = static_cast<C>(*reinterpret_cast<const T *>(base + cb));
+                if constexpr (SH) d[i] = v;
+                else d[i] = v - a.shift[i];
             });
-            const Moments<Q, C> mo = moments_of<Q>(d, a.rho0);
+            C drho, j[3];
+            cell_moments<Q>(d, drho, j);
+            const C inv_rho = C(1) / (a.rho0 + drho);
+            const C u[3] = {j[0] * inv_rho, j[1] * inv_rho, j[2] * inv_rho};
+            const C m15usq = C(-1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
             C num = C(0), den = C(0), kkn = C(0);
-            static_for<0, Q>([&](auto ic) {
+            auto relax = [&](auto ic, C br) {
                 constexpr int i = decltype(ic)::value;
-                const C deq = deq_of<Q, i>(mo, a.rho0);
+                const C deq = wmul<C, Vel<Q, i>::w>(br);
                 const C fneq = d[i] - deq;
                 if constexpr (SENSOR) {
                     const C feq = a.shift[i] + deq;
@@ -187,7 +219,19 @@ __global__ __launch_bounds__(512) void patch_step(const PatchArgs<C> a) {
                         kkn += fabs(fneq / feq);
                     }
                 }
-                store_dev<T>(a.dst, i * a.pitch + c, d[i] - a.omega * fneq, a.shift[i], SH);
+                C out = d[i] - a.omega * fneq;
+                if constexpr (!SH) out += a.shift[i];
+                *reinterpret_cast<T *>(dst + i * plane_bytes + cb) = static_cast<T>(out);
+            };
+            relax(std::integral_constant<int, 0>{}, drho + (a.rho0 * m15usq + drho * m15usq));
+            static_for<0, (Q - 1) / 2>([&](auto kc) {
+                constexpr int i = 2 * decltype(kc)::value + 1;
+                const C cu = dot_c<Q, i>(u);
+                const C cj = dot_c<Q, i>(j);
+                const C p2 = C(4.5) * cu * cu + m15usq;
+                const C even = drho + (a.rho0 * p2 + drho * p2);
+                relax(std::integral_constant<int, i>{}, even + C(3) * cj);
+                relax(std::integral_constant<int, i + 1>{}, even - C(3) * cj);
             });
             if constexpr (SENSOR) m = nan_max(m, SKIND == kSensorL2 ? num / den : kkn * C(1.0 / Q));
         }
