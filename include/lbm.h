@@ -353,6 +353,16 @@ lbm_status lbm_hierarchy_info(lbm_hierarchy *H, int64_t *fine_cells, int64_t *fi
 lbm_status lbm_hierarchy_autotune(lbm_hierarchy *H, int32_t reps, int32_t *tile_x, int32_t *workgroups,
                                   double *step_us);
 
+/* Advances the hierarchy by `steps` coarse steps (no sensor) launched one by
+ * one, with HIP events recorded between the kernels on the handle's stream,
+ * and writes the mean duration of one launch of each kind, in microseconds:
+ * us[0] the coarse step, us[1] a ghost fill, us[2] a fine step over all
+ * patches, us[3] the restriction.  The kernels run in their production order
+ * and on production data, so their caches are warm or cold as they would be
+ * in stepping; each bracket also times a few microseconds of event packets.
+ * steps >= 1; us must hold 4 doubles.  Synchronises. */
+lbm_status lbm_hierarchy_profile(lbm_hierarchy *H, int32_t steps, double *us);
+
 /* Releases the hierarchy (host memory and graphs); buffers are untouched. */
 void lbm_destroy_hierarchy(lbm_hierarchy *H);
 

@@ -19,7 +19,8 @@ from .abi import (  # noqa: F401
     lbm_conservation, lbm_tau_from_reynolds, lbm_destroy, lbm_last_error,
     lbm_sensor_levels, lbm_sensor_average_begin, lbm_sensor_average, lbm_sensor_average_end,
     lbm_autotune, lbm_use_graphs, lbm_hierarchy_required_bytes, lbm_create_hierarchy, lbm_hierarchy_step, lbm_hierarchy_sensor,
-    lbm_hierarchy_patch_fields, lbm_hierarchy_info, lbm_hierarchy_autotune, lbm_destroy_hierarchy,
+    lbm_hierarchy_patch_fields, lbm_hierarchy_info, lbm_hierarchy_autotune, lbm_hierarchy_profile,
+    lbm_destroy_hierarchy,
 )
 from .blocks import Blocks  # noqa: F401
 from .hierarchy import Hierarchy  # noqa: F401

@@ -120,6 +120,7 @@ def _load_library():
         "lbm_hierarchy_patch_fields": [H, ctypes.c_int32, dp, dp, dp],
         "lbm_hierarchy_info": [H, i64p, i64p, dp, dp, i32p, i32p],
         "lbm_hierarchy_autotune": [H, ctypes.c_int32, i32p, i32p, dp],
+        "lbm_hierarchy_profile": [H, ctypes.c_int32, dp],
     })
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -354,6 +355,13 @@ def lbm_hierarchy_autotune(H, reps: int):
     tz, wg, us = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0.0)
     st = _lib.lbm_hierarchy_autotune(H, int(reps), ctypes.byref(tz), ctypes.byref(wg), ctypes.byref(us))
     return st, tz.value, wg.value, us.value
+
+
+def lbm_hierarchy_profile(H, steps: int):
+    """(status, [coarse step, ghost fill, fine step, restriction] microseconds per launch)."""
+    us = (ctypes.c_double * 4)()
+    st = _lib.lbm_hierarchy_profile(H, int(steps), us)
+    return st, list(us)
 
 
 def lbm_destroy_hierarchy(H):

@@ -269,24 +269,36 @@ void hier_ghosts(lbm_hierarchy *H, void *state, const void *s0, const void *s1, 
 }
 
 // One coarse step (steps 1-6 above) enqueued on the coarse handle's stream.
-void hier_coarse_step(lbm_hierarchy *H, bool sens) {
+// With `ev` (7 events), the events are recorded before, between and after
+// the six launches, for lbm_hierarchy_profile.
+void hier_coarse_step(lbm_hierarchy *H, bool sens, hipEvent_t *ev = nullptr) {
     lbm_blocks *h = H->coarse;
+    auto mark = [&](int i) {
+        if (ev) (void)hipEventRecord(ev[i], h->stream);
+    };
     void *X = state_ptr(h);
     void *Y = h->d.buf[h->cur ? LBM_BUF_F_A : LBM_BUF_F_B];
     void *A = fine_buf(H, H->cur), *B = fine_buf(H, H->cur ^ 1);
+    mark(0);
     hier_ghosts(H, A, X, X, 0.0);
+    mark(1);
     hier_fine_step(H, A, B, false);
+    mark(2);
     const int64_t step = h->step + 1;
     launch_step_any(h, sens);
+    mark(3);
     h->cur ^= 1;
     h->step = step;
     if (sens) h->last_sensor_step = step;
     hier_ghosts(H, B, X, Y, 0.5);
+    mark(4);
     hier_fine_step(H, B, A, sens);
+    mark(5);
     with_hier_types(H, [&]<int Q, typename T, typename C, bool SH>() {
         launch_patch_restrict<Q, T, C, SH>(patch_args<C>(H, A, A), coarse_view<C>(H, Y, Y, 0.0, Y), A,
                                            patch_lists(H), h->stream);
     });
+    mark(6);
     H->step += 1;
     if (sens) H->last_sensor_step = H->step;
 }
@@ -656,6 +668,38 @@ lbm_status lbm_hierarchy_autotune(lbm_hierarchy *H, int32_t reps, int32_t *tile_
     if (tile_x) *tile_x = H->wmax;
     if (workgroups) *workgroups = H->nwg;
     if (step_us) *step_us = 1e3 * (double)best / reps;
+    return LBM_OK;
+}
+
+lbm_status lbm_hierarchy_profile(lbm_hierarchy *H, int32_t steps, double *us) {
+    lbm_status st = hier_check(H);
+    if (st != LBM_OK) return st;
+    if (steps < 1) return fail(LBM_EINVAL, "steps = %d < 1", steps);
+    if (!us) return fail(LBM_EINVAL, "us is NULL");
+    hipEvent_t ev[7] = {};
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 7 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+    // sums over launches: coarse, ghosts (two per step), fine (two), restriction
+    double sum[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int32_t k = 0; k < steps && e == hipSuccess; ++k) {
+        hier_coarse_step(H, false, ev);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipEventSynchronize(ev[6]);
+        float ms[6] = {};
+        for (int i = 0; i < 6 && e == hipSuccess; ++i) e = hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]);
+        // launch order: ghosts, fine, coarse, ghosts, fine, restriction
+        sum[1] += ms[0] + ms[3];
+        sum[2] += ms[1] + ms[4];
+        sum[0] += ms[2];
+        sum[3] += ms[5];
+    }
+    for (int i = 0; i < 7; ++i)
+        if (ev[i]) (void)hipEventDestroy(ev[i]);
+    if (e != hipSuccess) return fail(LBM_EHIP, "profile: %s", hipGetErrorString(e));
+    us[0] = 1e3 * sum[0] / steps;
+    us[1] = 1e3 * sum[1] / (2.0 * steps);
+    us[2] = 1e3 * sum[2] / (2.0 * steps);
+    us[3] = 1e3 * sum[3] / steps;
     return LBM_OK;
 }
 

@@ -338,7 +338,8 @@ __global__ __launch_bounds__(256) void patch_ghosts_lds(const PatchArgs<C> a, co
                                                         const int *gsrc, const int *gloc, const uint32_t *gmask) {
     static_assert(kGhostBox <= 256, "one box cell per thread");
     __shared__ C box[Q * kGhostBox];
-    const GhostTile tl = tiles[blockIdx.x];
+    // neighbouring tiles of a face share coarse lines: give each XCD a run of them
+    const GhostTile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const int ncell = tl.dx * tl.dy * tl.dz;
     if ((int)threadIdx.x < ncell) {
         const int cell = threadIdx.x;

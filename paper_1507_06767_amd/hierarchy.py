@@ -70,6 +70,14 @@ class Hierarchy:
         _check(st)
         return tz, wg, us
 
+    def profile(self, steps: int = 4):
+        """Advances `steps` coarse steps launched one by one and returns the
+        mean microseconds per launch of each kernel kind, timed with HIP
+        events in production order: {"coarse", "ghosts", "fine", "restrict"}."""
+        st, us = abi.lbm_hierarchy_profile(self.h, steps)
+        _check(st)
+        return dict(zip(("coarse", "ghosts", "fine", "restrict"), us))
+
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value is not None:
             abi.lbm_destroy_hierarchy(self.h)

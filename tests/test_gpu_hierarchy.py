@@ -182,3 +182,32 @@ def test_lds_ghost_fill_matches_list_fill(env, monkeypatch, q):
     assert np.array_equal(out["lds"][0], out["plain"][0]) and np.array_equal(out["lds"][2], out["plain"][2])
     for a, b in zip(out["lds"][1], out["plain"][1]):
         assert np.array_equal(a, b)
+
+
+def test_profile_times_kernels_and_steps_like_eager(env):
+    """lbm_hierarchy_profile advances the state exactly as eager stepping
+    does (identical bits) and returns positive per-launch durations."""
+    torch, lbm = env
+    print("\n[case] hierarchy profile", flush=True)
+    out = []
+    for prof in (True, False):
+        blk, H = _make(torch, lbm, 19, 2, use_graph=False)
+        H.step_n(2, 0)
+        if prof:
+            us = H.profile(3)
+            print("profile us per launch:", {k: round(v, 1) for k, v in us.items()})
+            assert set(us) == {"coarse", "ghosts", "fine", "restrict"}
+            assert all(v > 0.0 for v in us.values())
+        else:
+            H.step_n(3, 0)
+        out.append((blk.populations(), [H.patch_fields(p)[2] for p in range(len(_BOXES))]))
+        H.close()
+        blk.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    for a, b in zip(out[0][1], out[1][1]):
+        assert np.array_equal(a, b)
+    blk, H = _make(torch, lbm, 19, 2, use_graph=False)
+    st, _ = lbm.lbm_hierarchy_profile(H.h, 0)
+    assert st == lbm.LBM_EINVAL
+    H.close()
+    blk.close()
