@@ -33,7 +33,8 @@ The value counts lattice updates of both levels; the roofline entry prices
 the fine step (all patches, one persistent launch) at one read and one write
 of every population of every fine cell, its duration timed in production
 order after the timed region (lbm_hierarchy_profile: HIP events between the
-launches of 4 coarse steps; all four kernels are listed under
+launches of 4 coarse steps; the coarse step, ghost fill and the second fine
+step, which also restricts to the coarse level, are listed beside it under
 per_kernel_us).
 
 --workload cavity64_2d: the 64^2 D2Q9 float64 cavity (Re 100, 2000 steps,
@@ -186,7 +187,7 @@ def run_refined(args, lbm, torch):
     # launched one by one, HIP events between the launches)
     prof = H.profile(4)
     fine_us_tuned = fine_us
-    fine_us = prof["fine"]
+    fine_us = prof["fine"]        # the first fine step (the second also restricts)
     H.step_n(2, 2)
     fbm, ffl, _ = H.sensor()
     rho, u = blk.macros()
@@ -216,7 +217,7 @@ def run_refined(args, lbm, torch):
                      "kernel": "patch_step (all patches, one persistent launch)",
                      "algorithmic_bytes_per_launch": fine_bytes,
                      "per_kernel_us": {"patch_step": round(prof["fine"], 2), "patch_ghosts": round(prof["ghosts"], 2),
-                                       "patch_restrict": round(prof["restrict"], 2),
+                                       "patch_step_with_restriction": round(prof["fine_restrict"], 2),
                                        "coarse_step": round(prof["coarse"], 2)},
                      "patch_step_us_autotune": round(fine_us_tuned, 2)},
         "fine_refine_blocks": int((ffl == 1).sum()),

@@ -355,9 +355,10 @@ lbm_status lbm_hierarchy_autotune(lbm_hierarchy *H, int32_t reps, int32_t *tile_
 
 /* Advances the hierarchy by `steps` coarse steps (no sensor) launched one by
  * one, with HIP events recorded between the kernels on the handle's stream,
- * and writes the mean duration of one launch of each kind, in microseconds:
- * us[0] the coarse step, us[1] a ghost fill, us[2] a fine step over all
- * patches, us[3] the restriction.  The kernels run in their production order
+ * and writes mean durations in microseconds: us[0] the coarse step, us[1] a
+ * ghost fill, us[2] the first fine step over all patches, us[3] the second
+ * fine step, which also restricts the fine level to the covered coarse
+ * cells.  The kernels run in their production order
  * and on production data, so their caches are warm or cold as they would be
  * in stepping; each bracket also times a few microseconds of event packets.
  * steps >= 1; us must hold 4 doubles.  Synchronises. */

@@ -358,7 +358,8 @@ def lbm_hierarchy_autotune(H, reps: int):
 
 
 def lbm_hierarchy_profile(H, steps: int):
-    """(status, [coarse step, ghost fill, fine step, restriction] microseconds per launch)."""
+    """(status, [coarse step, ghost fill, first fine step, second fine step with the
+    restriction] microseconds)."""
     us = (ctypes.c_double * 4)()
     st = _lib.lbm_hierarchy_profile(H, int(steps), us)
     return st, list(us)

@@ -12,10 +12,12 @@
 // Steps 1-6 of two consecutive coarse steps are captured once into a HIP
 // graph per coarse parity and replayed (the kernels' arguments repeat every
 // two coarse steps).  The fine step walks a tile list, the ghost fill a
-// ghost list and the restriction a list of covered coarse cells, all built
-// here on the host at creation.
+// ghost list and the separate restriction kernel (a comparison path; the
+// second fine step restricts by default) a list of covered coarse cells, all
+// built here on the host at creation.
 
 #include <array>
+#include <string>
 
 #include "patch_kernels.hpp"
 
@@ -254,11 +256,21 @@ hipError_t upload_tiles(lbm_hierarchy *H) {
                           hipMemcpyHostToDevice, H->coarse->stream);
 }
 
-void hier_fine_step(lbm_hierarchy *H, const void *src, void *dst, bool sensor) {
+// A fine step over all patches; with `restrict_out` (the coarse state being
+// completed) it also restricts every covered coarse cell to it.
+void hier_fine_step(lbm_hierarchy *H, const void *src, void *dst, bool sensor, void *restrict_out = nullptr) {
     with_hier_types(H, [&]<int Q, typename T, typename C, bool SH>() {
-        PatchLaunch l{H->coarse->stream, sensor, H->coarse->d.sensor_kind, H->nwg};
-        launch_patch_step<Q, T, C, SH>(patch_args<C>(H, src, dst), l);
+        PatchLaunch l{H->coarse->stream, sensor, H->coarse->d.sensor_kind, restrict_out != nullptr, H->nwg};
+        launch_patch_step<Q, T, C, SH>(patch_args<C>(H, src, dst),
+                                       coarse_view<C>(H, restrict_out, restrict_out, 0.0, restrict_out), l);
     });
+}
+
+// The restriction runs inside the second fine step unless LBM_HIER_RESTRICT
+// is "separate" (its own kernel over the precomputed list; for comparison).
+bool restriction_fused() {
+    const char *s = std::getenv("LBM_HIER_RESTRICT");
+    return !(s && std::string(s) == "separate");
 }
 
 void hier_ghosts(lbm_hierarchy *H, void *state, const void *s0, const void *s1, double w1) {
@@ -268,7 +280,8 @@ void hier_ghosts(lbm_hierarchy *H, void *state, const void *s0, const void *s1, 
     });
 }
 
-// One coarse step (steps 1-6 above) enqueued on the coarse handle's stream.
+// One coarse step (steps 1-6 above; step 6 inside step 5 by default)
+// enqueued on the coarse handle's stream.
 // With `ev` (7 events), the events are recorded before, between and after
 // the six launches, for lbm_hierarchy_profile.
 void hier_coarse_step(lbm_hierarchy *H, bool sens, hipEvent_t *ev = nullptr) {
@@ -292,12 +305,14 @@ void hier_coarse_step(lbm_hierarchy *H, bool sens, hipEvent_t *ev = nullptr) {
     if (sens) h->last_sensor_step = step;
     hier_ghosts(H, B, X, Y, 0.5);
     mark(4);
-    hier_fine_step(H, B, A, sens);
+    const bool fused = restriction_fused();
+    hier_fine_step(H, B, A, sens, fused ? Y : nullptr);
     mark(5);
-    with_hier_types(H, [&]<int Q, typename T, typename C, bool SH>() {
-        launch_patch_restrict<Q, T, C, SH>(patch_args<C>(H, A, A), coarse_view<C>(H, Y, Y, 0.0, Y), A,
-                                           patch_lists(H), h->stream);
-    });
+    if (!fused)
+        with_hier_types(H, [&]<int Q, typename T, typename C, bool SH>() {
+            launch_patch_restrict<Q, T, C, SH>(patch_args<C>(H, A, A), coarse_view<C>(H, Y, Y, 0.0, Y), A,
+                                               patch_lists(H), h->stream);
+        });
     mark(6);
     H->step += 1;
     if (sens) H->last_sensor_step = H->step;
@@ -679,7 +694,8 @@ lbm_status lbm_hierarchy_profile(lbm_hierarchy *H, int32_t steps, double *us) {
     hipEvent_t ev[7] = {};
     hipError_t e = hipSuccess;
     for (int i = 0; i < 7 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
-    // sums over launches: coarse, ghosts (two per step), fine (two), restriction
+    // sums over launches: coarse, ghosts (two per step), first fine step,
+    // second fine step (with the restriction) plus the separate restriction if any
     double sum[4] = {0.0, 0.0, 0.0, 0.0};
     for (int32_t k = 0; k < steps && e == hipSuccess; ++k) {
         hier_coarse_step(H, false, ev);
@@ -687,18 +703,18 @@ lbm_status lbm_hierarchy_profile(lbm_hierarchy *H, int32_t steps, double *us) {
         if (e == hipSuccess) e = hipEventSynchronize(ev[6]);
         float ms[6] = {};
         for (int i = 0; i < 6 && e == hipSuccess; ++i) e = hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]);
-        // launch order: ghosts, fine, coarse, ghosts, fine, restriction
+        // launch order: ghosts, fine, coarse, ghosts, fine (+ restriction), [restriction]
         sum[1] += ms[0] + ms[3];
-        sum[2] += ms[1] + ms[4];
+        sum[2] += ms[1];
         sum[0] += ms[2];
-        sum[3] += ms[5];
+        sum[3] += ms[4] + ms[5];
     }
     for (int i = 0; i < 7; ++i)
         if (ev[i]) (void)hipEventDestroy(ev[i]);
     if (e != hipSuccess) return fail(LBM_EHIP, "profile: %s", hipGetErrorString(e));
     us[0] = 1e3 * sum[0] / steps;
     us[1] = 1e3 * sum[1] / (2.0 * steps);
-    us[2] = 1e3 * sum[2] / (2.0 * steps);
+    us[2] = 1e3 * sum[2] / steps;
     us[3] = 1e3 * sum[3] / steps;
     return LBM_OK;
 }

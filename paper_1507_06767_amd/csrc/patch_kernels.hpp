@@ -159,10 +159,14 @@ __device__ __forceinline__ int64_t padded_index(const PatchRec &p, int x, int y,
 // uses the one 32-bit byte offset c * sizeof(T).  The collision is the step
 // kernel's: moments in population order, the even part of the equilibrium
 // shared by each opposite pair.
-template <int Q, typename T, typename C, bool SH, bool SENSOR, int SKIND>
-__global__ __launch_bounds__(512) void patch_step(const PatchArgs<C> a) {
+template <int Q, typename T, typename C, bool SH, bool SENSOR, int SKIND, bool RESTRICT>
+__global__ __launch_bounds__(512) void patch_step(const PatchArgs<C> a, const CoarseView<C> v) {
     static_assert(Lattice<Q>::D == 3, "3D patches");
     __shared__ C red[8][4];      // [wave][block of the tile]
+    // restriction: per coarse cell of the tile (at most 16 x 4 x 4) and
+    // population, the sum of its 8 fine cells (two partial sums of 4)
+    constexpr int kCoarsePerTile = 256;
+    __shared__ C racc[RESTRICT ? Q * kCoarsePerTile : 1];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const char *src = static_cast<const char *>(a.src);
     char *dst = static_cast<char *>(a.dst);
@@ -185,11 +189,17 @@ __global__ __launch_bounds__(512) void patch_step(const PatchArgs<C> a) {
         const int x = t % W, y = (t / W) & 7, zstep = 64 / W;
         const int sy = p.e[0] + 2, sz = sy * (p.e[1] + 2);
         C m = C(0);
+        if constexpr (RESTRICT) {
+            for (int r = t; r < Q * kCoarsePerTile; r += 512) racc[r] = C(0);
+            __syncthreads();
+        }
 #pragma unroll 1
         for (int zz = t / (8 * W); zz < 8; zz += zstep) {
             // padded cell index (< 2^29, checked on the host) as a byte offset
             const uint32_t cb = (uint32_t)(p.off + (tl.z0 + zz + 1) * sz + (tl.y0 + y + 1) * sy + (tl.x0 + x + 1)) *
                                 (uint32_t)sizeof(T);
+            const int rslot = ((zz >> 1) * 4 + (y >> 1)) * (W >> 1) + (x >> 1);
+            (void)rslot;
             C d[Q];
             static_for<0, Q>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
@@ -221,7 +231,19 @@ __global__ __launch_bounds__(512) void patch_step(const PatchArgs<C> a) {
                 }
                 C out = d[i] - a.omega * fneq;
                 if constexpr (!SH) out += a.shift[i];
-                *reinterpret_cast<T *>(dst + i * plane_bytes + cb) = static_cast<T>(out);
+                const T stored = static_cast<T>(out);
+                *reinterpret_cast<T *>(dst + i * plane_bytes + cb) = stored;
+                if constexpr (RESTRICT) {
+                    // the value the level below reads back, summed over the x pair
+                    // (lanes t, t^1) and the y pair (lanes t, t^W) in a fixed order;
+                    // the two z halves meet in LDS (two additions to a zeroed slot,
+                    // so the result does not depend on their order)
+                    C r = static_cast<C>(stored);
+                    if constexpr (!SH) r -= a.shift[i];
+                    r += static_cast<C>(__shfl_xor(r, 1));
+                    r += static_cast<C>(__shfl_xor(r, W));
+                    if (((x | y) & 1) == 0) atomicAdd(&racc[i * kCoarsePerTile + rslot], r);
+                }
             };
             relax(std::integral_constant<int, 0>{}, drho + (a.rho0 * m15usq + drho * m15usq));
             static_for<0, (Q - 1) / 2>([&](auto kc) {
@@ -234,6 +256,33 @@ __global__ __launch_bounds__(512) void patch_step(const PatchArgs<C> a) {
                 relax(std::integral_constant<int, i + 1>{}, even - C(3) * cj);
             });
             if constexpr (SENSOR) m = nan_max(m, SKIND == kSensorL2 ? num / den : kkn * C(1.0 / Q));
+        }
+        if constexpr (RESTRICT) {
+            // each coarse cell of the tile takes the mean of its 8 fine cells,
+            // rescaled to the coarse level: d_c = deq + (d - deq) / alpha
+            __syncthreads();
+            const int ncoarse = 8 * W;   // (W / 2) x 4 x 4
+            if (t < ncoarse) {
+                const int hx = W >> 1;
+                const int cxl = t % hx, cyl = (t / hx) & 3, czl = t / (4 * hx);
+                const int cx = ((p.o[0] + tl.x0) >> 1) + cxl;
+                const int cy = ((p.o[1] + tl.y0) >> 1) + cyl;
+                const int cz = ((p.o[2] + tl.z0) >> 1) + czl;
+                const int64_t cc = ((int64_t)cz * v.ny + cy) * v.nx + cx;
+                C dr[Q];
+                static_for<0, Q>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    dr[i] = racc[i * kCoarsePerTile + t] * C(0.125);
+                });
+                const Moments<Q, C> mo = moments_of<Q>(dr, a.rho0);
+                const C inv_alpha = C(1) / v.alpha;
+                static_for<0, Q>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    const C deq = deq_of<Q, i>(mo, a.rho0);
+                    store_dev<T>(v.out, i * v.pitch + cc, deq + inv_alpha * (dr[i] - deq), a.shift[i], SH);
+                });
+            }
+            __syncthreads();   // the next tile zeroes racc
         }
         if constexpr (SENSOR) {
             // lane bits 3.. log2(W)-1 number the block of the lane's x: reduce
@@ -492,6 +541,7 @@ struct PatchLaunch {
     hipStream_t stream;
     bool sensor;
     int sensor_kind;
+    bool restrict_to_coarse;   // also restrict to the coarse state (CoarseView::out)
     int nwg;         // workgroups of the persistent launch
 };
 
@@ -509,7 +559,7 @@ struct PatchLists {
 };
 
 template <int Q, typename T, typename C, bool SH>
-void launch_patch_step(const PatchArgs<C> &a, const PatchLaunch &l);
+void launch_patch_step(const PatchArgs<C> &a, const CoarseView<C> &v, const PatchLaunch &l);
 template <int Q, typename T, typename C, bool SH>
 void launch_patch_init(const PatchArgs<C> &a, const CoarseView<C> &v, void *state, int64_t total_padded,
                        hipStream_t st);
@@ -525,11 +575,18 @@ void launch_patch_macros(const PatchArgs<C> &a, const void *state, int patch, in
 
 #ifdef LBM_PATCH_DEFINITIONS
 template <int Q, typename T, typename C, bool SH>
-void launch_patch_step(const PatchArgs<C> &a, const PatchLaunch &l) {
+void launch_patch_step(const PatchArgs<C> &a, const CoarseView<C> &v, const PatchLaunch &l) {
     const dim3 g(l.nwg), b(512);
-    if (!l.sensor) hipLaunchKernelGGL((patch_step<Q, T, C, SH, false, kSensorL2>), g, b, 0, l.stream, a);
-    else if (l.sensor_kind == kSensorL2) hipLaunchKernelGGL((patch_step<Q, T, C, SH, true, kSensorL2>), g, b, 0, l.stream, a);
-    else hipLaunchKernelGGL((patch_step<Q, T, C, SH, true, kSensorKKn>), g, b, 0, l.stream, a);
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, g, b, 0, l.stream, a, v); };
+    if (l.restrict_to_coarse) {
+        if (!l.sensor) go(patch_step<Q, T, C, SH, false, kSensorL2, true>);
+        else if (l.sensor_kind == kSensorL2) go(patch_step<Q, T, C, SH, true, kSensorL2, true>);
+        else go(patch_step<Q, T, C, SH, true, kSensorKKn, true>);
+    } else {
+        if (!l.sensor) go(patch_step<Q, T, C, SH, false, kSensorL2, false>);
+        else if (l.sensor_kind == kSensorL2) go(patch_step<Q, T, C, SH, true, kSensorL2, false>);
+        else go(patch_step<Q, T, C, SH, true, kSensorKKn, false>);
+    }
 }
 
 template <int Q, typename T, typename C, bool SH>
@@ -566,7 +623,8 @@ void launch_patch_macros(const PatchArgs<C> &a, const void *state, int patch, in
 }
 
 #define LBM_INSTANTIATE_PATCH(Q, T, C, SH)                                                                   \
-    template void launch_patch_step<Q, T, C, SH>(const PatchArgs<C> &, const PatchLaunch &);                 \
+    template void launch_patch_step<Q, T, C, SH>(const PatchArgs<C> &, const CoarseView<C> &,                \
+                                                 const PatchLaunch &);                                       \
     template void launch_patch_init<Q, T, C, SH>(const PatchArgs<C> &, const CoarseView<C> &, void *, int64_t, \
                                                  hipStream_t);                                               \
     template void launch_patch_ghosts<Q, T, C, SH>(const PatchArgs<C> &, const CoarseView<C> &, void *,      \

@@ -71,12 +71,14 @@ class Hierarchy:
         return tz, wg, us
 
     def profile(self, steps: int = 4):
-        """Advances `steps` coarse steps launched one by one and returns the
-        mean microseconds per launch of each kernel kind, timed with HIP
-        events in production order: {"coarse", "ghosts", "fine", "restrict"}."""
+        """Advances `steps` coarse steps launched one by one and returns mean
+        microseconds, timed with HIP events in production order: "coarse"
+        (the coarse step), "ghosts" (one ghost fill), "fine" (the first fine
+        step) and "fine_restrict" (the second fine step, which also
+        restricts to the coarse level)."""
         st, us = abi.lbm_hierarchy_profile(self.h, steps)
         _check(st)
-        return dict(zip(("coarse", "ghosts", "fine", "restrict"), us))
+        return dict(zip(("coarse", "ghosts", "fine", "fine_restrict"), us))
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value is not None:

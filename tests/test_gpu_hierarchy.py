@@ -196,7 +196,7 @@ def test_profile_times_kernels_and_steps_like_eager(env):
         if prof:
             us = H.profile(3)
             print("profile us per launch:", {k: round(v, 1) for k, v in us.items()})
-            assert set(us) == {"coarse", "ghosts", "fine", "restrict"}
+            assert set(us) == {"coarse", "ghosts", "fine", "fine_restrict"}
             assert all(v > 0.0 for v in us.values())
         else:
             H.step_n(3, 0)
@@ -211,3 +211,31 @@ def test_profile_times_kernels_and_steps_like_eager(env):
     assert st == lbm.LBM_EINVAL
     H.close()
     blk.close()
+
+
+@pytest.mark.parametrize("storage", [0, 2], ids=["f64", "f32s"])
+def test_fused_restriction_matches_separate_kernel(env, monkeypatch, storage):
+    """The restriction summed inside the second fine step (x and y pairs by
+    lane shuffles, z pairs in LDS) and the separate list-driven kernel
+    (8 fine cells in a row) differ only in the order of the sum: to
+    rounding after 8 coarse steps (1e-14 in float64, 1e-6 in shifted
+    float32, values ~0.01-0.3)."""
+    torch, lbm = env
+    print(f"\n[case] fused vs separate restriction storage={storage}", flush=True)
+    out = {}
+    for mode in ("fused", "separate"):
+        if mode == "separate":
+            monkeypatch.setenv("LBM_HIER_RESTRICT", "separate")
+        else:
+            monkeypatch.delenv("LBM_HIER_RESTRICT", raising=False)
+        blk, H = _make(torch, lbm, 19, storage, use_graph=True)
+        H.step_n(8, 8)
+        out[mode] = (blk.populations(), [H.patch_fields(p)[2] for p in range(len(_BOXES))], H.sensor()[0])
+        H.close()
+        blk.close()
+    tol = 1e-14 if storage == 0 else 1e-6
+    ec = np.abs(out["fused"][0] - out["separate"][0]).max()
+    ef = max(np.abs(a - b).max() for a, b in zip(out["fused"][1], out["separate"][1]))
+    print(f"fused vs separate: coarse {ec:.2e}, fine {ef:.2e}")
+    assert ec < tol and ef < tol
+    assert np.allclose(out["fused"][2], out["separate"][2], rtol=1e-5 if storage else 1e-12, atol=0)
