@@ -72,14 +72,14 @@ def _workload(name, storage):
     raise SystemExit(f"unknown workload {name}")
 
 
-def _traffic_from_profile(kernel_tag):
+def _traffic_from_profile(kernel_tag, source="step_kernel.hpp"):
     """HBM bytes per launch measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE,
     scaled by a copy-kernel calibration), read from the committed summary if it
     was taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel_tag}.txt")
     if not os.path.exists(path):
         return None
-    src = os.path.join(ROOT, "paper_1507_06767_amd", "csrc", "step_kernel.hpp")
+    src = os.path.join(ROOT, "paper_1507_06767_amd", "csrc", source)
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     vals = {}
     for line in open(path):
@@ -223,8 +223,13 @@ def run_refined(args, lbm, torch):
         "fine_refine_blocks": int((ffl == 1).sum()),
         "nonfinite": bool(not np.isfinite(rho).all()),
     }
+    result["roofline"]["traffic"] = _traffic_from_profile(f"refined256_{args.storage}_patch_step", "patch_kernels.hpp")
     H.close()
     blk.close()
+    if not args.no_copy_calibration:
+        cal = copy_calibration()
+        result["copy_calibration"] = cal
+        result["roofline"]["frac_of_copy"] = round(achieved / cal["gbs"], 4)
     return result
 
 
