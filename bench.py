@@ -144,7 +144,7 @@ def cpu_baseline(w, tau, sample_steps):
     t0 = time.perf_counter()
     S, _ = G.run(S, 1, sample_steps, w.sensor_every)
     dt = time.perf_counter() - t0
-    one_steps = max(1, sample_steps // 10)
+    one_steps = max(1, sample_steps // 20)
     prev = oracle.set_threads(1)
     t1 = time.perf_counter()
     S, _ = G.run(S, 1 + sample_steps, one_steps, w.sensor_every)
@@ -334,7 +334,7 @@ def main():
     ap.add_argument("--lattice", type=int, default=19, choices=[19, 27])
     ap.add_argument("--smagorinsky", type=float, default=0.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=20)
+    ap.add_argument("--cpu-sample-steps", type=int, default=100)
     ap.add_argument("--kernel-samples", type=int, default=200,
                     help="single launches timed one by one for the per-kernel durations")
     ap.add_argument("--no-copy-calibration", action="store_true",
