@@ -75,6 +75,21 @@ int32_t lbm_cnn_mse(const float *y, int32_t ystride, const float *target, int64_
 int32_t lbm_cnn_adam(float *w, const float *g, float *m, float *v, int64_t count, float lr, float beta1,
                      float beta2, float eps, int32_t t, void *stream);
 
+/* The same update with its hyperparameters in device memory, so that a
+ * training step can be captured once into a HIP graph and replayed: hyper
+ * holds LBM_CNN_HYPER_FLOATS floats, [0] lr, [1] beta1, [2] beta2, [3] eps,
+ * [4] the step t (a whole number stored as a float; start from 0).
+ * lbm_cnn_adam_begin opens a step: it writes lr, beta1, beta2, eps (taken
+ * by value, so a captured graph replays them unchanged) and adds 1 to t, in
+ * one single-thread kernel; lbm_cnn_adam_dev then updates count parameters,
+ * forming the bias corrections 1 - beta^t on the device.  Both return -1 on
+ * a NULL pointer or a hyperparameter out of range (lr >= 0, 0 <= beta < 1,
+ * eps > 0), -3 if the launch fails; asynchronous on `stream`. */
+#define LBM_CNN_HYPER_FLOATS 8
+int32_t lbm_cnn_adam_begin(float *hyper, float lr, float beta1, float beta2, float eps, void *stream);
+int32_t lbm_cnn_adam_dev(float *w, const float *g, float *m, float *v, int64_t count, const float *hyper,
+                         void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,6 +16,7 @@ from . import abi
 
 LBM_CNN_TAPS = 27
 LBM_CNN_LOSS_FLOATS = 257
+LBM_CNN_HYPER_FLOATS = 8
 
 _lib = abi._lib
 _P = ctypes.c_void_p
@@ -29,6 +30,8 @@ _SIG = {
     "lbm_cnn_relu_backward": ([_P, _P, _I64, _P], _I32),
     "lbm_cnn_mse": ([_P, _I32, _P, _I64, _P, _P, _P], _I32),
     "lbm_cnn_adam": ([_P, _P, _P, _P, _I64, _F, _F, _F, _F, _I32, _P], _I32),
+    "lbm_cnn_adam_begin": ([_P, _F, _F, _F, _F, _P], _I32),
+    "lbm_cnn_adam_dev": ([_P, _P, _P, _P, _I64, _P, _P], _I32),
 }
 for _name, (_args, _res) in _SIG.items():
     _fn = getattr(_lib, _name)
@@ -108,3 +111,15 @@ def lbm_cnn_adam(w, g, m, v, count, lr, beta1, beta2, eps, t, stream=None):
     return _lib.lbm_cnn_adam(*(_ptr(a, torch.float32, count, nm) for a, nm in ((w, "w"), (g, "g"), (m, "m"),
                                                                                (v, "v"))),
                              int(count), float(lr), float(beta1), float(beta2), float(eps), int(t), _stream(stream))
+
+
+def lbm_cnn_adam_begin(hyper, lr, beta1, beta2, eps, stream=None):
+    return _lib.lbm_cnn_adam_begin(_ptr(hyper, torch.float32, LBM_CNN_HYPER_FLOATS, "hyper"), float(lr),
+                                   float(beta1), float(beta2), float(eps), _stream(stream))
+
+
+def lbm_cnn_adam_dev(w, g, m, v, count, hyper, stream=None):
+    return _lib.lbm_cnn_adam_dev(*(_ptr(a, torch.float32, count, nm) for a, nm in ((w, "w"), (g, "g"), (m, "m"),
+                                                                                   (v, "v"))),
+                                 int(count), _ptr(hyper, torch.float32, LBM_CNN_HYPER_FLOATS, "hyper"),
+                                 _stream(stream))

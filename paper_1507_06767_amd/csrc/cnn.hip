@@ -97,17 +97,28 @@ __global__ __launch_bounds__(256) void conv_forward_kernel(const float *x, int n
     const int va = v0 + r;
     const Vox pa = decompose(va < nv ? va : 0, d, h, w);
     f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int kc = 0; kc < k16; kc += 16) {
-        const int k = kc + 4 * kg;
-        const int tap = k / ci4, c = k % ci4;   // 4 consecutive k share the tap
-        float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (va < nv && tap < kTaps) {
-            const int64_t src = tap_voxel(pa, tap, d, h, w);
-            if (src >= 0) a = *reinterpret_cast<const float4 *>(x + src * ci4 + c);
+    // three K steps per pass: their loads (each from a clamped, always valid
+    // index, zeroed by a select) are issued before their MFMAs, which run in
+    // step order
+    constexpr int kPass = 3;
+    const uint16_t *wrow = packed + (int64_t)(co0 + r) * k16;
+    for (int kc0 = 0; kc0 < k16; kc0 += 16 * kPass) {
+        float4 a[kPass];
+        bf16x4 B[kPass];
+#pragma unroll
+        for (int q = 0; q < kPass; ++q) {
+            const int k = kc0 + 16 * q + 4 * kg;
+            const int tap = k / ci4, c = k % ci4;   // 4 consecutive k share the tap
+            const int64_t src = (va < nv && k < k16 && tap < kTaps) ? tap_voxel(pa, tap, d, h, w) : -1;
+            a[q] = *reinterpret_cast<const float4 *>(x + (src >= 0 ? src * ci4 + c : 0));
+            if (src < 0) a[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            B[q] = *reinterpret_cast<const bf16x4 *>(wrow + (k < k16 ? k : 0));
         }
-        const bf16x4 A = to_bf16x4(a.x, a.y, a.z, a.w);
-        const bf16x4 B = *reinterpret_cast<const bf16x4 *>(packed + (int64_t)(co0 + r) * k16 + k);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B, acc, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < kPass; ++q)
+            if (kc0 + 16 * q < k16)
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(to_bf16x4(a[q].x, a[q].y, a[q].z, a[q].w), B[q],
+                                                                acc, 0, 0, 0);
     }
     const int oc = co0 + r;
     if (oc >= co4) return;
@@ -144,24 +155,63 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(const float *x, const f
     float bsum = 0.0f;
     const int vbeg = chunk * kWgradVoxels + wave * (kWgradVoxels / 4);
     const int vend = min(vbeg + kWgradVoxels / 4, nv);
-    for (int v0 = vbeg; v0 < vend; v0 += 16) {
-        float a[4], b[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int v = v0 + 4 * kg + j;
-            a[j] = 0.0f;
-            b[j] = 0.0f;
-            if (v < vend) {
-                if (row_ok) a[j] = gz[(int64_t)v * co4 + ocol];
-                if (col_ok) {
-                    const int64_t src = tap_voxel(decompose(v, d, h, w), tap, d, h, w);
-                    if (src >= 0) b[j] = x[src * ci4 + cch];
-                }
-            }
-        }
+    // The lane's tap offset is fixed; its 4 voxels v0 + 4 kg + j are
+    // consecutive and, when w is a multiple of 4, lie in one row (v0 is a
+    // multiple of 16), so one decomposition per step serves all four.
+    const int tdz = tap / 9 - 1, tdy = (tap / 3) % 3 - 1, tdx = tap % 3 - 1;
+    const int tdelta = (tdz * h + tdy) * w + tdx;
+    const bool rows4 = (w & 3) == 0;
+    auto step = [&](const float (&a)[4], const float (&b)[4]) {
         bsum += ((a[0] + a[1]) + a[2]) + a[3];
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(to_bf16x4(a[0], a[1], a[2], a[3]),
                                                         to_bf16x4(b[0], b[1], b[2], b[3]), acc, 0, 0, 0);
+    };
+    if (rows4) {
+        // four steps per pass: the loads of all four are issued before their
+        // MFMAs (each from a clamped, always valid index, zeroed by a select),
+        // so a wave keeps 32 loads in flight; the sums run in step order
+        constexpr int kPass = 4;
+        for (int v0 = vbeg; v0 < vend; v0 += 16 * kPass) {
+            float a[kPass][4], b[kPass][4];
+#pragma unroll
+            for (int q = 0; q < kPass; ++q) {
+                const int vq = v0 + 16 * q + 4 * kg;
+                const Vox p = decompose(vq < nv ? vq : 0, d, h, w);
+                const bool zy_ok = col_ok && p.z + tdz >= 0 && p.z + tdz < d && p.y + tdy >= 0 && p.y + tdy < h;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int v = vq + j;
+                    const int xx = p.x + j + tdx;
+                    const bool oka = v < vend && row_ok;
+                    const bool okb = v < vend && zy_ok && xx >= 0 && xx < w;
+                    const float av = gz[oka ? (int64_t)v * co4 + ocol : 0];
+                    const float bv = x[okb ? (int64_t)(v + tdelta) * ci4 + cch : 0];
+                    a[q][j] = oka ? av : 0.0f;
+                    b[q][j] = okb ? bv : 0.0f;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kPass; ++q)
+                if (v0 + 16 * q < vend) step(a[q], b[q]);
+        }
+    } else {
+        for (int v0 = vbeg; v0 < vend; v0 += 16) {
+            float a[4], b[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int v = v0 + 4 * kg + j;
+                a[j] = 0.0f;
+                b[j] = 0.0f;
+                if (v < vend) {
+                    if (row_ok) a[j] = gz[(int64_t)v * co4 + ocol];
+                    if (col_ok) {
+                        const int64_t src = tap_voxel(decompose(v, d, h, w), tap, d, h, w);
+                        if (src >= 0) b[j] = x[src * ci4 + cch];
+                    }
+                }
+            }
+            step(a, b);
+        }
     }
     __shared__ float tile[4][16][16];
     __shared__ float bias[4][4][16];   // [wave][lane group][channel]
@@ -249,6 +299,31 @@ __global__ void adam_kernel(float *w, const float *g, float *m, float *v, int64_
     w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// The device-resident form: hyper = {lr, beta1, beta2, eps, t}; the bias
+// corrections 1 - beta^t are formed on the device.
+__global__ void adam_dev_kernel(float *w, const float *g, float *m, float *v, int64_t count, const float *hyper) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float lr = hyper[0], b1 = hyper[1], b2 = hyper[2], eps = hyper[3], t = hyper[4];
+    const float c1 = 1.0f - powf(b1, t), c2 = 1.0f - powf(b2, t);
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Opens an optimizer step: hyper[0..3] = (lr, beta1, beta2, eps), hyper[4] += 1.
+__global__ void adam_begin_kernel(float *hyper, float lr, float b1, float b2, float eps) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    hyper[0] = lr;
+    hyper[1] = b1;
+    hyper[2] = b2;
+    hyper[3] = eps;
+    hyper[4] = hyper[4] + 1.0f;
+}
+
 int32_t launched() { return hipGetLastError() == hipSuccess ? 0 : -3; }
 
 unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -333,6 +408,23 @@ int32_t lbm_cnn_adam(float *w, const float *g, float *m, float *v, int64_t count
     const float c1 = 1.0f - powf(beta1, (float)t), c2 = 1.0f - powf(beta2, (float)t);
     hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(count, 256)), dim3(256), 0, (hipStream_t)stream, w, g, m, v,
                        count, lr, beta1, beta2, eps, c1, c2);
+    return launched();
+}
+
+int32_t lbm_cnn_adam_begin(float *hyper, float lr, float beta1, float beta2, float eps, void *stream) {
+    if (!hyper || !(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+        !(eps > 0.0f))
+        return -1;
+    hipLaunchKernelGGL(adam_begin_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, hyper, lr, beta1, beta2, eps);
+    return launched();
+}
+
+int32_t lbm_cnn_adam_dev(float *w, const float *g, float *m, float *v, int64_t count, const float *hyper,
+                         void *stream) {
+    if (!w || !g || !m || !v || !hyper || count < 0) return -1;
+    if (count == 0) return 0;
+    hipLaunchKernelGGL(adam_dev_kernel, dim3(blocks_for(count, 256)), dim3(256), 0, (hipStream_t)stream, w, g, m, v,
+                       count, hyper);
     return launched();
 }
 

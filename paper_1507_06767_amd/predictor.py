@@ -92,6 +92,8 @@ class FlagPredictor:
         self.layers = [_Layer(channels[k], channels[k + 1], k + 2 < len(channels), rng, self.device)
                        for k in range(len(channels) - 1)]
         self.t = 0
+        # optimizer hyperparameters and step in device memory (lbm_cnn_adam_begin)
+        self.hyper = torch.zeros(cnn.LBM_CNN_HYPER_FLOATS, dtype=torch.float32, device=self.device)
         self.normalizer = None
         self._bufs = {}
         self._pack()
@@ -156,27 +158,63 @@ class FlagPredictor:
                                                   self.stream), "dgrad")
                 g = gin
 
-    def loss_and_grads(self, x, target):
-        """Loss (float) and gradients (in each layer's gw, gb) on a batch.
-        x (n, d, h, w, C0) normalized inputs, target (n, d, h, w)."""
+    def load_batch(self, x, target):
+        """Copies a batch to the device: x (n, d, h, w, C0) normalized inputs,
+        target (n, d, h, w).  Returns its shape."""
         shape = tuple(target.shape)
         B = self.load_input(x, shape)
         B["target"].copy_(torch.from_numpy(np.ascontiguousarray(target, dtype=np.float32).reshape(-1)))
+        return shape
+
+    def loss_and_grads_device(self, shape):
+        """Loss and gradients (in each layer's gw, gb) on the loaded batch;
+        returns the device loss tensor (element 0)."""
+        B = self._buffers(shape)
         y = self.forward_device(shape)
         nv = int(np.prod(shape))
         _check(cnn.lbm_cnn_mse(y, cnn.pad4(self.channels[-1]), B["target"], nv, B["grads"][-1], B["loss"],
                                self.stream), "mse")
         self.backward_device(shape)
-        return B["loss"][0]
+        return B["loss"]
+
+    def loss_and_grads(self, x, target):
+        """Loss (float) and gradients (in each layer's gw, gb) on a batch.
+        x (n, d, h, w, C0) normalized inputs, target (n, d, h, w)."""
+        return self.loss_and_grads_device(self.load_batch(x, target))[0]
 
     def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        """One Adam step of every parameter; the hyperparameters and the step
+        count go through device memory (so the step can be graph-captured)."""
         self.t += 1
+        _check(cnn.lbm_cnn_adam_begin(self.hyper, lr, beta1, beta2, eps, self.stream), "adam begin")
         for L in self.layers:
-            _check(cnn.lbm_cnn_adam(L.w, L.gw, L.mw, L.vw, L.w.numel(), lr, beta1, beta2, eps, self.t,
-                                    self.stream), "adam")
-            _check(cnn.lbm_cnn_adam(L.b, L.gb, L.mb, L.vb, L.b.numel(), lr, beta1, beta2, eps, self.t,
-                                    self.stream), "adam")
+            _check(cnn.lbm_cnn_adam_dev(L.w, L.gw, L.mw, L.vw, L.w.numel(), self.hyper, self.stream), "adam")
+            _check(cnn.lbm_cnn_adam_dev(L.b, L.gb, L.mb, L.vb, L.b.numel(), self.hyper, self.stream), "adam")
         self._pack()
+
+    def train_step(self, shape, lr):
+        """One training iteration (forward, loss, backward, Adam) on the
+        loaded batch, without host transfers."""
+        self.loss_and_grads_device(shape)
+        self.adam_step(lr)
+
+    def capture_train_step(self, shape, lr):
+        """A HIP graph of one training iteration on the loaded batch at a
+        fixed learning rate; each replay advances the device step count.
+        Count replays with `replayed(n)` to keep the host step count."""
+        self._buffers(shape)
+        g = torch.cuda.CUDAGraph()
+        saved, t0 = self.stream, self.t
+        self.stream = None       # launch on the capture stream
+        try:
+            with torch.cuda.graph(g):
+                self.train_step(shape, lr)
+        finally:
+            self.stream, self.t = saved, t0
+        return g
+
+    def replayed(self, n):
+        self.t += n
 
     def predict_raw(self, x):
         """Network output channel 0 for normalized inputs x (n, d, h, w, C0)."""

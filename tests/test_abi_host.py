@@ -59,6 +59,13 @@ def test_cnn_sizes_and_argument_checks(lbm):
     lib.lbm_cnn_adam.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int64] + [ctypes.c_float] * 4 + \
         [ctypes.c_int32, ctypes.c_void_p]
     assert lib.lbm_cnn_adam(16, 16, 16, 16, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == -1   # t < 1
+    lib.lbm_cnn_adam_begin.argtypes = [ctypes.c_void_p] + [ctypes.c_float] * 4 + [ctypes.c_void_p]
+    assert lib.lbm_cnn_adam_begin(None, 1e-3, 0.9, 0.999, 1e-8, None) == -1
+    assert lib.lbm_cnn_adam_begin(16, 1e-3, 1.0, 0.999, 1e-8, None) == -1                # beta1 = 1
+    assert lib.lbm_cnn_adam_begin(16, 1e-3, 0.9, 0.999, 0.0, None) == -1                 # eps = 0
+    lib.lbm_cnn_adam_dev.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.lbm_cnn_adam_dev(16, 16, 16, 16, 10, None, None) == -1                    # no hyper
+    assert lib.lbm_cnn_adam_dev(16, 16, 16, 16, -1, 16, None) == -1
 
 
 def test_library_exports_every_declared_symbol(lbm):

@@ -171,6 +171,21 @@ def test_relu_backward_mse_adam(env):
     err = np.abs(wd.cpu().numpy() - w).max()
     print(f"adam: max err after 5 steps {err:.2e}")
     assert err < 1e-6
+    # the device-resident form (hyperparameters and step in device memory)
+    hyper = torch.zeros(cnn.LBM_CNN_HYPER_FLOATS, dtype=torch.float32, device="cuda")
+    wd, md, vd = _dev(torch, w0), torch.zeros(777, device="cuda"), torch.zeros(777, device="cuda")
+    w, m, v = w0.copy(), np.zeros(777), np.zeros(777)
+    rng2 = np.random.default_rng(5)
+    for step in range(1, 6):
+        gr = rng2.standard_normal(777).astype(np.float32)
+        assert cnn.lbm_cnn_adam_begin(hyper, 1e-2, 0.9, 0.999, 1e-8) == 0
+        assert cnn.lbm_cnn_adam_dev(wd, _dev(torch, gr), md, vd, 777, hyper) == 0
+        w, m, v = ocnn.adam(w, gr.astype(np.float64), m, v, step, 1e-2)
+    torch.cuda.synchronize()
+    assert hyper[4].item() == 5.0
+    err = np.abs(wd.cpu().numpy() - w).max()
+    print(f"adam (device hyperparameters): max err after 5 steps {err:.2e}")
+    assert err < 1e-6
 
 
 def test_network_gradients_against_oracle(env):
