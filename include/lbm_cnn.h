@@ -90,6 +90,17 @@ int32_t lbm_cnn_adam_begin(float *hyper, float lr, float beta1, float beta2, flo
 int32_t lbm_cnn_adam_dev(float *w, const float *g, float *m, float *v, int64_t count, const float *hyper,
                          void *stream);
 
+/* lbm_cnn_adam_dev over one convolution layer in a single launch: weights
+ * w [co][27][ci] with gradient gw and moments mw, vw, and bias b [co] with
+ * gb, mb, vb; each updated weight is also written to packed and packed_flip
+ * in the layouts lbm_cnn_pack_weights gives with flip 0 and 1 (their
+ * padding entries, written by an earlier lbm_cnn_pack_weights, are left
+ * alone).  Sizes as for lbm_cnn_pack_weights; -1 on a NULL pointer or
+ * co, ci < 1, -3 if the launch fails. */
+int32_t lbm_cnn_adam_layer(float *w, float *b, const float *gw, const float *gb, float *mw, float *vw, float *mb,
+                           float *vb, int32_t co, int32_t ci, uint16_t *packed, uint16_t *packed_flip,
+                           const float *hyper, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,6 +32,7 @@ _SIG = {
     "lbm_cnn_adam": ([_P, _P, _P, _P, _I64, _F, _F, _F, _F, _I32, _P], _I32),
     "lbm_cnn_adam_begin": ([_P, _F, _F, _F, _F, _P], _I32),
     "lbm_cnn_adam_dev": ([_P, _P, _P, _P, _I64, _P, _P], _I32),
+    "lbm_cnn_adam_layer": ([_P] * 8 + [_I32, _I32, _P, _P, _P, _P], _I32),
 }
 for _name, (_args, _res) in _SIG.items():
     _fn = getattr(_lib, _name)
@@ -123,3 +124,14 @@ def lbm_cnn_adam_dev(w, g, m, v, count, hyper, stream=None):
                                                                                    (v, "v"))),
                                  int(count), _ptr(hyper, torch.float32, LBM_CNN_HYPER_FLOATS, "hyper"),
                                  _stream(stream))
+
+
+def lbm_cnn_adam_layer(w, b, gw, gb, mw, vw, mb, vb, co, ci, packed, packed_flip, hyper, stream=None):
+    nw, nb = co * LBM_CNN_TAPS * ci, co
+    args = [_ptr(w, torch.float32, nw, "w"), _ptr(b, torch.float32, nb, "b"), _ptr(gw, torch.float32, nw, "gw"),
+            _ptr(gb, torch.float32, nb, "gb"), _ptr(mw, torch.float32, nw, "mw"), _ptr(vw, torch.float32, nw, "vw"),
+            _ptr(mb, torch.float32, nb, "mb"), _ptr(vb, torch.float32, nb, "vb")]
+    return _lib.lbm_cnn_adam_layer(*args, int(co), int(ci),
+                                   _ptr(packed, torch.int16, lbm_cnn_packed_size(co, ci), "packed", 8),
+                                   _ptr(packed_flip, torch.int16, lbm_cnn_packed_size(ci, co), "packed_flip", 8),
+                                   _ptr(hyper, torch.float32, LBM_CNN_HYPER_FLOATS, "hyper"), _stream(stream))

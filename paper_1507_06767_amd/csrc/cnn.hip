@@ -231,25 +231,28 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(const float *x, const f
     }
 }
 
-// gw[co][tap][ci] = sum over chunks (in order) of the partials.
-__global__ void wgrad_fold_kernel(const float *work, int nchunk, int ci, int co, float *gw) {
+// The folds, in one launch: gw[co][tap][ci] and (with gb) gb[co] are the
+// sums over chunks, in chunk order, of the partials; threads below
+// co * 27 * ci fold the weight gradient, the next co threads the bias.
+__global__ void grad_fold_kernel(const float *work, int nchunk, int ci, int co, float *gw, float *gb) {
     const int ci4 = pad4(ci), k16 = pad16(kTaps * ci4), co16 = pad16(co);
+    const int nw = co * kTaps * ci;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= co * kTaps * ci) return;
-    const int c = idx % ci, tap = (idx / ci) % kTaps, o = idx / (ci * kTaps);
-    const int k = tap * ci4 + c;
-    float s = 0.0f;
-    for (int ch = 0; ch < nchunk; ++ch) s += work[((int64_t)ch * co16 + o) * k16 + k];
-    gw[idx] = s;
-}
-
-// gb[co] = sum over chunks (in order) of the per-chunk channel sums.
-__global__ void bias_fold_kernel(const float *part, int nchunk, int co, int co16, float *gb) {
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= co) return;
-    float s = 0.0f;
-    for (int ch = 0; ch < nchunk; ++ch) s += part[(int64_t)ch * co16 + o];
-    gb[o] = s;
+    if (idx < nw) {
+        const int c = idx % ci, tap = (idx / ci) % kTaps, o = idx / (ci * kTaps);
+        const int k = tap * ci4 + c;
+        float s = 0.0f;
+#pragma unroll 8
+        for (int ch = 0; ch < nchunk; ++ch) s += work[((int64_t)ch * co16 + o) * k16 + k];
+        gw[idx] = s;
+    } else if (gb && idx < nw + co) {
+        const int o = idx - nw;
+        const float *part = work + (int64_t)nchunk * co16 * k16;
+        float s = 0.0f;
+#pragma unroll 8
+        for (int ch = 0; ch < nchunk; ++ch) s += part[(int64_t)ch * co16 + o];
+        gb[o] = s;
+    }
 }
 
 __global__ void relu_backward_kernel(const float *a, float *g, int64_t count) {
@@ -314,6 +317,41 @@ __global__ void adam_dev_kernel(float *w, const float *g, float *m, float *v, in
     w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+__device__ inline uint16_t to_bf16_bits(float v) { return __builtin_bit_cast(uint16_t, static_cast<__bf16>(v)); }
+
+// Adam (device hyperparameters) over a layer's weights [co][27][ci] and bias
+// [co] in one launch, the arithmetic of adam_dev_kernel; each updated weight
+// is also written to both packed forms (the layouts of pack_kernel with flip
+// 0 and 1), whose padding entries stay as they are.
+__global__ void adam_layer_kernel(float *w, float *b, const float *gw, const float *gb, float *mw, float *vw,
+                                  float *mb, float *vb, int co, int ci, uint16_t *packed, uint16_t *packed_flip,
+                                  const float *hyper) {
+    const int nw = co * kTaps * ci;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nw + co) return;
+    const float lr = hyper[0], b1 = hyper[1], b2 = hyper[2], eps = hyper[3], t = hyper[4];
+    const float c1 = 1.0f - powf(b1, t), c2 = 1.0f - powf(b2, t);
+    const bool is_w = idx < nw;
+    const int i = is_w ? idx : idx - nw;
+    float *p = is_w ? w : b;
+    float *m = is_w ? mw : mb;
+    float *v = is_w ? vw : vb;
+    const float gi = is_w ? gw[i] : gb[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pn = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pn;
+    if (is_w) {
+        const int c = i % ci, tap = (i / ci) % kTaps, o = i / (ci * kTaps);
+        const int ci4 = pad4(ci), co4 = pad4(co);
+        const int k16 = pad16(kTaps * ci4), k16f = pad16(kTaps * co4);
+        packed[(int64_t)o * k16 + tap * ci4 + c] = to_bf16_bits(pn);
+        packed_flip[(int64_t)c * k16f + (kTaps - 1 - tap) * co4 + o] = to_bf16_bits(pn);
+    }
+}
+
 // Opens an optimizer step: hyper[0..3] = (lr, beta1, beta2, eps), hyper[4] += 1.
 __global__ void adam_begin_kernel(float *hyper, float lr, float b1, float b2, float eps) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -376,11 +414,8 @@ int32_t lbm_cnn_conv3d_wgrad(const float *x, const float *gz, int32_t n, int32_t
     hipStream_t st = (hipStream_t)stream;
     const dim3 grid(nchunk, pad16(kTaps * pad4(ci)) / 16, pad16(co) / 16);
     hipLaunchKernelGGL(conv_wgrad_kernel, grid, dim3(256), 0, st, x, gz, n, d, h, wd, ci, co, work);
-    hipLaunchKernelGGL(wgrad_fold_kernel, dim3(blocks_for((int64_t)co * kTaps * ci, 256)), dim3(256), 0, st,
-                       work, nchunk, ci, co, gw);
-    if (gb)
-        hipLaunchKernelGGL(bias_fold_kernel, dim3(blocks_for(co, 64)), dim3(64), 0, st,
-                           work + (int64_t)nchunk * pad16(co) * pad16(kTaps * pad4(ci)), nchunk, co, pad16(co), gb);
+    hipLaunchKernelGGL(grad_fold_kernel, dim3(blocks_for((int64_t)co * kTaps * ci + co, 256)), dim3(256), 0, st,
+                       work, nchunk, ci, co, gw, gb);
     return launched();
 }
 
@@ -416,6 +451,18 @@ int32_t lbm_cnn_adam_begin(float *hyper, float lr, float beta1, float beta2, flo
         !(eps > 0.0f))
         return -1;
     hipLaunchKernelGGL(adam_begin_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, hyper, lr, beta1, beta2, eps);
+    return launched();
+}
+
+int32_t lbm_cnn_adam_layer(float *w, float *b, const float *gw, const float *gb, float *mw, float *vw, float *mb,
+                           float *vb, int32_t co, int32_t ci, uint16_t *packed, uint16_t *packed_flip,
+                           const float *hyper, void *stream) {
+    if (!w || !b || !gw || !gb || !mw || !vw || !mb || !vb || !packed || !packed_flip || !hyper || co < 1 || ci < 1)
+        return -1;
+    if ((int64_t)co * kTaps * ci + co >= (int64_t(1) << 31)) return -1;
+    const int64_t n = (int64_t)co * kTaps * ci + co;
+    hipLaunchKernelGGL(adam_layer_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, w, b, gw, gb,
+                       mw, vw, mb, vb, co, ci, packed, packed_flip, hyper);
     return launched();
 }
 

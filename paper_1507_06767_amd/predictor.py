@@ -187,10 +187,9 @@ class FlagPredictor:
         count go through device memory (so the step can be graph-captured)."""
         self.t += 1
         _check(cnn.lbm_cnn_adam_begin(self.hyper, lr, beta1, beta2, eps, self.stream), "adam begin")
-        for L in self.layers:
-            _check(cnn.lbm_cnn_adam_dev(L.w, L.gw, L.mw, L.vw, L.w.numel(), self.hyper, self.stream), "adam")
-            _check(cnn.lbm_cnn_adam_dev(L.b, L.gb, L.mb, L.vb, L.b.numel(), self.hyper, self.stream), "adam")
-        self._pack()
+        for L in self.layers:   # weights, bias and both packed forms in one launch per layer
+            _check(cnn.lbm_cnn_adam_layer(L.w, L.b, L.gw, L.gb, L.mw, L.vw, L.mb, L.vb, L.co, L.ci, L.packed,
+                                          L.packed_flip, self.hyper, self.stream), "adam")
 
     def train_step(self, shape, lr):
         """One training iteration (forward, loss, backward, Adam) on the

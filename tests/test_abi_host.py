@@ -66,6 +66,11 @@ def test_cnn_sizes_and_argument_checks(lbm):
     lib.lbm_cnn_adam_dev.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
     assert lib.lbm_cnn_adam_dev(16, 16, 16, 16, 10, None, None) == -1                    # no hyper
     assert lib.lbm_cnn_adam_dev(16, 16, 16, 16, -1, 16, None) == -1
+    lib.lbm_cnn_adam_layer.argtypes = [ctypes.c_void_p] * 8 + [ctypes.c_int32] * 2 + [ctypes.c_void_p] * 4
+    ok = [16] * 8
+    assert lib.lbm_cnn_adam_layer(*ok, 16, 6, 16, 16, None, None) == -1                 # no hyper
+    assert lib.lbm_cnn_adam_layer(*ok, 0, 6, 16, 16, 16, None) == -1                    # co < 1
+    assert lib.lbm_cnn_adam_layer(*([None] + ok[1:]), 16, 6, 16, 16, 16, None) == -1    # no w
 
 
 def test_library_exports_every_declared_symbol(lbm):

@@ -186,6 +186,32 @@ def test_relu_backward_mse_adam(env):
     err = np.abs(wd.cpu().numpy() - w).max()
     print(f"adam (device hyperparameters): max err after 5 steps {err:.2e}")
     assert err < 1e-6
+    # one launch per layer (weights, bias, both packed forms) against
+    # lbm_cnn_adam_dev twice and lbm_cnn_pack_weights twice: identical bits
+    co, ci = 16, 6
+    nw = co * 27 * ci
+    lay = {k: _dev(torch, rng2.standard_normal(n)) for k, n in
+           (("w", nw), ("b", co), ("gw", nw), ("gb", co), ("mw", nw), ("vw", nw), ("mb", co), ("vb", co))}
+    lay["vw"].abs_()
+    lay["vb"].abs_()
+    ref = {k: v.clone() for k, v in lay.items()}
+    pk = [torch.zeros(cnn.lbm_cnn_packed_size(co, ci), dtype=torch.int16, device="cuda") for _ in range(2)]
+    pkf = [torch.zeros(cnn.lbm_cnn_packed_size(ci, co), dtype=torch.int16, device="cuda") for _ in range(2)]
+    for j in range(2):
+        assert cnn.lbm_cnn_pack_weights(lay["w"], co, ci, 0, pk[j]) == 0      # padding written once
+        assert cnn.lbm_cnn_pack_weights(lay["w"], co, ci, 1, pkf[j]) == 0
+    for _ in range(3):
+        assert cnn.lbm_cnn_adam_begin(hyper, 3e-3, 0.9, 0.999, 1e-8) == 0
+        assert cnn.lbm_cnn_adam_layer(lay["w"], lay["b"], lay["gw"], lay["gb"], lay["mw"], lay["vw"], lay["mb"],
+                                      lay["vb"], co, ci, pk[0], pkf[0], hyper) == 0
+        assert cnn.lbm_cnn_adam_dev(ref["w"], ref["gw"], ref["mw"], ref["vw"], nw, hyper) == 0
+        assert cnn.lbm_cnn_adam_dev(ref["b"], ref["gb"], ref["mb"], ref["vb"], co, hyper) == 0
+        assert cnn.lbm_cnn_pack_weights(ref["w"], co, ci, 0, pk[1]) == 0
+        assert cnn.lbm_cnn_pack_weights(ref["w"], co, ci, 1, pkf[1]) == 0
+    torch.cuda.synchronize()
+    for k in lay:
+        assert torch.equal(lay[k], ref[k]), k
+    assert torch.equal(pk[0], pk[1]) and torch.equal(pkf[0], pkf[1])
 
 
 def test_network_gradients_against_oracle(env):
