@@ -126,6 +126,47 @@ def test_small_grids(lbm, orc, case, kind, storage, scheme):
     blk.close()
 
 
+_DEGENERATE = [
+    # name, q, n, bc, wall_u: a cell that is its own periodic neighbour, or
+    # lies against both walls of an axis (so a link can cross two faces of
+    # one axis pair), and blocks cut to a single cell
+    ("q19_1x1x1_periodic", 19, (1, 1, 1), (PERIODIC,) * 6, _wall()),
+    ("q19_1x2x3_walls", 19, (1, 2, 3), (WALL,) * 6, _wall(0.05)),
+    ("q19_2x1x1_mixed", 19, (2, 1, 1), (WALL, WALL, PERIODIC, PERIODIC, WALL, WALL), _wall(0.04, 5, 1)),
+    ("q27_1x1x2_walls", 27, (1, 1, 2), (WALL,) * 6, _wall(0.05)),
+    ("q9_1x1_periodic", 9, (1, 1, 1), (PERIODIC, PERIODIC, PERIODIC, PERIODIC, PERIODIC, PERIODIC), _wall()),
+    ("q9_2x1_walls", 9, (2, 1, 1), (WALL, WALL, WALL, WALL, PERIODIC, PERIODIC), _wall(0.1)),
+]
+
+
+@pytest.mark.parametrize("scheme", ["pingpong", "inplace"])
+@pytest.mark.parametrize("case", _DEGENERATE, ids=[c[0] for c in _DEGENERATE])
+def test_degenerate_extents(lbm, orc, case, scheme):
+    """Grids of one or two cells along an axis against the oracle after each
+    of 7 steps with the sensor every step: ping-pong in float64 (populations
+    to 1e-14), in place in shifted float32 (1e-6; values ~0.03-0.4), block
+    maxima and flags as in the other parity tests."""
+    name, q, n, bc, wall_u = case
+    storage = 0 if scheme == "pingpong" else 2
+    print(f"\n[case] degenerate {name} {scheme}", flush=True)
+    desc, G = _pair(lbm, orc, q, n, bc, wall_u, 0.7, storage, 0, (0, 0, 0))
+    desc.streaming = lbm.LBM_STREAMING_PINGPONG if scheme == "pingpong" else lbm.LBM_STREAMING_INPLACE
+    S = G.equilibrium_state()
+    blk = lbm.Blocks(desc)
+    assert blk.scheme()["inplace"] == (scheme == "inplace")
+    for k in range(1, 8):
+        blk.step_n(1, 1)
+        S, hist = G.run(S, k - 1, 1, 1)
+        bm, fl, kk, _ = blk.sensor_flags()
+        assert kk == k
+        _compare_bmax(bm, hist[-1][1], storage)
+        _compare_flags(fl, hist[-1][2], hist[-1][1], storage)
+        err = np.abs(blk.populations() - S).max()
+        assert err < (1e-14 if storage == 0 else 1e-6), f"step {k}: {err:.2e}"
+    blk.close()
+
+
+
 def test_config0_cavity2d_full(lbm, orc):
     """64x64 D2Q9 FP64 cavity, Re = 100, lid 0.1, 2000 steps, sensor every 100:
     all 20 flag sets and block maxima, and the final fields."""
