@@ -54,7 +54,7 @@ int64_t lbm_cnn_wgrad_workspace(int32_t n, int32_t d, int32_t h, int32_t wd, int
  *   gw[co][tap][ci] = sum_{n, v} gz[n][v][co] x[n][v + tap - 13][ci],
  *   gb[co] = sum_{n, v} gz[n][v][co]  (gb may be NULL; summed in float32
  *   from the unrounded gz).
- * Deterministic: per-workgroup partial sums (chunks of 1024 voxels) in
+ * Deterministic: per-workgroup partial sums (chunks of 512 voxels) in
  * `work`, folded in a fixed order. */
 int32_t lbm_cnn_conv3d_wgrad(const float *x, const float *gz, int32_t n, int32_t d, int32_t h, int32_t wd,
                              int32_t ci, int32_t co, float *work, float *gw, float *gb, void *stream);

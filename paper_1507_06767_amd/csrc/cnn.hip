@@ -28,7 +28,7 @@ typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTaps = 27;
-constexpr int kWgradVoxels = 1024;   // voxels per weight-gradient workgroup
+constexpr int kWgradVoxels = 512;    // voxels per weight-gradient workgroup
 constexpr int kLossBlocks = 256;     // workgroups of the loss kernel (partial sums in loss[1..])
 
 __host__ __device__ inline int pad4(int c) { return (c + 3) / 4 * 4; }

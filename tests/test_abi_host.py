@@ -47,9 +47,9 @@ def test_cnn_sizes_and_argument_checks(lbm):
     assert lib.lbm_cnn_packed_size(16, 5) == 16 * 224
     assert lib.lbm_cnn_packed_size(1, 16) == 16 * 432
     assert lib.lbm_cnn_packed_size(0, 4) == -1
-    # chunks of 1024 voxels x Co16 x (K16 + 1) floats (the extra column: bias sums)
-    assert lib.lbm_cnn_wgrad_workspace(2, 16, 16, 16, 16, 16) == 8 * 16 * 433 * 4
-    assert lib.lbm_cnn_wgrad_workspace(1, 16, 16, 17, 16, 1) == 5 * 16 * 433 * 4
+    # chunks of 512 voxels x Co16 x (K16 + 1) floats (the extra column: bias sums)
+    assert lib.lbm_cnn_wgrad_workspace(2, 16, 16, 16, 16, 16) == 16 * 16 * 433 * 4
+    assert lib.lbm_cnn_wgrad_workspace(1, 16, 16, 17, 16, 1) == 9 * 16 * 433 * 4
     f = lib.lbm_cnn_conv3d_forward
     f.argtypes = [ctypes.c_void_p] + [ctypes.c_int32] * 5 + [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                                              ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
