@@ -489,3 +489,31 @@ def test_graph_replay_matches_launches(lbm, case, scheme):
         blk.close()
     for a, b in zip(out[0], out[1]):
         assert np.array_equal(a, b)
+
+
+_OVERRIDES = [("LBM_TILE_X", "32"), ("LBM_TILE_X", "64"), ("LBM_TILE_X", "128"),
+              ("LBM_PLANE_PAD", "0"), ("LBM_PLANE_PAD", "4096")]
+
+
+@pytest.mark.parametrize("override", _OVERRIDES, ids=[f"{k}={v}" for k, v in _OVERRIDES])
+def test_tuning_overrides_keep_bits(lbm, scheme, monkeypatch, override):
+    """The tile width and plane padding change only how cells map to
+    workgroups and where planes start: populations, block maxima and flags
+    are the same bits as with the defaults (ragged x extent, both schemes)."""
+    import torch
+    key, val = override
+    print(f"\n[case] override {key}={val} {scheme}", flush=True)
+    out = []
+    for setting in (None, val):
+        if setting is None:
+            monkeypatch.delenv(key, raising=False)
+        else:
+            monkeypatch.setenv(key, setting)
+        desc = lbm.make_desc(19, (70, 24, 20), (WALL,) * 6, 0.6, storage=2, wall_u=_wall(0.08))
+        blk = lbm.Blocks(desc, stream=torch.cuda.Stream())
+        blk.step_n(11, 5)
+        bm, fl = blk.sensor_flags()[:2]
+        out.append((blk.populations(), bm, fl))
+        blk.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
