@@ -331,7 +331,7 @@ lbm_status hier_capture(lbm_hierarchy *H, int parity) {
     H->step = s2;
     H->last_sensor_step = s3;
     hipError_t e = hipGraphInstantiate(&H->graph[parity], g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
         H->graph[parity] = nullptr;
         return fail(LBM_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
@@ -667,8 +667,8 @@ lbm_status lbm_hierarchy_autotune(lbm_hierarchy *H, int32_t reps, int32_t *tile_
         }
         if (e != hipSuccess) break;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     build_tiles(H, best_w);
     if (e == hipSuccess) e = upload_tiles(H);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -676,7 +676,7 @@ lbm_status lbm_hierarchy_autotune(lbm_hierarchy *H, int32_t reps, int32_t *tile_
     // graphs captured with the old tile list are stale
     for (int p = 0; p < 2; ++p)
         if (H->graph[p]) {
-            hipGraphExecDestroy(H->graph[p]);
+            (void)hipGraphExecDestroy(H->graph[p]);
             H->graph[p] = nullptr;
         }
     if (e != hipSuccess) return fail(LBM_EHIP, "autotune: %s", hipGetErrorString(e));
@@ -722,7 +722,7 @@ lbm_status lbm_hierarchy_profile(lbm_hierarchy *H, int32_t steps, double *us) {
 void lbm_destroy_hierarchy(lbm_hierarchy *H) {
     if (!H) return;
     for (int p = 0; p < 2; ++p)
-        if (H->graph[p]) hipGraphExecDestroy(H->graph[p]);
+        if (H->graph[p]) (void)hipGraphExecDestroy(H->graph[p]);
     delete H;
 }
 

@@ -884,8 +884,8 @@ lbm_status lbm_autotune(lbm_blocks *h, int32_t reps, int32_t *tile_x) {
             best_tile = tx;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (h->inplace) std::swap(h->d.buf[LBM_BUF_F_A], h->d.buf[LBM_BUF_F_B]);
     h->phase = saved_phase;
     h->tile_x = (e == hipSuccess) ? best_tile : saved_tile;

@@ -188,6 +188,12 @@ __global__ __launch_bounds__(512) void patch_step(const PatchArgs<C> a, const Co
         const int W = tl.w;
         const int x = t % W, y = (t / W) & 7, zstep = 64 / W;
         const int sy = p.e[0] + 2, sz = sy * (p.e[1] + 2);
+        // the first and last cell of a row also write their value into the
+        // row's ghost slot beside them (refilled before it is read): every
+        // padded row is then written whole, and the memory system sees whole
+        // lines instead of lines with a 4-byte hole at each row end
+        const bool xedge = (tl.x0 + x == 0) || (tl.x0 + x == p.e[0] - 1);
+        const int xoff = (tl.x0 + x == 0) ? -(int)sizeof(T) : (int)sizeof(T);
         C m = C(0);
         if constexpr (RESTRICT) {
             for (int r = t; r < Q * kCoarsePerTile; r += 512) racc[r] = C(0);
@@ -233,6 +239,7 @@ __global__ __launch_bounds__(512) void patch_step(const PatchArgs<C> a, const Co
                 if constexpr (!SH) out += a.shift[i];
                 const T stored = static_cast<T>(out);
                 *reinterpret_cast<T *>(dst + i * plane_bytes + cb) = stored;
+                if (xedge) *reinterpret_cast<T *>(dst + i * plane_bytes + cb + xoff) = stored;
                 if constexpr (RESTRICT) {
                     // the value the level below reads back, summed over the x pair
                     // (lanes t, t^1) and the y pair (lanes t, t^W) in a fixed order;
