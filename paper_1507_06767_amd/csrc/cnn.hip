@@ -97,10 +97,10 @@ __global__ __launch_bounds__(256) void conv_forward_kernel(const float *x, int n
     const int va = v0 + r;
     const Vox pa = decompose(va < nv ? va : 0, d, h, w);
     f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    // three K steps per pass: their loads (each from a clamped, always valid
-    // index, zeroed by a select) are issued before their MFMAs, which run in
-    // step order
-    constexpr int kPass = 3;
+    // nine K steps per pass (27 taps of 16 channels in three passes): their
+    // loads (each from a clamped, always valid index, zeroed by a select) are
+    // issued before their MFMAs, which run in step order
+    constexpr int kPass = 9;
     const uint16_t *wrow = packed + (int64_t)(co0 + r) * k16;
     for (int kc0 = 0; kc0 < k16; kc0 += 16 * kPass) {
         float4 a[kPass];
