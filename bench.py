@@ -320,7 +320,7 @@ def run_predictor(args, lbm, torch):
     conv_graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(conv_graph):
         for _ in range(reps):
-            assert cnn.lbm_cnn_conv3d_forward(B["acts"][0], *shape, L.ci, L.packed, L.co, L.b, 1,
+            assert cnn.lbm_cnn_conv3d_forward(B["acts"][0], *shape, L.ci, L.packed, L.co, L.b, 1, None,
                                               B["acts"][1]) == 0
     conv_graph.replay()
     torch.cuda.synchronize()

@@ -40,14 +40,20 @@ int32_t lbm_cnn_pack_weights(const float *w, int32_t co, int32_t ci, int32_t fli
                              void *stream);
 
 /* y[n][v][co] = act(sum_{tap, ci} w[co][tap][ci] x[n][v + tap - 13][ci] + bias[co]),
- * act = relu if relu != 0, identity otherwise; bias may be NULL.  Writes all
- * Co4 channels of y (padding channels get 0 + bias 0).  packed comes from
+ * act = relu if relu != 0, identity otherwise; bias may be NULL.  mask (NULL:
+ * none, else laid out like y) then zeroes every output whose mask value is
+ * not > 0: the data-gradient convolution followed by the ReLU backward of
+ * the layer below (mask = that layer's activation), the same bits as
+ * lbm_cnn_relu_backward on the unmasked output.  Writes all Co4 channels of
+ * y (padding channels get 0 + bias 0).  packed comes from
  * lbm_cnn_pack_weights(co, ci). */
 int32_t lbm_cnn_conv3d_forward(const float *x, int32_t n, int32_t d, int32_t h, int32_t wd, int32_t ci,
                                const uint16_t *packed, int32_t co, const float *bias, int32_t relu,
-                               float *y, void *stream);
+                               const float *mask, float *y, void *stream);
 
-/* Bytes of the float32 workspace lbm_cnn_conv3d_wgrad needs. */
+/* Bytes of the float32 workspace lbm_cnn_conv3d_wgrad needs (the partial
+ * sums; its contents between calls do not matter).  Calls that overlap in
+ * time must not share a workspace. */
 int64_t lbm_cnn_wgrad_workspace(int32_t n, int32_t d, int32_t h, int32_t wd, int32_t ci, int32_t co);
 
 /* Weight and bias gradients of the convolution:

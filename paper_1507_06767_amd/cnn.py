@@ -24,7 +24,7 @@ _I32, _I64, _F = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
 _SIG = {
     "lbm_cnn_packed_size": ([_I32, _I32], _I64),
     "lbm_cnn_pack_weights": ([_P, _I32, _I32, _I32, _P, _P], _I32),
-    "lbm_cnn_conv3d_forward": ([_P, _I32, _I32, _I32, _I32, _I32, _P, _I32, _P, _I32, _P, _P], _I32),
+    "lbm_cnn_conv3d_forward": ([_P, _I32, _I32, _I32, _I32, _I32, _P, _I32, _P, _I32, _P, _P, _P], _I32),
     "lbm_cnn_wgrad_workspace": ([_I32, _I32, _I32, _I32, _I32, _I32], _I64),
     "lbm_cnn_conv3d_wgrad": ([_P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P], _I32),
     "lbm_cnn_relu_backward": ([_P, _P, _I64, _P], _I32),
@@ -72,12 +72,13 @@ def lbm_cnn_pack_weights(w, co, ci, flip, packed, stream=None):
                                      _stream(stream))
 
 
-def lbm_cnn_conv3d_forward(x, n, d, h, wd, ci, packed, co, bias, relu, y, stream=None):
+def lbm_cnn_conv3d_forward(x, n, d, h, wd, ci, packed, co, bias, relu, mask, y, stream=None):
     nv = n * d * h * wd
     return _lib.lbm_cnn_conv3d_forward(
         _ptr(x, torch.float32, nv * pad4(ci), "x", 16), n, d, h, wd, ci,
         _ptr(packed, torch.int16, lbm_cnn_packed_size(co, ci), "packed", 8), co,
         _ptr(bias, torch.float32, co, "bias"), int(bool(relu)),
+        _ptr(mask, torch.float32, nv * pad4(co), "mask"),
         _ptr(y, torch.float32, nv * pad4(co), "y", 16), _stream(stream))
 
 

@@ -86,7 +86,7 @@ __global__ void pack_kernel(const float *w, int co, int ci, int flip, uint16_t *
 // barriers, so a wave past the last voxel simply returns.
 __global__ __launch_bounds__(256) void conv_forward_kernel(const float *x, int n, int d, int h, int w, int ci,
                                                            const uint16_t *packed, int co, const float *bias,
-                                                           int relu, float *y) {
+                                                           int relu, const float *mask, float *y) {
     const int ci4 = pad4(ci), co4 = pad4(co), k16 = pad16(kTaps * ci4);
     const int nv = n * d * h * w;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -129,6 +129,7 @@ __global__ __launch_bounds__(256) void conv_forward_kernel(const float *x, int n
         if (v >= nv) continue;
         float o = acc[j] + b;
         if (relu) o = o > 0.0f ? o : 0.0f;
+        if (mask) o = mask[(int64_t)v * co4 + oc] > 0.0f ? o : 0.0f;
         y[(int64_t)v * co4 + oc] = o;
     }
 }
@@ -387,14 +388,14 @@ int32_t lbm_cnn_pack_weights(const float *w, int32_t co, int32_t ci, int32_t fli
 
 int32_t lbm_cnn_conv3d_forward(const float *x, int32_t n, int32_t d, int32_t h, int32_t wd, int32_t ci,
                                const uint16_t *packed, int32_t co, const float *bias, int32_t relu,
-                               float *y, void *stream) {
+                               const float *mask, float *y, void *stream) {
     if (!x || !packed || !y || n < 1 || d < 1 || h < 1 || wd < 1 || ci < 1 || co < 1) return -1;
     if (((uintptr_t)x) % 16 || ((uintptr_t)packed) % 8) return -1;
     const int64_t nv = (int64_t)n * d * h * wd;
     if (nv >= (int64_t(1) << 31)) return -1;
     const dim3 grid(blocks_for(nv, 64), pad16(co) / 16);
     hipLaunchKernelGGL(conv_forward_kernel, grid, dim3(256), 0, (hipStream_t)stream, x, n, d, h, wd, ci, packed,
-                       co, bias, relu, y);
+                       co, bias, relu, mask, y);
     return launched();
 }
 

@@ -134,7 +134,7 @@ class FlagPredictor:
         n, d, h, w = shape
         a = B["x"]
         for L, out in zip(self.layers, B["acts"]):
-            _check(cnn.lbm_cnn_conv3d_forward(a, n, d, h, w, L.ci, L.packed, L.co, L.b, L.relu, out,
+            _check(cnn.lbm_cnn_conv3d_forward(a, n, d, h, w, L.ci, L.packed, L.co, L.b, L.relu, None, out,
                                               self.stream), "conv forward")
             a = out
         return a
@@ -145,16 +145,19 @@ class FlagPredictor:
         n, d, h, w = shape
         nv = n * d * h * w
         g = B["grads"][-1]
+        L = self.layers[-1]
+        if L.relu:   # the output layer's own ReLU (the layers below fuse theirs into the data gradient)
+            _check(cnn.lbm_cnn_relu_backward(B["acts"][-1], g, nv * cnn.pad4(L.co), self.stream), "relu bwd")
         for k in range(len(self.layers) - 1, -1, -1):
             L = self.layers[k]
-            if L.relu:
-                _check(cnn.lbm_cnn_relu_backward(B["acts"][k], g, nv * cnn.pad4(L.co), self.stream), "relu bwd")
             inp = B["x"] if k == 0 else B["acts"][k - 1]
             _check(cnn.lbm_cnn_conv3d_wgrad(inp, g, n, d, h, w, L.ci, L.co, B["work"], L.gw, L.gb, self.stream),
                    "wgrad")
             if k > 0:
+                # gradient at the input of layer k, through the ReLU of layer k - 1
                 gin = B["grads"][k]
-                _check(cnn.lbm_cnn_conv3d_forward(g, n, d, h, w, L.co, L.packed_flip, L.ci, None, 0, gin,
+                mask = B["acts"][k - 1] if self.layers[k - 1].relu else None
+                _check(cnn.lbm_cnn_conv3d_forward(g, n, d, h, w, L.co, L.packed_flip, L.ci, None, 0, mask, gin,
                                                   self.stream), "dgrad")
                 g = gin
 

@@ -52,10 +52,11 @@ def test_cnn_sizes_and_argument_checks(lbm):
     assert lib.lbm_cnn_wgrad_workspace(1, 16, 16, 17, 16, 1) == 9 * 16 * 433 * 4
     f = lib.lbm_cnn_conv3d_forward
     f.argtypes = [ctypes.c_void_p] + [ctypes.c_int32] * 5 + [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
-                                                             ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
-    assert f(None, 1, 2, 2, 2, 4, None, 4, None, 0, None, None) == -1
-    assert f(16, 0, 2, 2, 2, 4, 16, 4, None, 0, 16, None) == -1
-    assert f(20, 1, 2, 2, 2, 4, 16, 4, None, 0, 16, None) == -1       # x not 16-byte aligned
+                                                             ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                                             ctypes.c_void_p]
+    assert f(None, 1, 2, 2, 2, 4, None, 4, None, 0, None, None, None) == -1
+    assert f(16, 0, 2, 2, 2, 4, 16, 4, None, 0, None, 16, None) == -1
+    assert f(20, 1, 2, 2, 2, 4, 16, 4, None, 0, None, 16, None) == -1       # x not 16-byte aligned
     lib.lbm_cnn_adam.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int64] + [ctypes.c_float] * 4 + \
         [ctypes.c_int32, ctypes.c_void_p]
     assert lib.lbm_cnn_adam(16, 16, 16, 16, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == -1   # t < 1

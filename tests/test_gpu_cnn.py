@@ -51,7 +51,7 @@ def _forward(torch, cnn, x, w, b, relu, flip=False):
     xd = _dev(torch, _padded(x, cnn.pad4(cin)))
     y = torch.full((n * d * h * wd * cnn.pad4(cout),), float("nan"), dtype=torch.float32, device="cuda")
     bd = _dev(torch, b) if b is not None else None
-    assert cnn.lbm_cnn_conv3d_forward(xd, n, d, h, wd, cin, packed, cout, bd, relu, y) == 0
+    assert cnn.lbm_cnn_conv3d_forward(xd, n, d, h, wd, cin, packed, cout, bd, relu, None, y) == 0
     torch.cuda.synchronize()
     return y.cpu().numpy().astype(np.float64).reshape(n, d, h, wd, cnn.pad4(cout))
 
@@ -101,7 +101,38 @@ def test_conv_data_gradient(env, case):
     assert (gx[..., ci:] == 0).all()
 
 
-_WSHAPES = [((2, 5, 6, 7), 5, 16), ((1, 16, 16, 17), 16, 16), ((2, 8, 8, 8), 16, 1)]
+def test_conv_mask_is_relu_backward(env):
+    """A masked data-gradient convolution gives the same bits as the
+    unmasked one followed by lbm_cnn_relu_backward with the same mask (an
+    activation with zeros, negatives and a NaN)."""
+    torch, cnn = env
+    n, d, h, wd = 2, 5, 6, 7
+    co, ci = 16, 16                      # the convolution maps co -> ci channels
+    print(f"\n[case] masked dgrad {(n, d, h, wd)} {co}->{ci}", flush=True)
+    rng = np.random.default_rng(21)
+    gz = rng.standard_normal((n, d, h, wd, co)).astype(np.float32)
+    w = (rng.standard_normal((co, 27, ci)) * 0.2).astype(np.float32)
+    nv = n * d * h * wd
+    act = np.maximum(rng.standard_normal(nv * cnn.pad4(ci)), 0.0).astype(np.float32)
+    act[::7] = -1.0
+    act[3] = np.nan
+    packed = _pack(torch, cnn, w, co, ci, True)
+    gd = _dev(torch, _padded(gz, cnn.pad4(co)))
+    mask = _dev(torch, act)
+    outs = []
+    for m in (None, mask):
+        y = torch.full((nv * cnn.pad4(ci),), float("nan"), dtype=torch.float32, device="cuda")
+        assert cnn.lbm_cnn_conv3d_forward(gd, n, d, h, wd, co, packed, ci, None, 0, m, y) == 0
+        outs.append(y)
+    assert cnn.lbm_cnn_relu_backward(mask, outs[0], nv * cnn.pad4(ci)) == 0
+    torch.cuda.synchronize()
+    a, b = outs[0].cpu().numpy(), outs[1].cpu().numpy()
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    assert (b[~(act > 0)] == 0).all()
+
+
+# the last case: a wide layer (216 x 8 output tiles of 16 x 16)
+_WSHAPES = [((2, 5, 6, 7), 5, 16), ((1, 16, 16, 17), 16, 16), ((2, 8, 8, 8), 16, 1), ((1, 3, 4, 5), 128, 128)]
 
 
 @pytest.mark.parametrize("case", _WSHAPES, ids=[f"{c[0]}_{c[1]}to{c[2]}" for c in _WSHAPES])
@@ -135,6 +166,37 @@ def test_conv_weight_gradient(env, case):
     print(f"wgrad: max err {ew.max():.2e} (err/bound {(ew / bound_w).max():.3f}); "
           f"bias grad max err {eb.max():.2e} (err/bound {(eb / bound_b).max():.3f})")
     assert (ew <= bound_w).all() and (eb <= bound_b).all()
+
+
+def test_weight_gradient_workspace_shared(env):
+    """One workspace through calls of different shapes (as the layers of a
+    network use it): every call gives the same bits as with a fresh
+    workspace."""
+    torch, cnn = env
+    cases = [((1, 16, 16, 17), 16, 16), ((2, 5, 6, 7), 5, 16), ((2, 8, 8, 8), 16, 1), ((1, 16, 16, 17), 16, 16)]
+    print("\n[case] wgrad shared workspace", flush=True)
+    rng = np.random.default_rng(31)
+    data = []
+    for shape, ci, co in cases[:3]:
+        x = rng.standard_normal(shape + (ci,)).astype(np.float32)
+        gz = rng.standard_normal(shape + (co,)).astype(np.float32)
+        data.append((shape, ci, co, _dev(torch, _padded(x, cnn.pad4(ci))), _dev(torch, _padded(gz, cnn.pad4(co)))))
+    data.append(data[0])
+
+    def run(item, work):
+        shape, ci, co, xd, gd = item
+        gw = torch.full((co * 27 * ci,), float("nan"), dtype=torch.float32, device="cuda")
+        gb = torch.full((co,), float("nan"), dtype=torch.float32, device="cuda")
+        assert cnn.lbm_cnn_conv3d_wgrad(xd, gd, *shape, ci, co, work, gw, gb) == 0
+        return gw, gb
+
+    size = max(cnn.lbm_cnn_wgrad_workspace(*s, ci, co) for s, ci, co in cases) // 4
+    shared = torch.zeros(size, dtype=torch.float32, device="cuda")
+    got = [run(item, shared) for item in data]
+    fresh = [run(item, torch.zeros(size, dtype=torch.float32, device="cuda")) for item in data]
+    torch.cuda.synchronize()
+    for (a, b), (c, e) in zip(got, fresh):
+        assert torch.equal(a, c) and torch.equal(b, e)
 
 
 def test_relu_backward_mse_adam(env):
