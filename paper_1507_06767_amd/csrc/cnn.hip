@@ -233,27 +233,43 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(const float *x, const f
 }
 
 // The folds, in one launch: gw[co][tap][ci] and (with gb) gb[co] are the
-// sums over chunks, in chunk order, of the partials; threads below
-// co * 27 * ci fold the weight gradient, the next co threads the bias.
-__global__ void grad_fold_kernel(const float *work, int nchunk, int ci, int co, float *gw, float *gb) {
+// sums over chunks of the partials.  A workgroup folds 64 outputs (indices
+// below co * 27 * ci: weights, the next co: biases) with its 8 waves: wave
+// s sums chunks s, s + 8, s + 16, ... in that order, and the 8 sums are
+// added pairwise, ((0+1)+(2+3))+((4+5)+(6+7)): a fixed order, so the result
+// is deterministic, with 8 loads per lane in flight instead of a chain of
+// nchunk.
+constexpr int kFoldWaves = 8;
+__global__ __launch_bounds__(64 * kFoldWaves) void grad_fold_kernel(const float *work, int nchunk, int ci, int co,
+                                                                    float *gw, float *gb) {
     const int ci4 = pad4(ci), k16 = pad16(kTaps * ci4), co16 = pad16(co);
     const int nw = co * kTaps * ci;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx < nw) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int idx = blockIdx.x * 64 + lane;
+    const bool is_w = idx < nw, is_b = !is_w && gb && idx < nw + co;
+    // partial of chunk ch for this output: base + ch * stride
+    int64_t base = 0, stride = 0;
+    if (is_w) {
         const int c = idx % ci, tap = (idx / ci) % kTaps, o = idx / (ci * kTaps);
-        const int k = tap * ci4 + c;
-        float s = 0.0f;
-#pragma unroll 8
-        for (int ch = 0; ch < nchunk; ++ch) s += work[((int64_t)ch * co16 + o) * k16 + k];
-        gw[idx] = s;
-    } else if (gb && idx < nw + co) {
-        const int o = idx - nw;
-        const float *part = work + (int64_t)nchunk * co16 * k16;
-        float s = 0.0f;
-#pragma unroll 8
-        for (int ch = 0; ch < nchunk; ++ch) s += part[(int64_t)ch * co16 + o];
-        gb[o] = s;
+        base = (int64_t)o * k16 + tap * ci4 + c;
+        stride = (int64_t)co16 * k16;
+    } else if (is_b) {
+        base = (int64_t)nchunk * co16 * k16 + (idx - nw);
+        stride = co16;
     }
+    float s = 0.0f;
+    if (is_w || is_b) {
+#pragma unroll 8
+        for (int ch = wave; ch < nchunk; ch += kFoldWaves) s += work[base + ch * stride];
+    }
+    __shared__ float part[kFoldWaves][64];
+    part[wave][lane] = s;
+    __syncthreads();
+    if (wave != 0 || !(is_w || is_b)) return;
+    const float t = ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) +
+                    ((part[4][lane] + part[5][lane]) + (part[6][lane] + part[7][lane]));
+    if (is_w) gw[idx] = t;
+    else gb[idx - nw] = t;
 }
 
 __global__ void relu_backward_kernel(const float *a, float *g, int64_t count) {
@@ -283,12 +299,18 @@ __global__ __launch_bounds__(256) void mse_kernel(const float *y, int ys, const 
     if (threadIdx.x == 0) loss[1 + blockIdx.x] = sh[0];
 }
 
-// loss[0] = (sum of the partials, in order) / count.
-__global__ void mse_fold_kernel(float *loss, int nblocks, int64_t count) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    float s = 0.0f;
-    for (int b = 0; b < nblocks; ++b) s += loss[1 + b];
-    loss[0] = s / (float)count;
+// loss[0] = (sum of the nblocks <= 256 partials) / count, the partials
+// added by a fixed pairwise tree (the same order on every call).
+__global__ __launch_bounds__(kLossBlocks) void mse_fold_kernel(float *loss, int nblocks, int64_t count) {
+    __shared__ float sh[kLossBlocks];
+    const int t = threadIdx.x;
+    sh[t] = t < nblocks ? loss[1 + t] : 0.0f;
+    __syncthreads();
+    for (int k = kLossBlocks / 2; k > 0; k >>= 1) {
+        if (t < k) sh[t] += sh[t + k];
+        __syncthreads();
+    }
+    if (t == 0) loss[0] = sh[0] / (float)count;
 }
 
 __global__ void adam_kernel(float *w, const float *g, float *m, float *v, int64_t count, float lr, float b1,
@@ -415,8 +437,8 @@ int32_t lbm_cnn_conv3d_wgrad(const float *x, const float *gz, int32_t n, int32_t
     hipStream_t st = (hipStream_t)stream;
     const dim3 grid(nchunk, pad16(kTaps * pad4(ci)) / 16, pad16(co) / 16);
     hipLaunchKernelGGL(conv_wgrad_kernel, grid, dim3(256), 0, st, x, gz, n, d, h, wd, ci, co, work);
-    hipLaunchKernelGGL(grad_fold_kernel, dim3(blocks_for((int64_t)co * kTaps * ci + co, 256)), dim3(256), 0, st,
-                       work, nchunk, ci, co, gw, gb);
+    hipLaunchKernelGGL(grad_fold_kernel, dim3(blocks_for((int64_t)co * kTaps * ci + co, 64)), dim3(64 * kFoldWaves),
+                       0, st, work, nchunk, ci, co, gw, gb);
     return launched();
 }
 
@@ -433,7 +455,7 @@ int32_t lbm_cnn_mse(const float *y, int32_t ystride, const float *target, int64_
     if (!y || !target || !g || !loss || ystride < 1 || count < 1) return -1;
     const int nb = (int)std::min<int64_t>(kLossBlocks, (count + 255) / 256);
     hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, (hipStream_t)stream, y, ystride, target, count, g, loss);
-    hipLaunchKernelGGL(mse_fold_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, loss, nb, count);
+    hipLaunchKernelGGL(mse_fold_kernel, dim3(1), dim3(kLossBlocks), 0, (hipStream_t)stream, loss, nb, count);
     return launched();
 }
 
