@@ -27,14 +27,16 @@ f^neq scaled by tau_f / (2 tau_c), hence alpha for post-collision values.)
 Pins (tests/test_oracle_hier.py): a uniform flow stays uniform through the
 interface; a plane Couette flow across a patch converges to the exact linear
 profile on both levels (a wrong alpha breaks the stress balance at the
-interface and fails it); the single-level reduction (no patch effect outside
-the stencil) is covered by comparing with the plain coarse oracle.
+interface and fails it); the fine sensor of both kinds takes its closed form
+on a uniform state with a known non-equilibrium part; the single-level
+reduction (no patch effect outside the stencil) is covered by comparing with
+the plain coarse oracle.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from . import ABI_VELOCITIES, Grid, abi_permutation, lattice_tables
+from . import ABI_VELOCITIES, SENSOR_KKN, Grid, abi_permutation, lattice_tables
 
 
 def _weights(q):
@@ -129,8 +131,10 @@ class Hierarchy:
     # -- fine step ----------------------------------------------------------------
     def fine_step(self, sensor=False):
         """Pull streaming from the padded neighbours and BGK collision with
-        tau_f; returns per patch the cell sensor ||f^neq|| / ||f^eq|| of the
-        pre-collision populations if sensor."""
+        tau_f; returns per patch the cell sensor of the pre-collision
+        populations if sensor, of the coarse grid's kind (Sec. 3.2):
+        ||f^neq|| / ||f^eq|| (Eq. sensor), or (1/q) sum_i |f^neq_i / f^eq_i|
+        (Eq. kkn)."""
         sens = []
         for p, F in enumerate(self.F):
             ex, ey, ez = self.e[p]
@@ -143,7 +147,10 @@ class Hierarchy:
             eq = self.feq(rho, u)
             neq = flat - eq
             if sensor:
-                s = np.sqrt((neq * neq).sum(axis=0)) / np.sqrt((eq * eq).sum(axis=0))
+                if self.G.sensor_kind == SENSOR_KKN:
+                    s = np.abs(neq / eq).sum(axis=0) / self.q
+                else:
+                    s = np.sqrt((neq * neq).sum(axis=0)) / np.sqrt((eq * eq).sum(axis=0))
                 sens.append(s.reshape(ez, ey, ex))
             G = F.copy()
             G[:, 1:-1, 1:-1, 1:-1] = (flat - neq / self.tau_f).reshape(self.q, ez, ey, ex)

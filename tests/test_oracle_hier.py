@@ -32,6 +32,38 @@ def test_uniform_flow_crosses_the_interface(orc, q):
     assert max(b.max() for b in bm) < 1e-13
 
 
+@pytest.mark.parametrize("kind", [0, 1], ids=["l2", "kkn"])
+def test_fine_sensor_closed_form(orc, kind):
+    """A uniform coarse state f^eq(rho, u) + delta, delta orthogonal to the
+    mass and momentum sums: every fine cell, ghosts included, starts at
+    f^eq + alpha delta (interpolation keeps it, the rescaling scales the
+    non-equilibrium part by alpha), streaming leaves it, and the fine sensor
+    takes the closed form of Sec. 3.2 on it: ||alpha delta|| / ||f^eq||
+    (Eq. sensor) or (1/q) sum_i |alpha delta_i| / f^eq_i (Eq. kkn)."""
+    from oracle.hier import Hierarchy
+    G = orc.Grid(q=19, n=(12, 12, 12), bc=(PERIODIC,) * 6, tau=0.7, sensor_kind=kind)
+    rho, u = 1.02, np.array([0.04, -0.01, 0.02])
+    S = _uniform_state(G, rho, u)
+    feq = S[:, 0, 0, 0].copy()
+    c = np.asarray(orc.ABI_VELOCITIES[19], dtype=float)
+    M = np.vstack([np.ones(19), c.T])                        # the mass and momentum sums
+    r = np.random.default_rng(9).standard_normal(19) * 1e-3 * feq
+    delta = r - M.T @ np.linalg.solve(M @ M.T, M @ r)        # orthogonal to them
+    assert np.abs(M @ delta).max() < 1e-17
+    S = S + delta[:, None, None, None]
+    H = Hierarchy(G, [((3, 3, 3), (7, 7, 7)), ((7, 3, 3), (11, 7, 7))])
+    H.init_from(S)
+    H.fill_ghosts(S, S, 0.0)
+    sens = H.fine_step(sensor=True)
+    ad = H.alpha * delta
+    want = (np.sqrt((ad * ad).sum()) / np.sqrt((feq * feq).sum()) if kind == 0
+            else np.abs(ad / feq).sum() / 19)
+    assert want > 1e-4
+    for s in sens:
+        assert s.shape == (8, 8, 8)
+        assert np.abs(s / want - 1).max() < 1e-10
+
+
 def _couette(orc, alpha=None, steps=1500):
     """Plane Couette flow between y walls (the +y wall moves at U in x),
     periodic in x and z, one patch across the middle of the gap, from the
