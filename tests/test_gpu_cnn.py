@@ -276,8 +276,10 @@ def test_relu_backward_mse_adam(env):
     assert torch.equal(pk[0], pk[1]) and torch.equal(pkf[0], pkf[1])
 
 
-def test_network_gradients_against_oracle(env):
-    """A 5 -> 16 -> 16 -> 16 -> 1 network on two 16^3 block grids: loss and
+@pytest.mark.parametrize("case", [(5, 2), (6, 8)], ids=["5ch_2x16^3", "6ch_8x16^3"])
+def test_network_gradients_against_oracle(env, case):
+    """A C -> 16 -> 16 -> 16 -> 1 network on B 16^3 block grids (the second
+    case is the trained network's shape and the benchmark's batch): loss and
     every weight and bias gradient from the GPU against the oracle's
     backpropagation with bfloat16-rounded product inputs (and, for scale,
     against the oracle in plain float64).
@@ -292,11 +294,12 @@ def test_network_gradients_against_oracle(env):
     (cosine > 0.99)."""
     torch, cnn = env
     from paper_1507_06767_amd.predictor import FlagPredictor
-    print("\n[case] network gradients 2x16^3", flush=True)
-    net = FlagPredictor(channels=(5, 16, 16, 16, 1), seed=3)
+    cin, batch = case
+    print(f"\n[case] network gradients {cin} channels, {batch}x16^3", flush=True)
+    net = FlagPredictor(channels=(cin, 16, 16, 16, 1), seed=3)
     rng = np.random.default_rng(9)
-    shape = (2, 16, 16, 16)
-    x = rng.standard_normal(shape + (5,)).astype(np.float32)
+    shape = (batch, 16, 16, 16)
+    x = rng.standard_normal(shape + (cin,)).astype(np.float32)
     t = rng.standard_normal(shape).astype(np.float32)
     loss = net.loss_and_grads(x, t).item()
     params = [(L.w.cpu().numpy().astype(np.float64), L.b.cpu().numpy().astype(np.float64)) for L in net.layers]
