@@ -571,9 +571,21 @@ __device__ __forceinline__ void write_block(const StepArgs<C> &a, int b, C M) {
 // the workgroup's 8 rows of block column tx.
 template <int BX, typename C>
 __device__ __forceinline__ C tile_block_max(C m) {
-    m = nan_max(m, static_cast<C>(__shfl_xor(m, 1)));
-    m = nan_max(m, static_cast<C>(__shfl_xor(m, 2)));
-    m = nan_max(m, static_cast<C>(__shfl_xor(m, 4)));
+    if constexpr (sizeof(C) == 4) {
+        // Sensor values are >= 0, +inf or NaN, so the unsigned order of their
+        // bits is a NaN-propagating max order: the max over each group of 8
+        // lanes takes three DPP moves (swap neighbours, swap pairs, mirror
+        // the half row) and unsigned maxima, with every lane active.
+        unsigned u = __float_as_uint(static_cast<float>(m));
+        u = max(u, static_cast<unsigned>(__builtin_amdgcn_mov_dpp(static_cast<int>(u), 0xB1, 0xF, 0xF, false)));
+        u = max(u, static_cast<unsigned>(__builtin_amdgcn_mov_dpp(static_cast<int>(u), 0x4E, 0xF, 0xF, false)));
+        u = max(u, static_cast<unsigned>(__builtin_amdgcn_mov_dpp(static_cast<int>(u), 0x141, 0xF, 0xF, false)));
+        m = static_cast<C>(__uint_as_float(u));
+    } else {
+        m = nan_max(m, static_cast<C>(__shfl_xor(m, 1)));
+        m = nan_max(m, static_cast<C>(__shfl_xor(m, 2)));
+        m = nan_max(m, static_cast<C>(__shfl_xor(m, 4)));
+    }
     __shared__ C red[kTileY][BX / kBlockEdge];
     if ((threadIdx.x & (kBlockEdge - 1)) == 0) red[threadIdx.y][threadIdx.x / kBlockEdge] = m;
     __syncthreads();
