@@ -255,22 +255,25 @@ def test_generic_state_single_step(lbm, orc, q, scheme):
         blk.close()
 
 
-def test_nonfinite_population_is_flagged(lbm, orc, scheme):
+@pytest.mark.parametrize("x", [20, 23, 24, 31])
+def test_nonfinite_population_is_flagged(lbm, orc, scheme, x):
     """A NaN written through set_populations gives flag 2 in its block and
-    LBM_ENONFINITE, while the other blocks keep their flags."""
+    LBM_ENONFINITE, while the other blocks keep their flags; cells at both
+    edges of a block's 8 x-lanes (x = 23 | 24, 31) stay in their block."""
     n = (32, 16, 16)
     desc, G = _pair(lbm, orc, 19, n, (PERIODIC,) * 6, _wall(), 0.8, lbm.LBM_F32)
     blk = lbm.Blocks(desc)
     f = G.equilibrium_state()
-    f[3, 5, 9, 20] = np.nan                      # cell x=20,y=9,z=5 -> block (2,1,0)
+    f[3, 5, 9, x] = np.nan                       # cell (x, 9, 5) -> block (x // 8, 1, 0)
     blk.set_populations(f)
     blk.step_n(1, 1)
     bm, fl, k, nonfinite = blk.sensor_flags()
     assert nonfinite and k == 1
-    assert fl[0, 1, 2] == 2 and np.isnan(bm[0, 1, 2])
-    # the NaN streamed to the neighbour of direction 3 (+y): still block (2,1,0)
+    bx = x // 8
+    assert fl[0, 1, bx] == 2 and np.isnan(bm[0, 1, bx])
+    # the NaN streamed to the neighbour of direction 3 (+y): still the same block
     others = np.ones(fl.shape, bool)
-    others[0, 1, 2] = False
+    others[0, 1, bx] = False
     assert (fl[others] == -1).all()
     blk.close()
 
