@@ -135,16 +135,19 @@ def copy_calibration(nbytes=1 << 30, reps=20):
     return {"bytes_per_copy": nbytes, "gbs": round(2 * nbytes / sec / 1e9, 1), "us": round(sec * 1e6, 2)}
 
 
-def cpu_baseline(w, tau, sample_steps):
+def cpu_baseline(w, tau, sample_steps, smagorinsky=0.0):
     """The FP64 oracle on the same workload, all host threads, a short run;
-    also one thread on a shorter run."""
+    also one thread on a shorter run.  Returns the JSON entry and the oracle's
+    last sensor result of the timed run, (step, block maxima, flags), or None
+    when that run has no sensor step."""
     import oracle
-    G = oracle.Grid(q=w.q, n=w.n, bc=w.bc, wall_u=w.wall_u, tau=tau, force=w.force)
+    G = oracle.Grid(q=w.q, n=w.n, bc=w.bc, wall_u=w.wall_u, tau=tau, force=w.force,
+                    theta_refine=w.theta_refine, theta_coarsen=w.theta_coarsen, smagorinsky=smagorinsky)
     S = G.equilibrium_state()
     S, _ = G.run(S, 0, 1, 1)                   # first touch of the work arrays
     threads = oracle.threads()
     t0 = time.perf_counter()
-    S, _ = G.run(S, 1, sample_steps, w.sensor_every)
+    S, hist = G.run(S, 1, sample_steps, w.sensor_every)
     dt = time.perf_counter() - t0
     one_steps = max(1, sample_steps // 20)
     prev = oracle.set_threads(1)
@@ -152,12 +155,35 @@ def cpu_baseline(w, tau, sample_steps):
     S, _ = G.run(S, 1 + sample_steps, one_steps, w.sensor_every)
     dt1 = time.perf_counter() - t1
     oracle.set_threads(prev)
-    return {"value": round(w.cells * sample_steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{sample_steps} steps of the same {w.n[0]}x{w.n[1]}x{w.n[2]} workload in FP64, "
-                      f"sensor every step, {dt:.1f} s",
-            "one_core": {"value": round(w.cells * one_steps / dt1 / 1e6, 3), "unit": "MLUPS",
-                         "sample": f"{one_steps} steps, {dt1:.1f} s"}}
+    entry = {"value": round(w.cells * sample_steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
+             "kind": "oracle",
+             "sample": f"{sample_steps} steps of the same {w.n[0]}x{w.n[1]}x{w.n[2]} workload in FP64, "
+                       f"sensor every step, {dt:.1f} s",
+             "one_core": {"value": round(w.cells * one_steps / dt1 / 1e6, 3), "unit": "MLUPS",
+                          "sample": f"{one_steps} steps, {dt1:.1f} s"}}
+    return entry, (hist[-1] if hist else None)
+
+
+def flag_agreement(lbm, torch, desc, every, ref, theta, eps=2e-4):
+    """The GPU path from rest to the oracle's sensor step `ref[0]` on the same
+    workload: its refine/keep/coarsen flags against the FP64 oracle's, block
+    by block.  Blocks whose oracle maximum lies within `eps` (relative) of a
+    threshold may round either way in float32 and are counted apart."""
+    k, bm_ref, fl_ref = ref
+    blk = lbm.Blocks(desc, device="cuda:0")
+    blk.step_n(k, every)
+    bm, fl, kk, _ = blk.sensor_flags()
+    blk.close()
+    assert kk == k
+    near = np.zeros(bm_ref.shape, dtype=bool)
+    for t in theta:
+        near |= np.abs(bm_ref - t) <= eps * t
+    differ = fl != fl_ref
+    return {"step": int(k), "blocks": int(fl.size), "equal": int((~differ).sum()),
+            "frac": round(float((~differ).mean()), 6), "differ_near_threshold": int((differ & near).sum()),
+            "differ_elsewhere": int((differ & ~near).sum()),
+            "max_block_rel_err": float((np.abs(bm - bm_ref) / np.maximum(bm_ref, theta[0])).max()),
+            "oracle": "FP64, same initial state and steps"}
 
 
 def run_refined(args, lbm, torch):
@@ -487,7 +513,10 @@ def main():
         result["copy_calibration"] = cal
         result["roofline"]["frac_of_copy"] = round(achieved / cal["gbs"], 4)
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(w, tau, args.cpu_sample_steps)
+        result["cpu_baseline"], ref = cpu_baseline(w, tau, args.cpu_sample_steps, args.smagorinsky)
+        if ref is not None:
+            result["flag_agreement"] = flag_agreement(lbm, torch, desc, every, ref,
+                                                      (w.theta_refine, w.theta_coarsen))
     print(json.dumps(result), flush=True)
 
 
