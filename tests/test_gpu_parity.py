@@ -520,3 +520,61 @@ def test_tuning_overrides_keep_bits(lbm, scheme, monkeypatch, override):
         blk.close()
     for a, b in zip(out[0], out[1]):
         assert np.array_equal(a, b)
+
+
+def test_cavity256_pingpong_sampled_regions(lbm, orc):
+    """The 256^3 cavity in the benchmark's launch configuration (ping-pong, as
+    its 1.19 GiB buffers require), plain float32, from a seeded velocity
+    perturbation at equilibrium, 5 steps with the sensor on the last: two
+    48^3 regions, one in the corner where the lid meets two side walls and
+    one inside, against the FP64 oracle run on each region alone.  A cut face
+    of a region is periodic (or a still wall when its axis has a real wall),
+    which the compared cells, more than 5 cells away, cannot see; blocks
+    entirely among them compare their maxima and flags."""
+    w = lbm_inputs.cavity3d(n=256)
+    steps = 5
+    print(f"\n[case] {w.name} ping-pong, sampled regions after {steps} steps", flush=True)
+    st, tau = lbm.lbm_tau_from_reynolds(w.lid_speed, w.n_across, w.reynolds)
+    desc = lbm.make_desc(19, w.n, w.bc, tau, storage=lbm.LBM_F32, wall_u=w.wall_u)
+    blk = lbm.Blocks(desc)
+    assert not blk.scheme()["inplace"]
+    u = lbm_inputs.velocity_perturbation(w.n, 0.01, 3)
+    blk.set_equilibrium(u=u)
+    blk.step_n(steps, steps)
+    f_gpu = blk.populations()
+    bm_gpu, fl_gpu, k, _ = blk.sensor_flags()
+    assert k == steps
+    blk.close()
+    N, R = 256, 48
+    for lo in ((0, N - R, 0), (104, 104, 104)):
+        bc, wall_u, core, bcore = [], [[0.0] * 3 for _ in range(6)], [], []
+        for a in range(3):
+            real_lo, real_hi = lo[a] == 0, lo[a] + R == N
+            bc += [WALL, WALL] if (real_lo or real_hi) else [PERIODIC, PERIODIC]
+            c0 = 0 if real_lo else steps + 1
+            c1 = R if real_hi else R - steps - 1
+            core.append(slice(c0, c1))
+            bcore.append(slice(-(-c0 // 8), c1 // 8))          # blocks inside [c0, c1)
+            if real_lo:
+                wall_u[2 * a] = list(w.wall_u[2 * a])
+            if real_hi:
+                wall_u[2 * a + 1] = list(w.wall_u[2 * a + 1])
+        G = orc.Grid(q=19, n=(R, R, R), bc=tuple(bc), wall_u=wall_u, tau=tau)
+        sl = (slice(lo[2], lo[2] + R), slice(lo[1], lo[1] + R), slice(lo[0], lo[0] + R))
+        ur = np.ascontiguousarray(u[(slice(None),) + sl])
+        S0 = G.equilibrium_state(u=ur).astype(np.float32).astype(np.float64)
+        S, hist = G.run(S0, 0, steps, steps)
+        cz, cy, cx = core[2], core[1], core[0]
+        mine = f_gpu[(slice(None),) + sl][:, cz, cy, cx]
+        ref = S[:, cz, cy, cx]
+        err = np.abs(mine - ref).max()
+        moved = np.abs(ref - S0[:, cz, cy, cx]).max()
+        bz, by, bx = bcore[2], bcore[1], bcore[0]
+        gb = bm_gpu[lo[2] // 8:(lo[2] + R) // 8, lo[1] // 8:(lo[1] + R) // 8, lo[0] // 8:(lo[0] + R) // 8]
+        gf = fl_gpu[lo[2] // 8:(lo[2] + R) // 8, lo[1] // 8:(lo[1] + R) // 8, lo[0] // 8:(lo[0] + R) // 8]
+        rb, rf = hist[-1][1][bz, by, bx], hist[-1][2][bz, by, bx]
+        eb = _compare_bmax(gb[bz, by, bx], rb, 1)
+        n_exc = _compare_flags(gf[bz, by, bx], rf, rb, 1)
+        print(f"region at {lo}: population err {err:.2e} (moved {moved:.2e}), {rb.size} blocks, "
+              f"block max rel err {eb:.2e}, excused flag blocks {n_exc}")
+        assert moved > 1e-4 and err < 1e-6 and rb.size >= 64
