@@ -8,6 +8,9 @@ any size are checked instead, from a seeded velocity perturbation at
 equilibrium (patches placed by the seeded generator on a seeded block mask
 confined to z < 96):
 
+  * an isolated patch (the last one, 20+ coarse cells from any other) and the
+    coarse cells around it match the FP64 hierarchy oracle run on a 28^3
+    region around it alone, away from the region's cut faces;
   * far from every patch the coarse level evolves as the plain single-grid
     BGK step: after 3 coarse steps, a 64 x 56 x 64 region under the lid (16+
     cells from any patch) matches the FP64 oracle run on that region alone,
@@ -33,13 +36,15 @@ pytestmark = pytest.mark.gpu
 N = 256
 STEPS = 3
 REGION_LO, REGION_N = (96, 200, 168), (64, 56, 64)     # under the lid (+y face)
+ISOLATED = ((128, 128, 136), (140, 140, 148))           # a patch 24 fine cells wide, far from the rest
+MARGIN = 8                                              # coarse cells around it in the oracle's region
 
 
 def _boxes():
     nb = N // 8
     mask = (lbm_inputs.uniform(11, nb ** 3) < 0.2).reshape(nb, nb, nb)
     mask[12:] = False                                    # blocks with z >= 96 stay unflagged
-    return lbm_inputs.place_patches(mask, 8, (N, N, N), count=400, seed=7)
+    return lbm_inputs.place_patches(mask, 8, (N, N, N), count=399, seed=7) + [ISOLATED]
 
 
 def _run(torch, lbm, w, tau, u, boxes, production):
@@ -66,7 +71,7 @@ def test_full_size_hierarchy(orc, monkeypatch):
     w = lbm_inputs.cavity3d(n=N)
     st, tau = lbm.lbm_tau_from_reynolds(w.lid_speed, w.n_across, w.reynolds)
     boxes = _boxes()
-    assert len(boxes) >= 200 and max(lo[2] + (hi[2] - lo[2]) for lo, hi in boxes) < 120
+    assert len(boxes) >= 200 and max(hi[2] for lo, hi in boxes[:-1]) < 120
     u = lbm_inputs.velocity_perturbation(w.n, 0.01, 5)
     print(f"\n[case] full-size hierarchy: {len(boxes)} patches, production configuration", flush=True)
     monkeypatch.delenv("LBM_HIER_RESTRICT", raising=False)
@@ -94,6 +99,29 @@ def test_full_size_hierarchy(orc, monkeypatch):
     moved = np.abs(S[core] - S0[core]).max()
     print(f"far field vs oracle: max err {e_far:.2e} (populations moved by up to {moved:.2e})")
     assert moved > 1e-4 and e_far < 1e-6
+
+    # the isolated patch against the hierarchy oracle on the region around it
+    from oracle.hier import Hierarchy as OH
+    lo, hi = ISOLATED
+    sub_lo = [lo[a] - MARGIN for a in range(3)]
+    sub_n = tuple(hi[a] - lo[a] + 2 * MARGIN for a in range(3))
+    Gs = orc.Grid(q=19, n=sub_n, bc=(PERIODIC,) * 6, tau=tau)
+    sl = tuple(slice(sub_lo[a], sub_lo[a] + sub_n[a]) for a in (2, 1, 0))
+    us = np.ascontiguousarray(u[(slice(None),) + sl])
+    Ss = Gs.equilibrium_state(u=us).astype(np.float32).astype(np.float64)
+    O = OH(Gs, [((MARGIN,) * 3, tuple(MARGIN + hi[a] - lo[a] for a in range(3)))])
+    O.init_from(Ss)
+    for k in range(STEPS):
+        Ss, bm_o = O.step(Ss, k, sensor=(k == STEPS - 1))
+    e_patch = np.abs(pa[1][-1] - O.patch_fields(0)[2]).max()
+    core = tuple(slice(STEPS + 1, sub_n[a] - STEPS - 1) for a in (2, 1, 0))
+    e_near = np.abs(pa[0][(slice(None),) + sl][(slice(None),) + core] - Ss[(slice(None),) + core]).max()
+    nb_before = sum(int(np.prod([2 * (b[1][a] - b[0][a]) // 8 for a in range(3)])) for b in boxes[:-1])
+    bm_p = pa[2][nb_before:nb_before + bm_o[0].size]
+    e_pb = float((np.abs(bm_p - bm_o[0].ravel()) / np.maximum(bm_o[0].ravel(), 1e-3)).max())
+    print(f"isolated patch vs hierarchy oracle: fine {e_patch:.2e}, coarse around it {e_near:.2e}, "
+          f"fine block max rel err {e_pb:.2e}")
+    assert e_patch < 1e-6 and e_near < 1e-6 and e_pb < 2e-4
 
     e_coarse = np.abs(pa[0] - pb[0]).max()
     e_fine = max(np.abs(a - b).max() for a, b in zip(pa[1], pb[1]))
