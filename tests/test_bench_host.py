@@ -15,7 +15,6 @@ import sys
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SOURCES = {"refined256": "patch_kernels.hpp"}          # default: step_kernel.hpp
 
 
 def _summaries():
