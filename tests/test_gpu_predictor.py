@@ -56,9 +56,9 @@ def test_predictor_beats_reusing_flags(lbm):
     Xte, Yte, runs_te = _snapshots(lbm, P, 202, 4)
     assert Xtr.shape == (200, 16, 16, 16, 6)
     print(f"training cavities (Re, lid) {runs_tr}\nheld-out {runs_te}", flush=True)
-    print("[case] predictor training 6000 iterations", flush=True)
+    print("[case] predictor training 10000 iterations", flush=True)
     net = P.FlagPredictor(seed=0)
-    hist = net.fit(Xtr, Ytr, iters=6000, batch=8, lr=1e-3, log_every=1000)
+    hist = net.fit(Xtr, Ytr, iters=10000, batch=8, lr=2e-3, log_every=2000)
     print("loss " + ", ".join(f"{it}: {l:.3e}" for it, l in hist), flush=True)
     pred = net.predict_log(Xte)
 
