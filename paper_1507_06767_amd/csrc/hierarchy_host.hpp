@@ -29,6 +29,7 @@ struct lbm_hierarchy {
     std::vector<PatchRec> rec;
     int64_t total_padded, covered, nblocks, fine_cells, max_patch_cells;
     int64_t pitch;            // elements between fine planes
+    int64_t xg_pitch;         // elements between the x-face ghost planes (after the q fine planes)
     size_t elem;              // bytes per stored value
     size_t meta_patch, meta_tile, meta_cover, meta_gdst, meta_gsrc, meta_gloc, meta_gmask, meta_gtile, meta_rc,
         meta_rf, meta_rp,
@@ -73,7 +74,7 @@ lbm_status hier_layout(const lbm_blocks *h, int32_t nbox, const lbm_box *boxes, 
     H->npatch = nbox;
     H->boxes.assign(boxes, boxes + nbox);
     H->rec.assign(nbox, PatchRec{});
-    int64_t padded = 0, blocks = 0, cov = 0, maxc = 0;
+    int64_t padded = 0, blocks = 0, cov = 0, maxc = 0, xg = 0;
     for (int p = 0; p < nbox; ++p) {
         const lbm_box &b = boxes[p];
         PatchRec &r = H->rec[p];
@@ -96,6 +97,8 @@ lbm_status hier_layout(const lbm_blocks *h, int32_t nbox, const lbm_box *boxes, 
         r.off = (int)padded;
         r.blk0 = (int)blocks;
         r.coff = (int)cov;
+        r.xoff = (int)xg;                         // the patch's two x-face ghost arrays
+        xg += 2 * (int64_t)(r.e[1] + 2) * (r.e[2] + 2);
         const int64_t pc = (int64_t)(r.e[0] + 2) * (r.e[1] + 2) * (r.e[2] + 2);
         const int64_t cells = (int64_t)r.e[0] * r.e[1] * r.e[2];
         padded += pc;
@@ -104,7 +107,8 @@ lbm_status hier_layout(const lbm_blocks *h, int32_t nbox, const lbm_box *boxes, 
         maxc = std::max(maxc, cells);
     }
     // the ghost list packs a padded index and three interpolation bits in 32 bits
-    if (padded >= (int64_t(1) << 29)) return fail(LBM_ENOTSUP, "patches hold more than 2^29 padded cells");
+    if (padded >= (int64_t(1) << 29) || xg >= (int64_t(1) << 29))
+        return fail(LBM_ENOTSUP, "patches hold more than 2^29 padded cells");
     H->total_padded = padded;
     H->nblocks = blocks;
     H->covered = cov;
@@ -112,9 +116,11 @@ lbm_status hier_layout(const lbm_blocks *h, int32_t nbox, const lbm_box *boxes, 
     H->max_patch_cells = maxc;
     H->elem = h->L.elem;
     H->pitch = (int64_t)round_up((size_t)padded, 64) + 64;
+    H->xg_pitch = (int64_t)round_up((size_t)xg, 64) + 64;
     H->tau_f = tau_f;
     H->alpha = (tau_f - 1.0) / (2.0 * (tau_c - 1.0));
-    H->bytes[LBM_HBUF_F_A] = H->bytes[LBM_HBUF_F_B] = round_up((size_t)H->q * H->pitch * H->elem, kAlign);
+    H->bytes[LBM_HBUF_F_A] = H->bytes[LBM_HBUF_F_B] =
+        round_up((size_t)H->q * (H->pitch + H->xg_pitch) * H->elem, kAlign);
     H->bytes[LBM_HBUF_BLOCK_MAX] = round_up((size_t)blocks * h->L.cbytes, kAlign);
     H->bytes[LBM_HBUF_FLAGS] = round_up((size_t)blocks, kAlign);
     H->nghost = padded - 8 * cov;
@@ -151,6 +157,8 @@ PatchArgs<C> patch_args(lbm_hierarchy *H, const void *src, void *dst) {
     a.src = src;
     a.dst = dst;
     a.pitch = H->pitch;
+    a.xg_base = (int64_t)H->q * H->pitch;
+    a.xg_pitch = H->xg_pitch;
     char *meta = static_cast<char *>(H->buf[LBM_HBUF_META]);
     a.patch = reinterpret_cast<const PatchRec *>(meta + H->meta_patch);
     a.tile = reinterpret_cast<const PatchTile *>(meta + H->meta_tile);
@@ -434,7 +442,10 @@ lbm_status lbm_create_hierarchy(lbm_blocks *coarse, int32_t nbox, const lbm_box 
                             pc[ua] = uu;
                             pc[va] = vv;
                             const int g[3] = {r.o[0] + pc[0] - 1, r.o[1] + pc[1] - 1, r.o[2] + pc[2] - 1};
-                            const uint32_t dst = (uint32_t)(r.off + ((int64_t)pc[2] * P[1] + pc[1]) * P[0] + pc[0]);
+                            // an x-face ghost lives in its side's compact array [pc2][pc1]
+                            const uint32_t dst =
+                                (na == 0) ? (uint32_t)(r.xoff + ((int64_t)(f & 1) * P[2] + pc[2]) * P[1] + pc[1])
+                                          : (uint32_t)(r.off + ((int64_t)pc[2] * P[1] + pc[1]) * P[0] + pc[0]);
                             uint32_t need = 0;   // populations an interior cell pulls from this ghost
                             for (int i = 0; i < H->q; ++i) {
                                 bool in = true;
@@ -444,6 +455,7 @@ lbm_status lbm_create_hierarchy(lbm_blocks *coarse, int32_t nbox, const lbm_box 
                                 }
                                 if (in) need |= 1u << i;
                             }
+                            if (na == 0) need |= kGhostXFace;
                             gmask.push_back(need);
                             const int owner = cover[((size_t)(g[2] >> 1) * ny + (g[1] >> 1)) * nx + (g[0] >> 1)];
                             if (owner >= 0) {
@@ -531,6 +543,10 @@ lbm_status lbm_create_hierarchy(lbm_blocks *coarse, int32_t nbox, const lbm_box 
                                            coarse_view<C>(H, X, X, 0.0, nullptr), fine_buf(H, 0), H->total_padded, s);
         });
         e = hipGetLastError();
+        // the x-face ghost arrays start defined (every fine step is preceded by a ghost fill)
+        for (int b = 0; b < 2 && e == hipSuccess; ++b)
+            e = hipMemsetAsync(static_cast<char *>(H->buf[LBM_HBUF_F_A + b]) + (size_t)H->q * H->pitch * H->elem, 0,
+                               (size_t)H->q * H->xg_pitch * H->elem, s);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {

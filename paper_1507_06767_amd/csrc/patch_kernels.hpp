@@ -35,7 +35,8 @@ struct PatchRec {
     int off;        // first padded cell of the patch in each plane
     int blk0;       // first 8^3 sensor block of the patch
     int coff;       // first covered coarse cell (restriction enumeration)
-    int pad[3];
+    int xoff;       // first element of its two x-face ghost arrays (low x side, then high)
+    int pad[2];
 };
 static_assert(sizeof(PatchRec) == 48, "PatchRec layout");
 
@@ -56,6 +57,10 @@ static_assert(sizeof(PatchTile) == 32, "PatchTile layout");
 // extent dx x dy x dz <= kGhostBox cells; extent 0 when every ghost of the
 // tile copies from an abutting patch).
 constexpr int kGhostBox = 200;
+// gmask bit of a ghost on an x face: its values go to the patch's compact
+// x-face array (element gdst & 0x1FFFFFFF of each x-ghost plane), not to its
+// slot in the padded rows (population bits stay below bit 27).
+constexpr uint32_t kGhostXFace = 1u << 31;
 struct GhostTile {
     int k0, n;
     int ox, oy, oz;
@@ -68,6 +73,8 @@ struct PatchArgs {
     const void *src;          // fine state read by the step (padded planes)
     void *dst;                // fine state written by the step
     int64_t pitch;            // elements between fine planes
+    int64_t xg_base;          // first element of the x-face ghost planes (after the q padded planes)
+    int64_t xg_pitch;         // elements between x-face ghost planes
     const PatchRec *patch;    // [npatch]
     const PatchTile *tile;    // [ntiles]
     int npatch, ntiles;
@@ -137,6 +144,13 @@ __device__ __forceinline__ void store_dev(void *buf, int64_t idx, C d, C shift, 
     static_cast<T *>(buf)[idx] = static_cast<T>(shifted ? d : d + shift);
 }
 
+// Element of population i of ghost entry g: its slot in the padded rows, or
+// for an x-face ghost its element of the compact x-face array.
+template <typename C>
+__device__ __forceinline__ int64_t ghost_index(const PatchArgs<C> &a, uint32_t need, int i, int64_t g) {
+    return (need & kGhostXFace) ? a.xg_base + i * a.xg_pitch + g : i * a.pitch + g;
+}
+
 // Padded index of fine cell (x, y, z) of a patch (interior cells 0..e-1).
 __device__ __forceinline__ int64_t padded_index(const PatchRec &p, int x, int y, int z) {
     return (int64_t)p.off + ((int64_t)(z + 1) * (p.e[1] + 2) + (y + 1)) * (p.e[0] + 2) + (x + 1);
@@ -192,8 +206,15 @@ __global__ __launch_bounds__(512) void patch_step(const PatchArgs<C> a, const Co
         // row's ghost slot beside them (refilled before it is read): every
         // padded row is then written whole, and the memory system sees whole
         // lines instead of lines with a 4-byte hole at each row end
-        const bool xedge = (tl.x0 + x == 0) || (tl.x0 + x == p.e[0] - 1);
-        const int xoff = (tl.x0 + x == 0) ? -(int)sizeof(T) : (int)sizeof(T);
+        const bool xlo = tl.x0 + x == 0, xhi = tl.x0 + x == p.e[0] - 1;
+        const bool xedge = xlo || xhi;
+        const int xoff = xlo ? -(int)sizeof(T) : (int)sizeof(T);
+        // the first and last cell of a row pull their x-face ghosts from the
+        // compact x-face arrays: element (z + 1) P1 + (y + 1) of the low or
+        // high side, minus the population's (y, z) offset
+        const int P1 = p.e[1] + 2;
+        const int64_t xg_side = (int64_t)P1 * (p.e[2] + 2);
+        const T *xg0 = static_cast<const T *>(a.src) + a.xg_base + p.xoff + (xhi ? xg_side : 0) + (tl.y0 + y + 1);
         C m = C(0);
         if constexpr (RESTRICT) {
             for (int r = t; r < Q * kCoarsePerTile; r += 512) racc[r] = C(0);
@@ -202,6 +223,7 @@ __global__ __launch_bounds__(512) void patch_step(const PatchArgs<C> a, const Co
 #pragma unroll 1
         for (int zz = t / (8 * W); zz < 8; zz += zstep) {
             // padded cell index (< 2^29, checked on the host) as a byte offset
+            const T *xgc = xg0 + (int64_t)(tl.z0 + zz + 1) * P1;
             const uint32_t cb = (uint32_t)(p.off + (tl.z0 + zz + 1) * sz + (tl.y0 + y + 1) * sy + (tl.x0 + x + 1)) *
                                 (uint32_t)sizeof(T);
             const int rslot = ((zz >> 1) * 4 + (y >> 1)) * (W >> 1) + (x >> 1);
@@ -212,7 +234,13 @@ __global__ __launch_bounds__(512) void patch_step(const PatchArgs<C> a, const Co
                 using V = Vel<Q, i>;
                 const int64_t delta = V::x + (int64_t)V::y * sy + (int64_t)V::z * sz;
                 const char *base = src + i * plane_bytes - delta * (int64_t)sizeof(T);
-                const C v = static_cast<C>(*reinterpret_cast<const T *>(base + cb));
+                const T *from = reinterpret_cast<const T *>(base + cb);
+                if constexpr (V::x > 0) {
+                    if (xlo) from = xgc + (i * a.xg_pitch - (V::z * P1 + V::y));
+                } else if constexpr (V::x < 0) {
+                    if (xhi) from = xgc + (i * a.xg_pitch - (V::z * P1 + V::y));
+                }
+                const C v = static_cast<C>(*from);
                 if constexpr (SH) d[i] = v;
                 else d[i] = v - a.shift[i];
             });
@@ -366,7 +394,7 @@ __global__ __launch_bounds__(256) void patch_ghosts(const PatchArgs<C> a, const 
         static_for<0, Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             if ((need >> i) & 1u)
-                static_cast<T *>(state)[i * a.pitch + g] = static_cast<const T *>(state)[i * a.pitch + src];
+                static_cast<T *>(state)[ghost_index(a, need, i, g)] = static_cast<const T *>(state)[i * a.pitch + src];
         });
         return;
     }
@@ -379,7 +407,7 @@ __global__ __launch_bounds__(256) void patch_ghosts(const PatchArgs<C> a, const 
     coarse_to_fine<Q, T, C, SH>(v, a.shift, a.rho0, C(x0) + fx, C(y0) + fy, C(z0) + fz, d);
     static_for<0, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        if ((need >> i) & 1u) store_dev<T>(state, i * a.pitch + g, d[i], a.shift[i], SH);
+        if ((need >> i) & 1u) store_dev<T>(state, ghost_index(a, need, i, g), d[i], a.shift[i], SH);
     });
 }
 
@@ -419,7 +447,7 @@ __global__ __launch_bounds__(256) void patch_ghosts_lds(const PatchArgs<C> a, co
         static_for<0, Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             if ((need >> i) & 1u)
-                static_cast<T *>(state)[i * a.pitch + g] = static_cast<const T *>(state)[i * a.pitch + src];
+                static_cast<T *>(state)[ghost_index(a, need, i, g)] = static_cast<const T *>(state)[i * a.pitch + src];
         });
         return;
     }
@@ -443,7 +471,7 @@ __global__ __launch_bounds__(256) void patch_ghosts_lds(const PatchArgs<C> a, co
     static_for<0, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         const C deq = deq_of<Q, i>(mo, a.rho0);
-        if ((need >> i) & 1u) store_dev<T>(state, i * a.pitch + g, deq + v.alpha * (d[i] - deq), a.shift[i], SH);
+        if ((need >> i) & 1u) store_dev<T>(state, ghost_index(a, need, i, g), deq + v.alpha * (d[i] - deq), a.shift[i], SH);
     });
 }
 
