@@ -307,7 +307,8 @@ enum { LBM_HBUF_F_A = 0, LBM_HBUF_F_B = 1, LBM_HBUF_BLOCK_MAX = 2,   /* hierarch
        LBM_HBUF_FLAGS = 3, LBM_HBUF_META = 4, LBM_NHBUF = 5 };
 
 /* Sizes of the five caller-owned device buffers of a hierarchy: the fine
- * populations twice (padded patches, ping-pong), the fine block maxima (the
+ * populations twice (padded patches, then the compact x-face ghost arrays;
+ * ping-pong), the fine block maxima (the
  * coarse handle's compute precision), the fine flags, and META (patch table,
  * block-to-patch map, coarse cover map, staging).  Host computation only. */
 lbm_status lbm_hierarchy_required_bytes(const lbm_blocks *coarse, int32_t nbox, const lbm_box *boxes,
