@@ -17,8 +17,10 @@
  *   - Device memory is OWNED BY THE CALLER.  The library never allocates
  *     device memory: the caller sizes the five buffers with
  *     lbm_required_bytes(), allocates them (for instance as torch tensors)
- *     and keeps them alive until lbm_destroy().  Host arrays are only read
- *     or written during the call that receives them.
+ *     and keeps them alive until lbm_destroy().  The one exception is the
+ *     32 KiB static workspace of lbm_conservation_noalloc, part of the
+ *     library's code object.  Host arrays are only read or written during
+ *     the call that receives them.
  *   - Work is enqueued on the caller's HIP stream (lbm_desc.stream; NULL is
  *     the null stream).  lbm_step_n() is asynchronous; the calls that return
  *     host data synchronise that stream.  One handle must not be used from
@@ -253,6 +255,21 @@ lbm_status lbm_set_step(lbm_blocks *h, int64_t step);
  * fixed-order two-pass tree (bitwise reproducible): out[0] = sum rho,
  * out[1..3] = sum_i xi_i S_i summed over cells.  Synchronises the stream. */
 lbm_status lbm_conservation(lbm_blocks *h, double out[4]);
+
+/* For callers that cannot allocate device memory or pass a workspace (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): lbm_conservation with the same result bits, whose partial sums
+ * and totals live in a 32 KiB array the library holds in device memory of
+ * each GPU it runs on (kept until the process ends; its address is looked
+ * up once per device, on the first call there) instead of the handle's
+ * scratch buffer.  No grid is too large for it: the first pass caps its
+ * workgroups at 1024, each then summing more cells.  Allocates nothing and
+ * calls no allocating routine; for an in-place handle the natural-order
+ * copy of the state is built in F_B, which the caller already provided.
+ * All calls on one GPU share the array: calls that overlap in time on one
+ * GPU (two host threads, or two streams) race and must be serialised by the
+ * caller.  Synchronises the stream. */
+lbm_status lbm_conservation_noalloc(lbm_blocks *h, double out[4]);
 
 /* tau = nu / c_s^2 + 1/2 with nu = u * n_across / re (Eq. nu_omega, c_s^2 = 1/3). */
 lbm_status lbm_tau_from_reynolds(double u, double n_across, double re, double *tau);

@@ -105,6 +105,7 @@ def _load_library():
         "lbm_sensor_average": [H, dp, ctypes.POINTER(ctypes.c_int64)],
         "lbm_sensor_average_end": [H],
         "lbm_conservation": [H, dp],
+        "lbm_conservation_noalloc": [H, dp],
         "lbm_tau_from_reynolds": [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp],
     }
     i32p, i64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
@@ -275,6 +276,12 @@ def lbm_set_step(h, step: int):
 def lbm_conservation(h):
     out = np.zeros(4)
     st = _lib.lbm_conservation(h, _dptr(out))
+    return st, out
+
+
+def lbm_conservation_noalloc(h):
+    out = np.zeros(4)
+    st = _lib.lbm_conservation_noalloc(h, _dptr(out))
     return st, out
 
 

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -827,6 +828,70 @@ lbm_status lbm_conservation(lbm_blocks *h, double out[4]) {
     double *partial = scratch_d(h, h->L.partial_off);
     double *res = scratch_d(h, h->L.out_off);
     const int nwg = (int)std::min<int64_t>(kMaxPartials, (cells + kReduceThreads - 1) / kReduceThreads);
+    void *canon = canonical_state(h);
+    with_types(h, [&]<int Q, typename T>() {
+        hipLaunchKernelGGL((conservation_pass1<Q, T>), dim3(nwg), dim3(kReduceThreads), 0, h->stream,
+                           planes_of<Q, T>(h, canon), partial);
+    });
+    hipLaunchKernelGGL(conservation_pass2, dim3(1), dim3(kReduceThreads), 0, h->stream, partial, nwg, res);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(out, res, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+}  // extern "C"
+
+// Workspace of lbm_conservation_noalloc, owned by the library: the first
+// pass's partial sums (4 doubles for each of at most kMaxPartials
+// workgroups) and the 4 totals, 32 KiB.  Each GPU the library runs on holds
+// its own copy until the process ends.  In host code `scratch` names a host
+// stand-in, not device memory: only the address from hipGetSymbolAddress,
+// kept per device in g_scratch_dev, is passed to kernels and copies.
+static __device__ __align__(256) double scratch[kMaxPartials * 4 + 4];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (the current device), looked up
+// once per device.
+lbm_status noalloc_scratch(int device, double **out) {
+    if (device < 0 || device >= kMaxDevices) return fail(LBM_ENOTSUP, "device %d beyond %d", device, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(LBM_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_dev[device] = static_cast<double *>(p);
+    }
+    *out = g_scratch_dev[device];
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_conservation_noalloc(lbm_blocks *h, double out[4]) {
+    lbm_status st = check_handle(h);
+    if (st != LBM_OK) return st;
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    const int64_t cells = h->L.cells;
+    // the first pass caps its workgroups at kMaxPartials (each then sums
+    // more cells), so every grid a handle accepts fits the workspace
+    const int nwg = (int)std::min<int64_t>(kMaxPartials, (cells + kReduceThreads - 1) / kReduceThreads);
+    double *ws = nullptr;
+    st = noalloc_scratch(h->device, &ws);
+    if (st != LBM_OK) return st;
+    double *partial = ws;
+    double *res = ws + (size_t)kMaxPartials * 4;
+    // The same kernels, workgroup count and summation order as
+    // lbm_conservation, so the totals are the same bits.  Every partial the
+    // second pass reads is written by the first, so nothing needs clearing.
     void *canon = canonical_state(h);
     with_types(h, [&]<int Q, typename T>() {
         hipLaunchKernelGGL((conservation_pass1<Q, T>), dim3(nwg), dim3(kReduceThreads), 0, h->stream,
