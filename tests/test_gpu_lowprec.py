@@ -133,24 +133,29 @@ def test_channel256_10000_steps_lowprec(lbm, orc):
         blk.close()
 
 
-def test_cavity128_5000_steps_lowprec(lbm):
-    """The 128^3 Re 1000 cavity (the benchmark workload) after 5000 steps in
-    16-bit storage, against the stored FP64 oracle values: mid-plane velocity,
-    density, block maxima and flag agreement."""
+def test_cavity128_10000_steps_lowprec(lbm):
+    """The 128^3 Re 1000 cavity (the benchmark workload) over 10^4 steps in
+    16-bit storage, against the stored FP64 oracle values: mid-plane velocity
+    and density after steps 5000 and 10000, block maxima and flag agreement
+    at steps 1000..10000."""
     g = np.load(os.path.join(os.path.dirname(__file__), "golden", "cavity3d_d3q19_128_re1000.npz"))
     w = lbm_inputs.cavity3d()
     st, tau = lbm.lbm_tau_from_reynolds(w.lid_speed, w.n_across, w.reynolds)
     # (mid-plane u rel L2, rho max abs, block max rel, flag disagreement
-    # fraction), about 2.5x the errors measured on MI355X: f16s 4.1e-4 /
-    # 3.6e-5 / 2.1e-2 / 0.03%, bf16s 6.3e-3 / 2.1e-4 / 0.22 / 0.37%, f16sr
-    # 5.2e-4 / 3.7e-5 / 3.0e-2 / 0.04%, bf16sr 4.0e-3 / 3.3e-4 / 0.31 / 0.49%.
-    bounds = {F16S: (1e-3, 1e-4, 6e-2, 0.002), BF16S: (1.5e-2, 6e-4, 0.5, 0.01),
-              F16SR: (1.5e-3, 1e-4, 8e-2, 0.002), BF16SR: (1e-2, 8e-4, 0.7, 0.015)}
+    # fraction), about 2.5x the errors measured on MI355X (the larger of
+    # steps 5000 and 10000; block maxima and flags over all 10 sensor sets):
+    # f16s 4.5e-4 / 3.1e-5 / 2.0e-2 / 0.02%, bf16s 1.1e-2 / 2.1e-4 / 0.28 /
+    # 0.37%, f16sr 5.3e-4 / 4.2e-5 / 2.9e-2 / 0.04%, bf16sr 4.2e-3 / 3.1e-4 /
+    # 0.31 / 0.69%.
+    bounds = {F16S: (1.2e-3, 8e-5, 5e-2, 0.002), BF16S: (3e-2, 5e-4, 0.7, 0.01),
+              F16SR: (1.5e-3, 1e-4, 8e-2, 0.002), BF16SR: (1.1e-2, 8e-4, 0.8, 0.02)}
+    nsets = len(g["steps"])
     for storage in (F16S, BF16S, F16SR, BF16SR):
-        print(f"\n[case] {w.name} 5000 steps {NAMES[storage]}", flush=True)
+        print(f"\n[case] {w.name} 10000 steps {NAMES[storage]}", flush=True)
         desc = lbm.make_desc(19, w.n, w.bc, tau, storage=storage, wall_u=w.wall_u)
         blk = lbm.Blocks(desc)
         worst, mism = 0.0, 0
+        fields = {}
         for j, k in enumerate(g["steps"]):
             blk.step_n(int(k) - blk.step, 1)
             bm, fl, kk, nonfinite = blk.sensor_flags()
@@ -158,13 +163,19 @@ def test_cavity128_5000_steps_lowprec(lbm):
             ref = g["block_max"][j]
             worst = max(worst, float((np.abs(bm - ref) / np.maximum(ref, 1e-3)).max()))
             mism += int((fl != g["flags"][j]).sum())
-        rho, u = blk.macros()
-        eu = np.linalg.norm(u[:, 64] - g["u_mid"]) / np.linalg.norm(g["u_mid"])
-        er = np.abs(rho[64] - g["rho_mid"]).max()
-        frac = mism / (5 * g["flags"][0].size)
-        print(f"cavity {NAMES[storage]}: mid-plane u rel err {eu:.2e}, rho max err {er:.2e}, "
-              f"block max rel err {worst:.2e}, flag disagreement {mism} of {5 * g['flags'][0].size} "
-              f"({100 * frac:.2f}%)")
+            if k in (5000, 10000):
+                rho, u = blk.macros()
+                eu = np.linalg.norm(u[:, 64] - g[f"u_mid_{k}"]) / np.linalg.norm(g[f"u_mid_{k}"])
+                er = np.abs(rho[64] - g[f"rho_mid_{k}"]).max()
+                es = float((np.abs(bm - ref) / np.maximum(ref, 1e-3)).max())
+                fields[int(k)] = (eu, er)
+                print(f"cavity {NAMES[storage]} step {k}: mid-plane u rel err {eu:.2e}, rho max err {er:.2e}, "
+                      f"block max rel err {es:.2e}", flush=True)
+        frac = mism / (nsets * g["flags"][0].size)
+        print(f"cavity {NAMES[storage]}: block max rel err (all sensor steps) {worst:.2e}, flag disagreement "
+              f"{mism} of {nsets * g['flags'][0].size} ({100 * frac:.2f}%)")
         bu, brho, bs, bf = bounds[storage]
-        assert eu < bu and er < brho and worst < bs and frac < bf
+        for k, (eu, er) in fields.items():
+            assert eu < bu and er < brho
+        assert worst < bs and frac < bf
         blk.close()
