@@ -22,8 +22,12 @@ slower one, whose figure is "achieved".  A 1 GiB device copy of random data
 is timed for comparison (copy_calibration, frac_of_copy).
 "traffic" is the measured HBM bytes per launch of that kernel from the
 committed rocprofv3 counter summary, when it was taken on the current kernel
-source.  The CPU baseline is the FP64 oracle timed on the host on a short run
-of the same workload.
+source.  The 128^3 in-place state (152 MiB) can stay in the 256 MB Infinity
+Cache (roofline.cache_resident); the default workload therefore also times
+the same step + sensor on the 256^3 cavity in float32 (ping-pong, 2.55 GB
+moved per step, beyond that cache), reported as roofline_cache_proof.  The
+CPU baseline is the FP64 oracle timed on the host on a short run of the same
+workload.
 
 --workload refined256: the two-level patch hierarchy.  A 256^3 D3Q19
 cavity (Re 1000) runs 1000 coarse steps, up to 400 cubic patches with fine
@@ -186,10 +190,51 @@ def flag_agreement(lbm, torch, desc, every, ref, theta, eps=2e-4):
             "oracle": "FP64, same initial state and steps"}
 
 
+def cache_proof_leg(lbm, torch, steps, warmup, every=1):
+    """The same step + sensor on the 256^3 cavity, float32, ping-pong: its two
+    1.19 GiB buffers cannot stay in the 256 MB Infinity Cache, so every step
+    streams the state from and to HBM.  Timed like the main leg (HIP events
+    around `steps` back-to-back steps on the library's stream); one kernel
+    runs per step, so the mean step period is its duration."""
+    import lbm_inputs
+    w = lbm_inputs.cavity3d(n=256, storage="f32")
+    st, tau = lbm.lbm_tau_from_reynolds(w.lid_speed, w.n_across, w.reynolds)
+    desc = lbm.make_desc(19, w.n, w.bc, tau, storage=lbm.LBM_F32, wall_u=w.wall_u,
+                         theta_refine=w.theta_refine, theta_coarsen=w.theta_coarsen)
+    blk = lbm.Blocks(desc, device="cuda:0")
+    stream = blk.stream
+    blk.step_n(warmup, every)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    blk.step_n(steps, every)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    bm, fl, k, nonfinite = blk.sensor_flags()
+    sch = blk.scheme()
+    blk.close()
+    step_s = ms / 1e3 / steps
+    algo = 2 * 19 * 4 * w.cells
+    achieved = algo / step_s / 1e9
+    tag = "cavity256_f32_pingpong"
+    return {"workload": w.name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": _traffic_from_profile(tag), "kernel": "pingpong",
+            "algorithmic_bytes_per_launch": algo, "per_kernel_us": {"pingpong": round(step_s * 1e6, 2)},
+            "mlups": round(w.cells / step_s / 1e6, 1), "steps": steps, "warmup": warmup,
+            "sensor_every": every, "scheme": sch, "last_sensor_step": k, "nonfinite": bool(nonfinite),
+            "working_set_bytes": algo}
+
+
 def run_refined(args, lbm, torch):
     """The two-level hierarchy over the 256^3 cavity; returns the JSON dict."""
     import lbm_inputs
-    storage = {"f32": lbm.LBM_F32, "f32s": lbm.LBM_F32_SHIFTED, "f64": lbm.LBM_F64}[args.storage]
+    storage = {"f32": lbm.LBM_F32, "f32s": lbm.LBM_F32_SHIFTED, "f64": lbm.LBM_F64,
+               "f16s": lbm.LBM_F16_SHIFTED, "bf16s": lbm.LBM_BF16_SHIFTED,
+               "f16sr": lbm.LBM_F16_SHIFTED_SR, "bf16sr": lbm.LBM_BF16_SHIFTED_SR}[args.storage]
+    sr = storage in (lbm.LBM_F16_SHIFTED_SR, lbm.LBM_BF16_SHIFTED_SR)
     w = lbm_inputs.cavity3d(n=256, storage=args.storage)
     st, tau = lbm.lbm_tau_from_reynolds(w.lid_speed, w.n_across, w.reynolds)
     desc = lbm.make_desc(19, w.n, w.bc, tau, storage=storage, wall_u=w.wall_u,
@@ -200,7 +245,8 @@ def run_refined(args, lbm, torch):
     blk.step_n(1000, 1000)
     bm, fl, _, _ = blk.sensor_flags()
     boxes = lbm_inputs.place_patches(fl == 1, 8, w.n, count=400, seed=7)
-    H = lbm.Hierarchy(blk, boxes, use_graph=True)
+    # stochastic rounding keys on the step index: launched step by step
+    H = lbm.Hierarchy(blk, boxes, use_graph=not sr)
     tx, wg, fine_us = H.autotune(5)
     H.step_n(args.warmup, 0)
     torch.cuda.synchronize()
@@ -222,7 +268,7 @@ def run_refined(args, lbm, torch):
     info = H.info()
     coarse_cells, fine_cells = w.cells, info["fine_cells"]
     updates = (coarse_cells + 2 * fine_cells) * args.steps
-    elem = 8 if storage == lbm.LBM_F64 else 4
+    elem = 8 if storage == lbm.LBM_F64 else (2 if storage >= lbm.LBM_F16_SHIFTED else 4)
     fine_bytes = 2 * 19 * elem * fine_cells
     achieved = fine_bytes / (fine_us * 1e-6) / 1e9
     uniform_fine_updates = 2 * 8 * coarse_cells            # a uniform 512^3 grid, 2 steps per coarse step
@@ -389,6 +435,8 @@ def main():
                     help="single launches timed one by one for the per-kernel durations")
     ap.add_argument("--no-copy-calibration", action="store_true",
                     help="skip timing a 1 GiB device copy (reported as copy_calibration)")
+    ap.add_argument("--no-cache-proof", action="store_true",
+                    help="skip the 256^3 leg of the default workload (roofline_cache_proof)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -508,10 +556,22 @@ def main():
         "env": host_env(),
     }
     blk.close()
+    # The in-place 128^3 float32 state (152 MiB) can stay in the 256 MB
+    # Infinity Cache, so the figure above is not an HBM-only one; the 256^3
+    # leg below is.
+    state_bytes = (1 if result["roofline"]["scheme"]["inplace"] else 2) * w.q * elem * w.cells
+    result["roofline"]["state_bytes"] = state_bytes
+    result["roofline"]["cache_resident"] = state_bytes <= (256 << 20)
+    if (args.workload == "cavity128" and args.storage == "f32" and w.q == 19 and args.smagorinsky == 0.0
+            and not args.no_cache_proof):
+        result["roofline_cache_proof"] = cache_proof_leg(lbm, torch, args.steps, args.warmup)
     if not args.no_copy_calibration:
         cal = copy_calibration()
         result["copy_calibration"] = cal
         result["roofline"]["frac_of_copy"] = round(achieved / cal["gbs"], 4)
+        if "roofline_cache_proof" in result:
+            cp = result["roofline_cache_proof"]
+            cp["frac_of_copy"] = round(cp["achieved"] / cal["gbs"], 4)
     if not args.no_cpu_baseline:
         result["cpu_baseline"], ref = cpu_baseline(w, tau, args.cpu_sample_steps, args.smagorinsky)
         if ref is not None:

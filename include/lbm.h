@@ -243,8 +243,9 @@ lbm_status lbm_set_equilibrium(lbm_blocks *h, const double *rho_host, const doub
 /* How the handle streams: *inplace = 1 for the single-buffer scheme (steps
  * alternate between a gather-scatter launch and a local launch; the step
  * counter's parity says which comes next via *next_is_gather), 0 for
- * ping-pong; *tile_x = workgroup tile width in cells.  Any pointer may be
- * NULL.  Pure host query. */
+ * ping-pong; *tile_x = workgroup tile width in cells (256: row tiles of one
+ * row, otherwise tiles of 8 rows).  Any pointer may be NULL.  Pure host
+ * query. */
 lbm_status lbm_get_scheme(lbm_blocks *h, int32_t *inplace, int32_t *next_is_gather, int32_t *tile_x);
 
 /* Step counter (number of steps taken since it was last set). */
@@ -281,9 +282,10 @@ void lbm_destroy(lbm_blocks *h);
 /* Message of the last failed call on this thread ("" if none). */
 const char *lbm_last_error(void);
 
-/* Picks the fastest tile width (32, 64 or 128 cells along x) for the handle's
- * step kernel by timing `reps` launches (in-place: `reps` pairs) of each on
- * the handle's stream, and keeps it for later steps.  The state is not
+/* Picks the fastest tile for the handle's step kernel, 32, 64 or 128 cells
+ * along x by 8 rows, or for 3D ping-pong also row tiles of 256 cells of one
+ * row (*tile_x = 256), by timing `reps` launches (in-place: `reps` pairs) of
+ * each on the handle's stream, and keeps it for later steps.  The state is not
  * changed: ping-pong timings write only the spare buffer, in-place ones run
  * on a copy in F_B.  Every tile width gives bit-identical results.  3D
  * float64 (one tile shape) returns 64 at once.  Synchronises the stream. */
@@ -302,10 +304,12 @@ lbm_status lbm_autotune(lbm_blocks *h, int32_t reps, int32_t *tile_x);
  *   - restriction: after each coarse step every covered coarse cell takes the
  *     mean of its 8 fine cells, non-equilibrium part scaled by 1/alpha.
  * The coarse handle keeps stepping every cell; it must stream ping-pong
- * (lbm_desc.streaming = LBM_STREAMING_PINGPONG), be 3D, store float64,
- * float32 or shifted float32, have no body force and no Smagorinsky model,
- * and have tau and 2 tau - 1/2 at least 0.05 away from 1 (else
- * LBM_ENOTSUP).  While the hierarchy exists the coarse handle must only be
+ * (lbm_desc.streaming = LBM_STREAMING_PINGPONG), be 3D, have no body force
+ * and no Smagorinsky model, and have tau and 2 tau - 1/2 at least 0.05 away
+ * from 1 (else LBM_ENOTSUP).  The fine level stores its populations in the
+ * coarse handle's storage type, 16-bit shifted storages included; every
+ * kernel of the hierarchy computes in float32 for them (float64 for
+ * LBM_F64).  While the hierarchy exists the coarse handle must only be
  * stepped through lbm_hierarchy_step.
  *
  * Boxes are in coarse cells, [lo, hi) per axis, with 1 <= lo, hi <= n - 1,
@@ -335,7 +339,9 @@ lbm_status lbm_hierarchy_required_bytes(const lbm_blocks *coarse, int32_t nbox, 
  * memory of at least the required sizes.  The fine state starts as the
  * interpolation of the coarse state.  use_graph != 0 replays pairs of coarse
  * steps from a captured HIP graph (needs a non-NULL stream; with the NULL
- * stream the steps are launched one by one).  Synchronises the stream. */
+ * stream the steps are launched one by one; LBM_ENOTSUP for the stochastic
+ * rounding storages, whose random bits depend on the step index).
+ * Synchronises the stream. */
 lbm_status lbm_create_hierarchy(lbm_blocks *coarse, int32_t nbox, const lbm_box *boxes, void *const buf[LBM_NHBUF],
                                 const size_t buf_bytes[LBM_NHBUF], int32_t use_graph, lbm_hierarchy **out);
 

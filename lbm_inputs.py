@@ -155,39 +155,108 @@ def predictor_cavities(count: int, seed: int, n: int = 128, re_range=(1000.0, 50
 
 
 def place_patches(flagged, block, n, count=400, edges=(16, 24, 32, 48), seed=7, margin=1):
-    """Up to ``count`` non-overlapping cubic patch boxes for a two-level run,
+    """``count`` non-overlapping cubic patch boxes for a two-level run,
     placed where a coarse run's sensor flags refinement.  ``flagged`` is the
     boolean block mask [nbz][nby][nbx] of the coarse grid (blocks of edge
     ``block``, grid extent ``n`` = (nx, ny, nz)).  Patch k has fine edge
-    edges[r] (r from the stream ``seed``), i.e. a coarse edge of half that,
-    and is centred on a flagged block taken in a seeded order; a box that
-    would overlap an earlier one or come within ``margin`` cells of the
-    domain faces is skipped.  Returns [((lo_x, lo_y, lo_z), (hi_x, hi_y, hi_z))]
-    in coarse cells."""
-    blocks = np.argwhere(np.asarray(flagged, dtype=bool))      # (z, y, x) block indices
-    if len(blocks) == 0:
+    edges[r_k] (r_k from the stream ``seed``), i.e. a coarse edge ce of half
+    that, with its origin on a multiple of 4 coarse cells and at least
+    ``margin`` cells from the domain faces.  It goes on the flagged blocks in
+    a seeded order, starting after the block of the previous patch: on the
+    first block where a free position exists, at the free origin whose box
+    overlaps that block and whose centre lies nearest the block's centre
+    (ties: lowest z, then y, then x).  When no flagged block has room left,
+    the mask grows by one block in every direction (the buffer layer around
+    tagged cells of Sec. 5.2) and the search goes on.  Raises ValueError if
+    the grid cannot hold ``count`` boxes.  Returns
+    [((lo_x, lo_y, lo_z), (hi_x, hi_y, hi_z))] in coarse cells."""
+    flagged = np.asarray(flagged, dtype=bool)
+    if count == 0:
         return []
-    order = np.argsort(uniform(seed, len(blocks)), kind="stable")
-    pick = (uniform(seed + 1, len(blocks)) * len(edges)).astype(np.int64)
-    taken = np.zeros((n[2], n[1], n[0]), dtype=bool)
+    if not flagged.any():
+        raise ValueError("no flagged block to place patches on")
+    assert block % 4 == 0 and all(e % 8 == 0 for e in edges)
+    pick = (uniform(seed + 1, count) * len(edges)).astype(np.int64)
+    # occupancy in units of 4 coarse cells (every box is 4-aligned); a box is
+    # free when its sum over the summed-volume table is zero
+    lo4_min = (margin + 3) // 4
+    hi4_max = [(n[a] - margin) // 4 for a in range(3)]
+    occ = np.zeros((n[2] // 4 + 1, n[1] // 4 + 1, n[0] // 4 + 1), dtype=np.int32)   # [z][y][x]
+    b4 = block // 4
+
+    def table():
+        t = np.zeros(tuple(d + 1 for d in occ.shape), dtype=np.int32)
+        t[1:, 1:, 1:] = occ.cumsum(0).cumsum(1).cumsum(2)
+        return t
+
+    def box_sums(t, lo, e):            # lo: (k, 3) in x, y, z units of 4 cells
+        x0, y0, z0 = lo[:, 0], lo[:, 1], lo[:, 2]
+        x1, y1, z1 = x0 + e, y0 + e, z0 + e
+        return (t[z1, y1, x1] - t[z0, y1, x1] - t[z1, y0, x1] - t[z1, y1, x0]
+                + t[z0, y0, x1] + t[z0, y1, x0] + t[z1, y0, x0] - t[z0, y0, x0])
+
+    def candidates(b, e4):             # b: block (x, y, z); origins whose box overlaps it, nearest first
+        rng = []
+        for a in range(3):
+            lo = max(b[a] * b4 - e4 + 1, lo4_min)
+            hi = min(b[a] * b4 + b4 - 1, hi4_max[a] - e4)
+            if hi < lo:
+                return None
+            rng.append(np.arange(lo, hi + 1))
+        gz, gy, gx = np.meshgrid(rng[2], rng[1], rng[0], indexing="ij")
+        c = np.stack([gx.ravel(), gy.ravel(), gz.ravel()], axis=1)
+        centre = 2 * np.asarray(b) * b4 + b4            # twice the block centre, units of 4 cells
+        d2 = ((2 * c + e4 - centre) ** 2).sum(axis=1)
+        return c[np.lexsort((c[:, 0], c[:, 1], c[:, 2], d2))]
+
+    masks = [flagged]
+    orders, cursors, failed = [], [], [set()]
     boxes = []
-    for k, idx in enumerate(order):
-        ce = edges[pick[k]] // 2
-        bz, by, bx = (int(v) for v in blocks[idx])
-        ce = int(ce)
-        centre = (bx * block + block // 2, by * block + block // 2, bz * block + block // 2)
-        # box origins on multiples of 4 coarse cells, clamped inside the margin
-        lo_min = 4 * ((margin + 3) // 4)
-        lo = [min(max(4 * ((c - ce // 2) // 4), lo_min), 4 * ((n[a] - margin - ce) // 4))
-              for a, c in enumerate(centre)]
-        hi = [lo[a] + ce for a in range(3)]
-        if any(lo[a] < margin or hi[a] > n[a] - margin for a in range(3)):
-            continue
-        sl = (slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
-        if taken[sl].any():
-            continue
-        taken[sl] = True
-        boxes.append((tuple(lo), tuple(hi)))
-        if len(boxes) == count:
+    t = table()
+    k = 0
+    p = 0
+    while k < count:
+        if p == len(orders):
+            blocks = np.argwhere(masks[p])[:, ::-1]            # (x, y, z) block indices
+            orders.append(blocks[np.argsort(uniform(seed + 2 + p, len(blocks)), kind="stable")])
+            cursors.append(0)
+        e4 = edges[pick[k]] // 8                                # coarse edge / 4
+        order = orders[p]
+        placed = False
+        for j in range(len(order)):
+            idx = (cursors[p] + j) % len(order)
+            b = tuple(int(v) for v in order[idx])
+            if any((b, e) in failed[p] for e in range(1, e4 + 1)):
+                continue
+            c = candidates(b, e4)
+            free = None if c is None else np.flatnonzero(box_sums(t, c, e4) == 0)
+            if free is None or len(free) == 0:
+                failed[p].add((b, e4))
+                continue
+            lo = c[free[0]]
+            occ[lo[2]:lo[2] + e4, lo[1]:lo[1] + e4, lo[0]:lo[0] + e4] = 1
+            t = table()
+            boxes.append((tuple(int(4 * v) for v in lo), tuple(int(4 * (v + e4)) for v in lo)))
+            cursors[p] = (idx + 1) % len(order)
+            placed = True
             break
+        if placed:
+            k += 1
+            p = 0
+            continue
+        p += 1
+        if p == len(masks):
+            grown = masks[-1].copy()
+            for ax in range(3):                             # one block in every direction
+                g = grown.copy()
+                sl_lo = [slice(None)] * 3
+                sl_hi = [slice(None)] * 3
+                sl_lo[ax], sl_hi[ax] = slice(1, None), slice(None, -1)
+                g[tuple(sl_lo)] |= grown[tuple(sl_hi)]
+                g[tuple(sl_hi)] |= grown[tuple(sl_lo)]
+                grown = g
+            if grown.sum() == masks[-1].sum():
+                raise ValueError(f"only {len(boxes)} of {count} patches fit on the grid")
+            masks.append(grown)
+            failed.append(set())
     return boxes

@@ -29,7 +29,7 @@
  *     corner) takes the SUM of those faces' wall velocities, so that a single
  *     moving lid acts on every link that crosses it;
  *   - body force by Guo's scheme (the paper cites it for the droplet case,
- *     Sec. 4.2): rho*u = sum_i xi_i f_i + F/2 and a source term in the
+ *     Sec. 4.5): rho*u = sum_i xi_i f_i + F/2 and a source term in the
  *     collision;
  *   - second sensor form: the L2 ratio ||f^neq||_2 / ||f^eq||_2 next to the
  *     paper's mean |f^neq_i / f^eq_i|;

@@ -4,7 +4,7 @@ Run as ``python paper_1507_06767_amd/build.py`` (by path: importing the
 package would load the library being rebuilt).  The host runtime, the
 predictor kernels, one object per step-kernel instantiation (lattice x
 storage type, all from step_inst.hip) and the patch-hierarchy kernels per
-lattice (patch_inst.hip) are compiled in parallel and linked into one shared
+lattice and storage family (patch_inst.hip) are compiled in parallel and linked into one shared
 library.  Flags: -O3, C++20, no fast-math (division and
 square root stay correctly rounded), multiply-adds fused only within one
 source expression (-ffp-contract=on: kernels that spell the same arithmetic
@@ -32,7 +32,8 @@ STORAGE_TYPES = [("double", "double", "false", "f64"), ("float", "float", "false
 UNITS = [("lbm.hip", [], "lbm.o"), ("cnn.hip", [], "cnn.o")] + [
     ("step_inst.hip", [f"-DLBM_Q={q}", f"-DLBM_T={t}", f"-DLBM_C={c}", f"-DLBM_SH={sh}"], f"step_q{q}_{tag}.o")
     for q in LATTICES for t, c, sh, tag in STORAGE_TYPES] + [
-    ("patch_inst.hip", [f"-DLBM_Q={q}"], f"patch_q{q}.o") for q in (19, 27)]
+    ("patch_inst.hip", [f"-DLBM_Q={q}", f"-DLBM_PATCH_SET={ps}"], f"patch_q{q}_{ps}.o")
+    for q in (19, 27) for ps in (0, 1)]
 SOURCES = sorted({u[0] for u in UNITS})
 OUT = os.path.join(HERE, "liblbm.so")
 

@@ -8,6 +8,7 @@
 #include <stdint.h>
 
 #include "lattice.hpp"
+#include "step_kernel.hpp"
 
 namespace lbm {
 
@@ -183,9 +184,25 @@ __global__ void dilate_kernel(const int8_t *in, int8_t *out, int nbx, int nby, i
     out[i] = (int8_t)best;
 }
 
-// Per block: the largest time-averaged cell sensor, sum / samples, NaN-propagating.
+// Block maxima and flags of a row-tile sensor step from the max bits its
+// workgroups folded into the low halves of the accumulator words, which are
+// cleared for the next sensor step; the L2 sensor's square root is taken
+// here, once per block.
 template <typename C>
-__global__ void average_block_max_kernel(const C *sum, double *out, int nx, int ny, int nz, int bx, int by,
+__global__ void finish_blocks_kernel(unsigned *w32, int nblocks, bool l2, C *block_max, int8_t *flags,
+                                     double theta_r, double theta_c) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nblocks) return;
+    float M = __uint_as_float(w32[2 * b]);
+    w32[2 * b] = 0u;
+    if (l2) M = sqrtf(M);
+    block_max[b] = static_cast<C>(M);
+    flags[b] = block_flag(static_cast<double>(M), theta_r, theta_c);
+}
+
+// Per block: the largest time-averaged cell sensor, sum / samples, NaN-propagating
+// (the per-cell sums are float64).
+__global__ void average_block_max_kernel(const double *sum, double *out, int nx, int ny, int nz, int bx, int by,
                                          int bz, int nbx, int nby, int nbz, double inv_samples) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nbx * nby * nbz) return;
@@ -195,7 +212,7 @@ __global__ void average_block_max_kernel(const C *sum, double *out, int nx, int 
     for (int z = z0; z < min(z0 + bz, nz); ++z)
         for (int y = y0; y < min(y0 + by, ny); ++y)
             for (int x = x0; x < min(x0 + bx, nx); ++x) {
-                const double v = static_cast<double>(sum[((int64_t)z * ny + y) * nx + x]) * inv_samples;
+                const double v = sum[((int64_t)z * ny + y) * nx + x] * inv_samples;
                 if (!(v == v)) nan = true;
                 else if (v > m) m = v;
             }

@@ -59,8 +59,8 @@ lbm_status hier_layout(const lbm_blocks *h, int32_t nbox, const lbm_box *boxes, 
     if (nbox < 1 || !boxes) return fail(LBM_EINVAL, "need at least one box");
     const lbm_desc &d = h->d;
     if (d.lattice == LBM_D2Q9) return fail(LBM_ENOTSUP, "the hierarchy is 3D (D3Q19 or D3Q27)");
-    if (d.storage != LBM_F64 && d.storage != LBM_F32 && d.storage != LBM_F32_SHIFTED)
-        return fail(LBM_ENOTSUP, "the hierarchy supports float64, float32 and shifted float32 storage");
+    if (d.storage < LBM_F64 || d.storage > LBM_BF16_SHIFTED_SR)
+        return fail(LBM_ENOTSUP, "storage %d", d.storage);
     if (h->inplace) return fail(LBM_ENOTSUP, "the coarse handle must stream ping-pong (LBM_STREAMING_PINGPONG)");
     if (h->has_force || d.smagorinsky > 0.0)
         return fail(LBM_ENOTSUP, "the hierarchy couples plain BGK without body force");
@@ -150,8 +150,10 @@ lbm_status hier_layout(const lbm_blocks *h, int32_t nbox, const lbm_box *boxes, 
     return LBM_OK;
 }
 
+// fine_step: index of the fine step the launch belongs to (the stochastic
+// rounding key of its stores)
 template <typename C>
-PatchArgs<C> patch_args(lbm_hierarchy *H, const void *src, void *dst) {
+PatchArgs<C> patch_args(lbm_hierarchy *H, const void *src, void *dst, int64_t fine_step = 0) {
     const lbm_desc &d = H->coarse->d;
     PatchArgs<C> a{};
     a.src = src;
@@ -179,6 +181,7 @@ PatchArgs<C> patch_args(lbm_hierarchy *H, const void *src, void *dst) {
     a.theta_c = d.theta_coarsen;
     a.block_max = static_cast<C *>(H->buf[LBM_HBUF_BLOCK_MAX]);
     a.flags = static_cast<int8_t *>(H->buf[LBM_HBUF_FLAGS]);
+    a.step = (uint32_t)fine_step;
     return a;
 }
 
@@ -204,9 +207,15 @@ template <typename F>
 void with_hier_types(lbm_hierarchy *H, F &&f) {
     const int s = H->coarse->d.storage;
     auto by_q = [&]<int Q>() {
-        if (s == LBM_F64) f.template operator()<Q, double, double, false>();
-        else if (s == LBM_F32) f.template operator()<Q, float, float, false>();
-        else f.template operator()<Q, float, float, true>();
+        switch (s) {
+            case LBM_F64: f.template operator()<Q, double, double, false>(); break;
+            case LBM_F32: f.template operator()<Q, float, float, false>(); break;
+            case LBM_F16_SHIFTED: f.template operator()<Q, _Float16, float, true>(); break;
+            case LBM_BF16_SHIFTED: f.template operator()<Q, __bf16, float, true>(); break;
+            case LBM_F16_SHIFTED_SR: f.template operator()<Q, half_sr, float, true>(); break;
+            case LBM_BF16_SHIFTED_SR: f.template operator()<Q, bf16_sr, float, true>(); break;
+            default: f.template operator()<Q, float, float, true>(); break;
+        }
     };
     if (H->q == 19) by_q.template operator()<19>();
     else by_q.template operator()<27>();
@@ -266,10 +275,11 @@ hipError_t upload_tiles(lbm_hierarchy *H) {
 
 // A fine step over all patches; with `restrict_out` (the coarse state being
 // completed) it also restricts every covered coarse cell to it.
-void hier_fine_step(lbm_hierarchy *H, const void *src, void *dst, bool sensor, void *restrict_out = nullptr) {
+void hier_fine_step(lbm_hierarchy *H, const void *src, void *dst, bool sensor, int64_t fine_step,
+                    void *restrict_out = nullptr) {
     with_hier_types(H, [&]<int Q, typename T, typename C, bool SH>() {
         PatchLaunch l{H->coarse->stream, sensor, H->coarse->d.sensor_kind, restrict_out != nullptr, H->nwg};
-        launch_patch_step<Q, T, C, SH>(patch_args<C>(H, src, dst),
+        launch_patch_step<Q, T, C, SH>(patch_args<C>(H, src, dst, fine_step),
                                        coarse_view<C>(H, restrict_out, restrict_out, 0.0, restrict_out), l);
     });
 }
@@ -281,9 +291,10 @@ bool restriction_fused() {
     return !(s && std::string(s) == "separate");
 }
 
-void hier_ghosts(lbm_hierarchy *H, void *state, const void *s0, const void *s1, double w1) {
+void hier_ghosts(lbm_hierarchy *H, void *state, const void *s0, const void *s1, double w1, int64_t fine_step) {
     with_hier_types(H, [&]<int Q, typename T, typename C, bool SH>() {
-        launch_patch_ghosts<Q, T, C, SH>(patch_args<C>(H, state, state), coarse_view<C>(H, s0, s1, w1, nullptr),
+        launch_patch_ghosts<Q, T, C, SH>(patch_args<C>(H, state, state, fine_step),
+                                         coarse_view<C>(H, s0, s1, w1, nullptr),
                                          state, patch_lists(H), H->coarse->stream);
     });
 }
@@ -300,10 +311,11 @@ void hier_coarse_step(lbm_hierarchy *H, bool sens, hipEvent_t *ev = nullptr) {
     void *X = state_ptr(h);
     void *Y = h->d.buf[h->cur ? LBM_BUF_F_A : LBM_BUF_F_B];
     void *A = fine_buf(H, H->cur), *B = fine_buf(H, H->cur ^ 1);
+    const int64_t f1 = 2 * H->step + 1, f2 = f1 + 1;   // fine steps of this coarse step
     mark(0);
-    hier_ghosts(H, A, X, X, 0.0);
+    hier_ghosts(H, A, X, X, 0.0, f1);
     mark(1);
-    hier_fine_step(H, A, B, false);
+    hier_fine_step(H, A, B, false, f1);
     mark(2);
     const int64_t step = h->step + 1;
     launch_step_any(h, sens);
@@ -311,14 +323,14 @@ void hier_coarse_step(lbm_hierarchy *H, bool sens, hipEvent_t *ev = nullptr) {
     h->cur ^= 1;
     h->step = step;
     if (sens) h->last_sensor_step = step;
-    hier_ghosts(H, B, X, Y, 0.5);
+    hier_ghosts(H, B, X, Y, 0.5, f2);
     mark(4);
     const bool fused = restriction_fused();
-    hier_fine_step(H, B, A, sens, fused ? Y : nullptr);
+    hier_fine_step(H, B, A, sens, f2, fused ? Y : nullptr);
     mark(5);
     if (!fused)
         with_hier_types(H, [&]<int Q, typename T, typename C, bool SH>() {
-            launch_patch_restrict<Q, T, C, SH>(patch_args<C>(H, A, A), coarse_view<C>(H, Y, Y, 0.0, Y), A,
+            launch_patch_restrict<Q, T, C, SH>(patch_args<C>(H, A, A, f2), coarse_view<C>(H, Y, Y, 0.0, Y), A,
                                                patch_lists(H), h->stream);
         });
     mark(6);
@@ -391,6 +403,11 @@ lbm_status lbm_create_hierarchy(lbm_blocks *coarse, int32_t nbox, const lbm_box 
     H->cur = 0;
     build_tiles(H, 32);
     H->nwg = (int)std::min<int64_t>(H->ntiles, 8 * kHierCUs);
+    const bool sr = coarse->d.storage == LBM_F16_SHIFTED_SR || coarse->d.storage == LBM_BF16_SHIFTED_SR;
+    if (use_graph != 0 && sr) {
+        delete H;
+        return fail(LBM_ENOTSUP, "stochastic rounding keys on the step index: no graph replay");
+    }
     H->use_graph = use_graph != 0 && coarse->stream != nullptr;
     H->graph[0] = H->graph[1] = nullptr;
     H->step = 0;
@@ -667,9 +684,9 @@ lbm_status lbm_hierarchy_autotune(lbm_hierarchy *H, int32_t reps, int32_t *tile_
         if (e != hipSuccess) break;
         for (int pc : per_cu) {
             H->nwg = (int)std::min<int64_t>(H->ntiles, (int64_t)pc * kHierCUs);
-            hier_fine_step(H, src, dst, false);   // warm-up
+            hier_fine_step(H, src, dst, false, 0);   // warm-up
             e = hipEventRecord(e0, s);
-            for (int r = 0; r < reps && e == hipSuccess; ++r) hier_fine_step(H, src, dst, false);
+            for (int r = 0; r < reps && e == hipSuccess; ++r) hier_fine_step(H, src, dst, false, 0);
             if (e == hipSuccess) e = hipEventRecord(e1, s);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.0f;

@@ -14,7 +14,8 @@ namespace lbm {
 
 struct LaunchCfg {
     hipStream_t stream;
-    int tile_x;        // 32, 64 or 128 (step_zmarch: 64)
+    int tile_x;        // 32, 64 or 128 cells x 8 rows; kRowTileX: one row, 3D ping-pong
+                       // only (step_zmarch: 64)
     int scheme;        // kPingPong, kStream or kLocal
     bool sensor;       // evaluate sensor, block maxima and flags in this step
     int sensor_kind;   // kSensorL2 or kSensorKKn
@@ -37,9 +38,10 @@ void launch_step_kernel(const StepArgs<C> &a, const LaunchCfg &c);
 #ifdef LBM_LAUNCH_DEFINITIONS
 template <bool ZM, int Q, typename T, typename C, bool SH, bool SENS, int SK, int MODEL, int BX, int SCH>
 void launch_one(hipStream_t st, const StepArgs<C> &a) {
-    const dim3 g(a.ntiles), b(BX, kTileY);
+    constexpr int TY = (BX == kRowTileX) ? 1 : kTileY;
+    const dim3 g(a.ntiles), b(BX, TY);
     if constexpr (ZM) hipLaunchKernelGGL((step_zmarch<Q, T, C, SH, SENS, SK, MODEL, BX>), g, b, 0, st, a);
-    else hipLaunchKernelGGL((step_cells<Q, T, C, SH, SENS, SK, MODEL, BX, SCH>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((step_cells<Q, T, C, SH, SENS, SK, MODEL, BX, SCH, TY>), g, b, 0, st, a);
 }
 
 template <bool ZM, int Q, typename T, typename C, bool SH, bool SENS, int SK, int BX, int SCH>
@@ -74,6 +76,8 @@ template <int Q, typename T, typename C, bool SH>
 void launch_step_kernel(const StepArgs<C> &a, const LaunchCfg &c) {
     if constexpr (uses_zmarch<Q, C>()) {
         launch_sk<true, Q, T, C, SH, 64, kPingPong>(a, c);
+    } else if (Lattice<Q>::D == 3 && c.tile_x == kRowTileX && c.scheme == kPingPong) {
+        if constexpr (Lattice<Q>::D == 3) launch_sk<false, Q, T, C, SH, kRowTileX, kPingPong>(a, c);
     } else {
         switch (c.tile_x) {
             case 32: launch_scheme<Q, T, C, SH, 32>(a, c); break;

@@ -52,19 +52,29 @@ constexpr size_t kAlign = 256;
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Tile width: the narrowest of 32, 64, 128 that spans the grid's x extent,
-// capped at 64 for the in-place scheme and 128 for ping-pong (measured best:
-// 64 for the in-place 128^3 cavity, 128 for the ping-pong 256^3 one).
-// LBM_TILE_X (32, 64 or 128) overrides it for tuning.
-int tile_x_setting(int nx, bool inplace) {
+// capped at 64 for the in-place scheme (measured best on the 128^3 cavity,
+// whose state stays in the Infinity Cache); 3D ping-pong grids wider than 128
+// cells take row tiles (kRowTileX cells of one row, natural dispatch order),
+// which stream a state too large for that cache faster than 128 x 8 tiles in
+// XCD runs (256^3: 73% against 68% of the HBM peak for the bare access
+// pattern).  LBM_TILE_X (32, 64, 128, or 256 for row tiles) overrides it for
+// tuning; row tiles are only taken by 3D ping-pong.
+int tile_x_setting(int nx, bool inplace, int dim) {
+    const bool rows_ok = !inplace && dim == 3;
     const char *s = std::getenv("LBM_TILE_X");
     if (s) {
         int v = std::atoi(s);
         if (v == 32 || v == 64 || v == 128) return v;
+        if (v == kRowTileX) return rows_ok ? v : 128;
     }
+    if (rows_ok && nx > 128) return kRowTileX;
     const int cap = inplace ? 64 : 128;
     const int fit = nx <= 32 ? 32 : (nx <= 64 ? 64 : 128);
     return fit < cap ? fit : cap;
 }
+
+// Rows of a tile of width tile_x.
+int tile_rows(int tile_x) { return tile_x == kRowTileX ? 1 : kTileY; }
 
 size_t plane_pad_setting() {
     const char *s = std::getenv("LBM_PLANE_PAD");
@@ -86,7 +96,7 @@ struct Layout {
     size_t bytes[LBM_NBUF];
     size_t acc_off;       // per-block accumulator words inside BLOCK_MAX
     size_t staging_off, partial_off, out_off;
-    size_t avg_off;       // per-cell running sensor sums (time average)
+    size_t avg_off;       // per-cell running sensor sums in float64 (time average)
     size_t lev_off;       // two per-block int8 level arrays
     size_t avgmax_off;    // per-block float64 maxima of the averaged sensor
     size_t means_off;     // per-block float64 means of (rho - rho0, u)
@@ -168,7 +178,7 @@ lbm_status check_desc(const lbm_desc *d, Layout *L) {
     L->partial_off = round_up((size_t)cells * 8 * 4, kAlign);
     L->out_off = L->partial_off + round_up((size_t)kMaxPartials * 4 * 8, kAlign);
     L->avg_off = L->out_off + kAlign;
-    L->lev_off = L->avg_off + round_up((size_t)cells * L->cbytes, kAlign);
+    L->lev_off = L->avg_off + round_up((size_t)cells * 8, kAlign);
     L->avgmax_off = L->lev_off + round_up((size_t)L->nblocks * 2, kAlign);
     L->means_off = L->avgmax_off + round_up((size_t)L->nblocks * 8, kAlign);
     L->bytes[LBM_BUF_SCRATCH] = L->means_off + round_up((size_t)L->nblocks * 4 * 8, kAlign);
@@ -283,7 +293,7 @@ StepArgs<C> step_args(lbm_blocks *h, const void *src, void *dst, bool zmarch, in
     a.ny = d.extent[1];
     a.nz = d.extent[2];
     a.ntx = (a.nx + tile_x - 1) / tile_x;
-    a.nty = (a.ny + kTileY - 1) / kTileY;
+    a.nty = (a.ny + tile_rows(tile_x) - 1) / tile_rows(tile_x);
     const int ntz = zmarch ? (a.nz + BZ - 1) / BZ : a.nz;
     a.ntiles = a.ntx * a.nty * ntz;
     a.nbx = h->L.nb[0];
@@ -310,7 +320,7 @@ StepArgs<C> step_args(lbm_blocks *h, const void *src, void *dst, bool zmarch, in
     a.theta_r = d.theta_refine;
     a.theta_c = d.theta_coarsen;
     a.step = (uint32_t)(h->step + 1);
-    a.avg = h->averaging ? reinterpret_cast<C *>(static_cast<char *>(d.buf[LBM_BUF_SCRATCH]) + h->L.avg_off)
+    a.avg = h->averaging ? reinterpret_cast<double *>(static_cast<char *>(d.buf[LBM_BUF_SCRATCH]) + h->L.avg_off)
                          : nullptr;
     a.block_max = static_cast<C *>(d.buf[LBM_BUF_BLOCK_MAX]);
     a.flags = static_cast<int8_t *>(d.buf[LBM_BUF_FLAGS]);
@@ -350,6 +360,20 @@ void reset_accumulators(lbm_blocks *h) {
                        acc, (int)h->L.nblocks);
 }
 
+// Row tiles leave a sensor step's block maxima as max bits in the
+// accumulator words: the block maxima and flags are written from them right
+// after the step (and the words cleared).
+void finish_blocks(lbm_blocks *h) {
+    auto *w32 = reinterpret_cast<unsigned *>(static_cast<char *>(h->d.buf[LBM_BUF_BLOCK_MAX]) + h->L.acc_off);
+    const bool l2 = h->d.sensor_kind == LBM_SENSOR_L2;
+    auto *fl = static_cast<int8_t *>(h->d.buf[LBM_BUF_FLAGS]);
+    const unsigned g = grid_for(h->L.nblocks);
+    // float storages only: 3D float64 steps with the z-march kernel
+    hipLaunchKernelGGL(finish_blocks_kernel<float>, dim3(g), dim3(kAuxThreads), 0, h->stream, w32,
+                       (int)h->L.nblocks, l2, static_cast<float *>(h->d.buf[LBM_BUF_BLOCK_MAX]), fl,
+                       h->d.theta_refine, h->d.theta_coarsen);
+}
+
 template <int Q, typename T, typename C, bool SH>
 void launch_step(lbm_blocks *h, bool sens) {
     void *src = state_ptr(h);
@@ -365,6 +389,7 @@ void launch_step(lbm_blocks *h, bool sens) {
     c.tile_x = zm ? 64 : h->tile_x;
     const StepArgs<C> a = step_args<Q, C>(h, src, dst, zm, c.tile_x);
     launch_step_kernel<Q, T, C, SH>(a, c);
+    if (sens && c.tile_x == kRowTileX && c.scheme == kPingPong) finish_blocks(h);
 }
 
 // Where host data and initial states are written: the state buffer for
@@ -519,7 +544,8 @@ lbm_status lbm_create_blocks(const lbm_desc *d, const double *f0_host, lbm_block
     h->L = L;
     h->stream = static_cast<hipStream_t>(d->stream);
     h->inplace = inplace_setting(d, L);
-    h->tile_x = tile_x_setting(d->extent[0], h->inplace);
+    // 3D float64 has one tile shape (the z-march kernel, 64 x 8)
+    h->tile_x = (L.dim == 3 && d->storage == LBM_F64) ? 64 : tile_x_setting(d->extent[0], h->inplace, L.dim);
     h->phase = 0;
     h->cur = 0;
     h->step = 0;
@@ -655,7 +681,7 @@ lbm_status lbm_sensor_levels(lbm_blocks *h, double a, double b, int32_t lmin, in
 lbm_status lbm_sensor_average_begin(lbm_blocks *h) {
     lbm_status st = check_handle(h);
     if (st != LBM_OK) return st;
-    const size_t bytes = (size_t)h->L.cells * h->L.cbytes;
+    const size_t bytes = (size_t)h->L.cells * 8;
     char *p = static_cast<char *>(h->d.buf[LBM_BUF_SCRATCH]) + h->L.avg_off;
     // cleared with a kernel (no memset node if the caller captures the stream)
     hipLaunchKernelGGL(zero_words_kernel, dim3(grid_for((int64_t)(bytes / 8))), dim3(kAuxThreads), 0,
@@ -681,14 +707,9 @@ lbm_status lbm_sensor_average(lbm_blocks *h, double *block_max_host, int64_t *sa
     double *out = reinterpret_cast<double *>(static_cast<char *>(h->d.buf[LBM_BUF_SCRATCH]) + h->L.avgmax_off);
     const double inv = 1.0 / (double)h->avg_samples;
     const lbm_desc &d = h->d;
-    if (h->L.cbytes == 8)
-        hipLaunchKernelGGL(average_block_max_kernel<double>, dim3(grid_for(nb)), dim3(kAuxThreads), 0, h->stream,
-                           reinterpret_cast<const double *>(scr + h->L.avg_off), out, d.extent[0], d.extent[1],
-                           d.extent[2], kBlockEdge, kBlockEdge, bz, h->L.nb[0], h->L.nb[1], h->L.nb[2], inv);
-    else
-        hipLaunchKernelGGL(average_block_max_kernel<float>, dim3(grid_for(nb)), dim3(kAuxThreads), 0, h->stream,
-                           reinterpret_cast<const float *>(scr + h->L.avg_off), out, d.extent[0], d.extent[1],
-                           d.extent[2], kBlockEdge, kBlockEdge, bz, h->L.nb[0], h->L.nb[1], h->L.nb[2], inv);
+    hipLaunchKernelGGL(average_block_max_kernel, dim3(grid_for(nb)), dim3(kAuxThreads), 0, h->stream,
+                       reinterpret_cast<const double *>(scr + h->L.avg_off), out, d.extent[0], d.extent[1],
+                       d.extent[2], kBlockEdge, kBlockEdge, bz, h->L.nb[0], h->L.nb[1], h->L.nb[2], inv);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(block_max_host, out, nb * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -929,7 +950,9 @@ lbm_status lbm_autotune(lbm_blocks *h, int32_t reps, int32_t *tile_x) {
     float best = 1e30f;
     int best_tile = saved_tile;
     hipError_t e = hipSuccess;
-    for (int tx : {32, 64, 128}) {
+    const bool rows_ok = !h->inplace && h->L.dim == 3;
+    for (int tx : {32, 64, 128, kRowTileX}) {
+        if (tx == kRowTileX && !rows_ok) continue;
         h->tile_x = tx;
         auto one = [&]() {
             launch_step_any(h, false);

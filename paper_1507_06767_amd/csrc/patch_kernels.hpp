@@ -83,7 +83,25 @@ struct PatchArgs {
     double theta_r, theta_c;
     C *block_max;             // [nblocks] (finished sensor values)
     int8_t *flags;            // [nblocks]
+    uint32_t step;            // fine step index: the key of stochastic rounding on store
 };
+
+// Stored representation of storage policy T (see Storage in step_kernel.hpp).
+template <typename T>
+using raw_t = typename Storage<T>::raw;
+
+// Stochastic-rounding keys of the hierarchy's stores: cell_key of a cell
+// index and a step, the index xor-ed with a salt per kind of store so that
+// the fine step, the ghost fill, the restriction and the initial fill draw
+// different bits from the coarse step kernel's (whose indices are coarse
+// cells) and from each other.
+constexpr uint32_t kSaltFine = 0x40000000u, kSaltGhost = 0x80000000u, kSaltRestrict = 0xC0000000u,
+                   kSaltInit = 0x20000000u;
+
+template <typename T>
+__device__ __forceinline__ uint32_t sr_cell_key(uint32_t cell, uint32_t salt, uint32_t step) {
+    return Storage<T>::sr ? cell_key(cell ^ salt, step) : 0u;
+}
 
 // Coarse-level view used by the ghost fill and the restriction.
 template <typename C>
@@ -135,13 +153,17 @@ __device__ __forceinline__ C deq_of(const Moments<Q, C> &m, C rho0) {
 
 template <typename T, typename C>
 __device__ __forceinline__ C load_dev(const void *buf, int64_t idx, C shift, bool shifted) {
-    const C v = static_cast<C>(static_cast<const T *>(buf)[idx]);
+    const C v = static_cast<C>(static_cast<const raw_t<T> *>(buf)[idx]);
     return shifted ? v : v - shift;
 }
 
+// Store of the deviation d (shift added back for unshifted storage) with the
+// rounding of policy T; ckey is the cell's stochastic-rounding key.
 template <typename T, typename C>
-__device__ __forceinline__ void store_dev(void *buf, int64_t idx, C d, C shift, bool shifted) {
-    static_cast<T *>(buf)[idx] = static_cast<T>(shifted ? d : d + shift);
+__device__ __forceinline__ void store_dev(void *buf, int64_t idx, C d, C shift, bool shifted, uint32_t ckey,
+                                          int pop) {
+    static_cast<raw_t<T> *>(buf)[idx] =
+        to_storage<T>(shifted ? d : d + shift, Storage<T>::sr ? round_key(ckey, pop) : 0u);
 }
 
 // Element of population i of ghost entry g: its slot in the padded rows, or
@@ -182,9 +204,10 @@ __global__ __launch_bounds__(512) void patch_step(const PatchArgs<C> a, const Co
     constexpr int kCoarsePerTile = 256;
     __shared__ C racc[RESTRICT ? Q * kCoarsePerTile : 1];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    using R = raw_t<T>;
     const char *src = static_cast<const char *>(a.src);
     char *dst = static_cast<char *>(a.dst);
-    const int64_t plane_bytes = a.pitch * (int64_t)sizeof(T);
+    const int64_t plane_bytes = a.pitch * (int64_t)sizeof(R);
     // Workgroups are dealt to the 8 XCDs round-robin by id.  With at least 8
     // workgroups, XCD j works through the j-th eighth of the tile list (tiles
     // are listed x fastest, patch by patch), so that tiles sharing halo lines
@@ -208,13 +231,13 @@ __global__ __launch_bounds__(512) void patch_step(const PatchArgs<C> a, const Co
         // lines instead of lines with a 4-byte hole at each row end
         const bool xlo = tl.x0 + x == 0, xhi = tl.x0 + x == p.e[0] - 1;
         const bool xedge = xlo || xhi;
-        const int xoff = xlo ? -(int)sizeof(T) : (int)sizeof(T);
+        const int xoff = xlo ? -(int)sizeof(R) : (int)sizeof(R);
         // the first and last cell of a row pull their x-face ghosts from the
         // compact x-face arrays: element (z + 1) P1 + (y + 1) of the low or
         // high side, minus the population's (y, z) offset
         const int P1 = p.e[1] + 2;
         const int64_t xg_side = (int64_t)P1 * (p.e[2] + 2);
-        const T *xg0 = static_cast<const T *>(a.src) + a.xg_base + p.xoff + (xhi ? xg_side : 0) + (tl.y0 + y + 1);
+        const R *xg0 = static_cast<const R *>(a.src) + a.xg_base + p.xoff + (xhi ? xg_side : 0) + (tl.y0 + y + 1);
         C m = C(0);
         if constexpr (RESTRICT) {
             for (int r = t; r < Q * kCoarsePerTile; r += 512) racc[r] = C(0);
@@ -223,9 +246,10 @@ __global__ __launch_bounds__(512) void patch_step(const PatchArgs<C> a, const Co
 #pragma unroll 1
         for (int zz = t / (8 * W); zz < 8; zz += zstep) {
             // padded cell index (< 2^29, checked on the host) as a byte offset
-            const T *xgc = xg0 + (int64_t)(tl.z0 + zz + 1) * P1;
-            const uint32_t cb = (uint32_t)(p.off + (tl.z0 + zz + 1) * sz + (tl.y0 + y + 1) * sy + (tl.x0 + x + 1)) *
-                                (uint32_t)sizeof(T);
+            const R *xgc = xg0 + (int64_t)(tl.z0 + zz + 1) * P1;
+            const uint32_t cidx = (uint32_t)(p.off + (tl.z0 + zz + 1) * sz + (tl.y0 + y + 1) * sy + (tl.x0 + x + 1));
+            const uint32_t cb = cidx * (uint32_t)sizeof(R);
+            const uint32_t ckey = sr_cell_key<T>(cidx, kSaltFine, a.step);
             const int rslot = ((zz >> 1) * 4 + (y >> 1)) * (W >> 1) + (x >> 1);
             (void)rslot;
             C d[Q];
@@ -233,8 +257,8 @@ __global__ __launch_bounds__(512) void patch_step(const PatchArgs<C> a, const Co
                 constexpr int i = decltype(ic)::value;
                 using V = Vel<Q, i>;
                 const int64_t delta = V::x + (int64_t)V::y * sy + (int64_t)V::z * sz;
-                const char *base = src + i * plane_bytes - delta * (int64_t)sizeof(T);
-                const T *from = reinterpret_cast<const T *>(base + cb);
+                const char *base = src + i * plane_bytes - delta * (int64_t)sizeof(R);
+                const R *from = reinterpret_cast<const R *>(base + cb);
                 if constexpr (V::x > 0) {
                     if (xlo) from = xgc + (i * a.xg_pitch - (V::z * P1 + V::y));
                 } else if constexpr (V::x < 0) {
@@ -265,9 +289,9 @@ __global__ __launch_bounds__(512) void patch_step(const PatchArgs<C> a, const Co
                 }
                 C out = d[i] - a.omega * fneq;
                 if constexpr (!SH) out += a.shift[i];
-                const T stored = static_cast<T>(out);
-                *reinterpret_cast<T *>(dst + i * plane_bytes + cb) = stored;
-                if (xedge) *reinterpret_cast<T *>(dst + i * plane_bytes + cb + xoff) = stored;
+                const R stored = to_storage<T>(out, Storage<T>::sr ? round_key(ckey, i) : 0u);
+                *reinterpret_cast<R *>(dst + i * plane_bytes + cb) = stored;
+                if (xedge) *reinterpret_cast<R *>(dst + i * plane_bytes + cb + xoff) = stored;
                 if constexpr (RESTRICT) {
                     // the value the level below reads back, summed over the x pair
                     // (lanes t, t^1) and the y pair (lanes t, t^W) in a fixed order;
@@ -311,10 +335,11 @@ __global__ __launch_bounds__(512) void patch_step(const PatchArgs<C> a, const Co
                 });
                 const Moments<Q, C> mo = moments_of<Q>(dr, a.rho0);
                 const C inv_alpha = C(1) / v.alpha;
+                const uint32_t rkey = sr_cell_key<T>((uint32_t)cc, kSaltRestrict, a.step);
                 static_for<0, Q>([&](auto ic) {
                     constexpr int i = decltype(ic)::value;
                     const C deq = deq_of<Q, i>(mo, a.rho0);
-                    store_dev<T>(v.out, i * v.pitch + cc, deq + inv_alpha * (dr[i] - deq), a.shift[i], SH);
+                    store_dev<T>(v.out, i * v.pitch + cc, deq + inv_alpha * (dr[i] - deq), a.shift[i], SH, rkey, i);
                 });
             }
             __syncthreads();   // the next tile zeroes racc
@@ -394,7 +419,8 @@ __global__ __launch_bounds__(256) void patch_ghosts(const PatchArgs<C> a, const 
         static_for<0, Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             if ((need >> i) & 1u)
-                static_cast<T *>(state)[ghost_index(a, need, i, g)] = static_cast<const T *>(state)[i * a.pitch + src];
+                static_cast<raw_t<T> *>(state)[ghost_index(a, need, i, g)] =
+                    static_cast<const raw_t<T> *>(state)[i * a.pitch + src];
         });
         return;
     }
@@ -405,9 +431,10 @@ __global__ __launch_bounds__(256) void patch_ghosts(const PatchArgs<C> a, const 
     const C fz = (code >> 31) & 1u ? C(0.75) : C(0.25);
     C d[Q];
     coarse_to_fine<Q, T, C, SH>(v, a.shift, a.rho0, C(x0) + fx, C(y0) + fy, C(z0) + fz, d);
+    const uint32_t gkey = sr_cell_key<T>((uint32_t)k, kSaltGhost, a.step);
     static_for<0, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        if ((need >> i) & 1u) store_dev<T>(state, ghost_index(a, need, i, g), d[i], a.shift[i], SH);
+        if ((need >> i) & 1u) store_dev<T>(state, ghost_index(a, need, i, g), d[i], a.shift[i], SH, gkey, i);
     });
 }
 
@@ -447,7 +474,8 @@ __global__ __launch_bounds__(256) void patch_ghosts_lds(const PatchArgs<C> a, co
         static_for<0, Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             if ((need >> i) & 1u)
-                static_cast<T *>(state)[ghost_index(a, need, i, g)] = static_cast<const T *>(state)[i * a.pitch + src];
+                static_cast<raw_t<T> *>(state)[ghost_index(a, need, i, g)] =
+                    static_cast<const raw_t<T> *>(state)[i * a.pitch + src];
         });
         return;
     }
@@ -468,10 +496,12 @@ __global__ __launch_bounds__(256) void patch_ghosts_lds(const PatchArgs<C> a, co
         });
     }
     const Moments<Q, C> mo = moments_of<Q>(d, a.rho0);
+    const uint32_t gkey = sr_cell_key<T>((uint32_t)k, kSaltGhost, a.step);
     static_for<0, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         const C deq = deq_of<Q, i>(mo, a.rho0);
-        if ((need >> i) & 1u) store_dev<T>(state, ghost_index(a, need, i, g), deq + v.alpha * (d[i] - deq), a.shift[i], SH);
+        if ((need >> i) & 1u)
+            store_dev<T>(state, ghost_index(a, need, i, g), deq + v.alpha * (d[i] - deq), a.shift[i], SH, gkey, i);
     });
 }
 
@@ -496,9 +526,10 @@ __global__ __launch_bounds__(256) void patch_init(const PatchArgs<C> a, const Co
     C d[Q];
     coarse_to_fine<Q, T, C, SH>(v, a.shift, a.rho0, C(0.5) * C(gx) - C(0.25), C(0.5) * C(gy) - C(0.25),
                                 C(0.5) * C(gz) - C(0.25), d);
+    const uint32_t ikey = sr_cell_key<T>((uint32_t)g, kSaltInit, a.step);
     static_for<0, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        store_dev<T>(state, i * a.pitch + g, d[i], a.shift[i], SH);
+        store_dev<T>(state, i * a.pitch + g, d[i], a.shift[i], SH, ikey, i);
     });
 }
 
@@ -529,10 +560,11 @@ __global__ __launch_bounds__(256) void patch_restrict(const PatchArgs<C> a, cons
     const Moments<Q, C> mo = moments_of<Q>(d, a.rho0);
     const int64_t cc = rc[t];
     const C inv_alpha = C(1) / v.alpha;
+    const uint32_t rkey = sr_cell_key<T>((uint32_t)cc, kSaltRestrict, a.step);
     static_for<0, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         const C deq = deq_of<Q, i>(mo, a.rho0);
-        store_dev<T>(v.out, i * v.pitch + cc, deq + inv_alpha * (d[i] - deq), a.shift[i], SH);
+        store_dev<T>(v.out, i * v.pitch + cc, deq + inv_alpha * (d[i] - deq), a.shift[i], SH, rkey, i);
     });
 }
 
@@ -551,7 +583,7 @@ __global__ __launch_bounds__(256) void patch_macros(const PatchArgs<C> a, const 
     static_for<0, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         using V = Vel<Q, i>;
-        const double s = static_cast<double>(static_cast<const T *>(state)[i * a.pitch + c]);
+        const double s = static_cast<double>(static_cast<const raw_t<T> *>(state)[i * a.pitch + c]);
         const double f = SH ? s + static_cast<double>(V::w) * static_cast<double>(a.rho0) : s;
         if (f_out) f_out[i * n + t] = f;
         r += f;

@@ -71,6 +71,7 @@ namespace lbm {
 
 constexpr int kBlockEdge = 8;       // sensor block edge along every active axis
 constexpr int kTileY = 8;           // rows per workgroup (one block row)
+constexpr int kRowTileX = 256;      // row tiles: 256 cells of one grid row per workgroup
 constexpr int kSensorL2 = 0;
 constexpr int kSensorKKn = 1;
 constexpr int kPingPong = 0;   // streaming schemes, see above
@@ -99,10 +100,11 @@ struct StepArgs {
     C F[3];                 // body-force density
     double theta_r, theta_c;
     uint32_t step;          // index of the step this launch computes (stochastic rounding key)
-    C *avg;                 // per-cell running sums of the sensor (time average); nullptr: off
+    double *avg;            // per-cell running sums of the sensor in float64 (time average); nullptr: off
     C *block_max;           // [nbz][nby][nbx]
     int8_t *flags;          // [nbz][nby][nbx]
-    unsigned long long *acc;  // per block (count << 32 | max bits), zero between sensor steps
+    unsigned long long *acc;  // per block (count << 32 | max bits), zero between steps; row tiles
+                              // fold max bits into its low 32-bit half
 };
 
 // Workgroups are dealt to the 8 XCDs round-robin by workgroup id.  Renumber
@@ -554,22 +556,24 @@ __device__ __forceinline__ C collide_store(const StepArgs<C> &a, const Geo<C> &g
     return C(0);
 }
 
+// Refine / keep / coarsen decision of a block maximum (non-finite: 2).
+__host__ __device__ __forceinline__ int8_t block_flag(double Md, double theta_r, double theta_c) {
+    if (!(Md == Md) || Md == HUGE_VAL) return 2;
+    if (Md > theta_r) return 1;
+    if (Md < theta_c) return -1;
+    return 0;
+}
+
 template <typename C>
 __device__ __forceinline__ void write_block(const StepArgs<C> &a, int b, C M) {
     a.block_max[b] = M;
-    const double Md = static_cast<double>(M);
-    int8_t fl;
-    if (!(Md == Md) || Md == HUGE_VAL) fl = 2;
-    else if (Md > a.theta_r) fl = 1;
-    else if (Md < a.theta_c) fl = -1;
-    else fl = 0;
-    a.flags[b] = fl;
+    a.flags[b] = block_flag(static_cast<double>(M), a.theta_r, a.theta_c);
 }
 
 // In-workgroup part of the block maximum: lanes 8k..8k+7 of a row hold one
 // block column; returns, for threads (tx < BX/8, ty == 0), the maximum over
-// the workgroup's 8 rows of block column tx.
-template <int BX, typename C>
+// the workgroup's TY rows of block column tx.
+template <int BX, int TY, typename C>
 __device__ __forceinline__ C tile_block_max(C m) {
     if constexpr (sizeof(C) == 4) {
         // Sensor values are >= 0, +inf or NaN, so the unsigned order of their
@@ -586,14 +590,14 @@ __device__ __forceinline__ C tile_block_max(C m) {
         m = nan_max(m, static_cast<C>(__shfl_xor(m, 2)));
         m = nan_max(m, static_cast<C>(__shfl_xor(m, 4)));
     }
-    __shared__ C red[kTileY][BX / kBlockEdge];
+    __shared__ C red[TY][BX / kBlockEdge];
     if ((threadIdx.x & (kBlockEdge - 1)) == 0) red[threadIdx.y][threadIdx.x / kBlockEdge] = m;
     __syncthreads();
     C M = C(0);
     if (threadIdx.y == 0 && threadIdx.x < BX / kBlockEdge) {
         M = red[0][threadIdx.x];
 #pragma unroll
-        for (int r = 1; r < kTileY; ++r) M = nan_max(M, red[r][threadIdx.x]);
+        for (int r = 1; r < TY; ++r) M = nan_max(M, red[r][threadIdx.x]);
     }
     return M;
 }
@@ -605,25 +609,39 @@ __device__ __forceinline__ C finish(C M) {
 }
 
 // Time average of the cell sensor (the averaged sensor of Sec. 5.1): adds the
-// cell's sensor value to its running sum when averaging is switched on.
+// cell's sensor value to its running sum when averaging is switched on.  The
+// sums are float64 whatever the arithmetic type: over windows of 10^4 sensor
+// steps a float32 sum would lose ~10^4 half-ulps, far above the sensor's own
+// float32 error.
 template <int SKIND, typename C>
 __device__ __forceinline__ void accumulate(const StepArgs<C> &a, uint32_t cell, C s) {
-    if (a.avg) a.avg[cell] += finish<SKIND>(s);
+    if (a.avg) a.avg[cell] += static_cast<double>(finish<SKIND>(s));
 }
 
-template <int Q, typename T, typename C, bool SHIFTED, bool SENSOR, int SKIND, int MODEL, int BX, int SCHEME>
-__global__ __launch_bounds__(BX *kTileY) void step_cells(const StepArgs<C> a) {
+// Tiles of BX x TY cells of one z-slice.  TY = 8 (one block row) is dealt to
+// the XCDs in contiguous runs (xcd_tile), which keeps the lines shared by
+// x-neighbouring tiles in one L2: the better order while the state fits the
+// Infinity Cache.  TY = 1 (row tiles, 3D ping-pong only) takes the natural
+// order instead, so that the whole chip streams through one compact window
+// of every population plane: measured on a 256^3 float32 state (2.5 GB per
+// step), the plain pull pattern runs at 73% of the HBM peak with row tiles
+// in natural order and at 68% with 128 x 8 tiles in XCD runs.  Row tiles
+// complete a block maximum across 8 rows x 8 slices of workgroups.
+template <int Q, typename T, typename C, bool SHIFTED, bool SENSOR, int SKIND, int MODEL, int BX, int SCHEME,
+          int TY = kTileY>
+__global__ __launch_bounds__(BX *TY) void step_cells(const StepArgs<C> a) {
     constexpr int D = Lattice<Q>::D;
     static_assert(BX % kBlockEdge == 0, "tile width must hold whole blocks");
     static_assert(D == 2 || !SENSOR || sizeof(C) == 4, "3D float64 uses step_zmarch");
+    static_assert(TY == kTileY || (D == 3 && kTileY % TY == 0), "row tiles are for 3D grids");
 
-    const int tile = xcd_tile(blockIdx.x, a.ntiles);
+    const int tile = (TY == kTileY) ? xcd_tile(blockIdx.x, a.ntiles) : (int)blockIdx.x;
     const int tix = tile % a.ntx;
     const int rest = tile / a.ntx;
     const int tiy = rest % a.nty;
     const int z = rest / a.nty;
     const int x = tix * BX + (int)threadIdx.x;
-    const int y = tiy * kTileY + wave_row<BX>();
+    const int y = tiy * TY + wave_row<BX>();
 
     C s = C(0);
     if (x < a.nx && y < a.ny) {
@@ -634,7 +652,7 @@ __global__ __launch_bounds__(BX *kTileY) void step_cells(const StepArgs<C> a) {
         if constexpr (SENSOR) accumulate<SKIND>(a, g.cell, s);
     }
     if constexpr (SENSOR) {
-        const C M = tile_block_max<BX>(s);
+        const C M = tile_block_max<BX, TY>(s);
         if (threadIdx.y == 0 && threadIdx.x < BX / kBlockEdge) {
             const int bx = tix * (BX / kBlockEdge) + (int)threadIdx.x;
             if (bx < a.nbx) {
@@ -642,11 +660,25 @@ __global__ __launch_bounds__(BX *kTileY) void step_cells(const StepArgs<C> a) {
                     write_block(a, tiy * a.nbx + bx, finish<SKIND>(M));
                 } else {
                     const int bz = z / kBlockEdge;
-                    const int b = (bz * a.nby + tiy) * a.nbx + bx;
-                    const unsigned need = (unsigned)min(kBlockEdge, a.nz - kBlockEdge * bz);
+                    const int by = (tiy * TY) / kBlockEdge;
+                    const int b = (bz * a.nby + by) * a.nbx + bx;
                     // M >= 0, +inf or NaN: unsigned order of the bits is a
                     // NaN-propagating max order
                     const unsigned mine = __float_as_uint(static_cast<float>(M));
+                    if constexpr (TY < kTileY) {
+                        // Row tiles: 64 workgroups meet in a block, most of them at
+                        // the same time, so a compare-and-swap loop would retry
+                        // (measured: +50% on a 256^3 step).  Each folds its maximum
+                        // into the low half of the block's word with one atomic max
+                        // and nothing else; finish_blocks_kernel, launched right
+                        // after the step, writes the block maxima and flags and
+                        // clears the words.
+                        unsigned *w32 = reinterpret_cast<unsigned *>(a.acc);
+                        __hip_atomic_fetch_max(&w32[2 * b], mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        return;
+                    }
+                    // contributions to block (bx, by, bz): one per z-slice of the block
+                    const unsigned need = (unsigned)min(kBlockEdge, a.nz - kBlockEdge * bz);
                     unsigned long long old = a.acc[b], seen;
                     unsigned cnt, top;
                     do {
@@ -692,7 +724,7 @@ __global__ __launch_bounds__(BX *kTileY) void step_zmarch(const StepArgs<C> a) {
         }
     }
     if constexpr (SENSOR) {
-        const C M = tile_block_max<BX>(m);
+        const C M = tile_block_max<BX, kTileY>(m);
         if (threadIdx.y == 0 && threadIdx.x < BX / kBlockEdge) {
             const int bx = tix * (BX / kBlockEdge) + (int)threadIdx.x;
             if (bx < a.nbx) write_block(a, (tiz * a.nby + tiy) * a.nbx + bx, finish<SKIND>(M));

@@ -1,5 +1,5 @@
 """The two-level hierarchy at the size of the refined benchmark (256^3 D3Q19
-lid-driven cavity, Re 1000, plain float32, up to 400 patches with fine edges
+lid-driven cavity, Re 1000, plain float32, 400 patches with fine edges
 from {16, 24, 32, 48}), in the benchmark's launch configuration: autotuned
 tiles and workgroups, coarse steps replayed from HIP graphs, the restriction
 fused into the second fine step, the LDS-staged ghost fill.  The oracle of
@@ -71,7 +71,9 @@ def test_full_size_hierarchy(orc, monkeypatch):
     w = lbm_inputs.cavity3d(n=N)
     st, tau = lbm.lbm_tau_from_reynolds(w.lid_speed, w.n_across, w.reynolds)
     boxes = _boxes()
-    assert len(boxes) >= 200 and max(hi[2] for lo, hi in boxes[:-1]) < 120
+    assert len(boxes) == 400 and max(hi[2] for lo, hi in boxes[:-1]) < 120
+    fine_cells = 8 * sum(int(np.prod([hi[a] - lo[a] for a in range(3)])) for lo, hi in boxes)
+    assert fine_cells > 14e6
     u = lbm_inputs.velocity_perturbation(w.n, 0.01, 5)
     print(f"\n[case] full-size hierarchy: {len(boxes)} patches, production configuration", flush=True)
     monkeypatch.delenv("LBM_HIER_RESTRICT", raising=False)

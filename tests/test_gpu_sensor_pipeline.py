@@ -32,6 +32,9 @@ def scheme(request, monkeypatch):
     return request.param
 
 
+_ORACLE_CACHE = {}
+
+
 def _wall(lid):
     w = [[0.0] * 3 for _ in range(6)]
     w[3][0] = lid
@@ -122,6 +125,36 @@ def test_time_averaged_sensor(lbm, orc, storage, kind, scheme):
     blk.average_end()
     blk.step_n(4, 2)
     assert blk.average()[1] == 15          # no longer accumulating
+    blk.close()
+
+
+@pytest.mark.parametrize("storage", [0, 2], ids=["f64", "f32s"])
+def test_time_averaged_sensor_10000_samples(lbm, orc, storage):
+    """The averaging window of the paper's runs (Sec. 4.3 averages over 10^4
+    iterations, Sec. 5.1 over a period): 10^4 sensor steps summed per cell in
+    float64 on a 16^3 lid cavity, against the oracle's mean of its per-step
+    sensor (Grid.sensor_history)."""
+    n = (16, 16, 16)
+    wall_u = _wall(0.08)
+    print(f"\n[case] average of 10^4 samples storage={storage}", flush=True)
+    desc = lbm.make_desc(19, n, (WALL,) * 6, 0.6, storage=storage, wall_u=wall_u)
+    G = orc.Grid(q=19, n=n, bc=(WALL,) * 6, wall_u=wall_u, tau=0.6)
+    blk = lbm.Blocks(desc)
+    blk.step_n(100, 0)
+    blk.average_begin()
+    blk.step_n(10000, 1)
+    bm, samples = blk.average()
+    if "avg10k" not in _ORACLE_CACHE:      # about 40 s of oracle steps, shared by both storages
+        S100, _ = G.run(G.equilibrium_state(), 0, 100, 0)
+        _, mean, cnt = G.sensor_history(S100, 100, 10000, 1, start=100)
+        _ORACLE_CACHE["avg10k"] = (G.block_max(mean), cnt)
+    ref, cnt = _ORACLE_CACHE["avg10k"]
+    assert samples == cnt == 10000
+    err = np.abs(bm - ref) / np.maximum(ref, 1e-3)
+    print(f"average of 10^4 samples: max rel err {err.max():.2e} (block max up to {ref.max():.2e})")
+    # float64: the populations themselves drift apart by ~1e-13 over 10^4
+    # steps; shifted float32: the per-sample sensor tolerance
+    assert err.max() <= (1e-10 if storage == 0 else 2e-5)
     blk.close()
 
 
