@@ -3,10 +3,15 @@
 The sensor's block maxima M_b (Sec. 3.2, blocks of Sec. 3.4) say where the
 mesh must be fine now; regridding every so many steps wants to know where it
 must be fine by the next regrid.  ``FlagPredictor`` is a small 3D CNN over
-the block grid that predicts log10 M_b `horizon` steps ahead from the
-per-block means of (rho - rho0, u) and log10 M_b now and one horizon earlier
-(the sensor's recent trend).  It predicts the change of log10 M_b, so "no
-change" (reusing the current flags) is what an untrained network returns.
+the block grid that predicts log10 M_b `horizon` steps ahead.  Two forms:
+
+* the configured one reads the per-block means of (rho - rho0, u) only (4
+  channels) and predicts log10 M_b at the horizon directly (standardised
+  with the training targets' mean and spread);
+* an extension also reads log10 M_b now and one horizon earlier (6
+  channels: the sensor and its recent trend) and predicts the change of
+  log10 M_b, so that "no change" (reusing the current flags) is what an
+  untrained network returns.
 
 Every product runs in the matrix-core kernels of liblbm.so (bindings in
 ``cnn``): forward, data and weight gradients, ReLU backward, the loss and
@@ -84,7 +89,10 @@ class _Layer:
 class FlagPredictor:
     """channels: (input, hidden..., 1); 3x3x3 convolutions, ReLU between."""
 
-    def __init__(self, channels=(6, 16, 16, 16, 1), seed=0, device="cuda", stream=None):
+    def __init__(self, channels=(6, 16, 16, 16, 1), seed=0, device="cuda", stream=None, residual=True):
+        """residual: the network learns the change of log10 M_b from the last
+        input channel (log10 M_b now); else it learns log10 M_b itself."""
+        self.residual = residual
         self.device = torch.device(device)
         self.stream = stream
         rng = np.random.default_rng(seed)
@@ -95,6 +103,7 @@ class FlagPredictor:
         # optimizer hyperparameters and step in device memory (lbm_cnn_adam_begin)
         self.hyper = torch.zeros(cnn.LBM_CNN_HYPER_FLOATS, dtype=torch.float32, device=self.device)
         self.normalizer = None
+        self.y_offset, self.y_scale = 0.0, 1.0
         self._bufs = {}
         self._pack()
 
@@ -227,13 +236,30 @@ class FlagPredictor:
         return y.view(-1, c4)[:, 0].cpu().numpy().astype(np.float64).reshape(shape)
 
     # -- the flag predictor ------------------------------------------------------
+    def _target_scale(self, raw, target_log):
+        """(offset, scale) with network output = (learned quantity - offset) * scale."""
+        y = np.asarray(target_log, dtype=np.float64)
+        if self.residual:
+            return 0.0, 1.0
+        sd = float(y.std())
+        return float(y.mean()), (1.0 / sd if sd > 0 else 1.0)
+
+    def _learned(self, raw, target_log):
+        """What the network output stands for: the change of log10 M_b from
+        the last input channel (residual), else log10 M_b itself."""
+        y = np.asarray(target_log, dtype=np.float64)
+        return y - raw[..., -1] if self.residual else y
+
     def fit(self, raw, target_log, iters=1500, batch=8, lr=2e-3, seed=0, log_every=0):
         """Trains on raw features [S, nbz, nby, nbx, C0] to predict
-        target_log [S, nbz, nby, nbx] = log10 M_b at the horizon.  The network
-        learns target - log10 M_b(now).  Returns the loss history."""
+        target_log [S, nbz, nby, nbx] = log10 M_b at the horizon (residual:
+        as target - log10 M_b now, the last channel; else the standardised
+        target).  Cosine learning rate from lr over `iters` Adam steps on
+        random batches.  Returns the loss history."""
         self.normalizer = Normalizer.fit(raw)
         xs = self.normalizer(raw)
-        dy = np.asarray(target_log, dtype=np.float64) - raw[..., -1]
+        self.y_offset, self.y_scale = self._target_scale(raw, target_log)
+        dy = (self._learned(raw, target_log) - self.y_offset) * self.y_scale
         rng = np.random.default_rng(seed)
         hist = []
         S = raw.shape[0]
@@ -249,7 +275,8 @@ class FlagPredictor:
         """Predicted log10 M_b at the horizon for raw features [S, ..., C0]."""
         if self.normalizer is None:
             raise RuntimeError("the predictor has not been fitted")
-        return raw[..., -1] + self.predict_raw(self.normalizer(raw))
+        y = self.predict_raw(self.normalizer(raw)) / self.y_scale + self.y_offset
+        return raw[..., -1] + y if self.residual else y
 
 
 def snapshot_run(Blocks, desc, snapshots, horizon, warm, history=True):

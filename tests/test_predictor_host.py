@@ -32,3 +32,20 @@ def test_flag_scores():
     p, r = P.flag_scores(pred, true)
     assert (p, r) == (2 / 3, 2 / 4)
     assert P.flag_scores(np.zeros(4, bool), np.zeros(4, bool)) == (0.0, 0.0)
+
+
+def test_learned_quantity_and_its_scale():
+    """The sensor network learns the change of log10 M_b from its last input
+    channel; the (rho, u) network learns log10 M_b itself, standardised with
+    the training targets' mean and spread."""
+    from types import SimpleNamespace
+    rng = np.random.default_rng(1)
+    raw = rng.standard_normal((3, 2, 2, 2, 6))
+    y = rng.standard_normal((3, 2, 2, 2)) * 0.7 - 3.0
+    res = SimpleNamespace(residual=True)
+    assert P.FlagPredictor._target_scale(res, raw, y) == (0.0, 1.0)
+    assert np.array_equal(P.FlagPredictor._learned(res, raw, y), y - raw[..., -1])
+    direct = SimpleNamespace(residual=False)
+    off, sc = P.FlagPredictor._target_scale(direct, raw[..., :4], y)
+    z = (P.FlagPredictor._learned(direct, raw[..., :4], y) - off) * sc
+    assert abs(z.mean()) < 1e-12 and abs(z.std() - 1.0) < 1e-12
