@@ -41,7 +41,7 @@ struct lbm_hierarchy {
     void *buf[LBM_NHBUF];
     int cur;                  // fine state in F_A (0) or F_B (1)
     double tau_f, alpha;
-    int wmax, nwg;            // widest fine tile (8, 16, 32) and persistent workgroups
+    int wmax, nwg;            // widest fine tile (8, 16, 32; kBandMaxW: bands) and persistent workgroups
     bool use_graph;
     hipGraphExec_t graph[2];  // two coarse steps, by the coarse buffer parity
     int64_t step;             // coarse steps taken through the hierarchy
@@ -241,7 +241,10 @@ PatchLists patch_lists(lbm_hierarchy *H) {
 }
 
 // Tiles of the fine step: per patch, rows of 8 x 8 x 8 blocks cut along x
-// into the widest of 32, 16, 8 cells (at most wmax) that still fit.
+// into the widest of 32, 16, 8 cells (at most wmax) that still fit (the
+// W x 8 x 8 tiles of patch_step), or for wmax = kBandMaxW into bands of
+// patch_band_step: the whole row when it is at most 48 cells wide, else
+// pieces of 48 cells and the rest (a multiple of 8).
 void build_tiles(lbm_hierarchy *H, int wmax) {
     H->tiles.clear();
     for (int p = 0; p < H->npatch; ++p) {
@@ -251,7 +254,9 @@ void build_tiles(lbm_hierarchy *H, int wmax) {
             for (int by = 0; by < nby; ++by)
                 for (int x0 = 0; x0 < r.e[0];) {
                     const int left = r.e[0] - x0;
-                    const int w = (wmax >= 32 && left >= 32) ? 32 : ((wmax >= 16 && left >= 16) ? 16 : 8);
+                    int w;
+                    if (wmax == kBandMaxW) w = std::min(left, kBandMaxW);
+                    else w = (wmax >= 32 && left >= 32) ? 32 : ((wmax >= 16 && left >= 16) ? 16 : 8);
                     PatchTile t{};
                     t.patch = p;
                     t.x0 = x0;
@@ -278,10 +283,22 @@ hipError_t upload_tiles(lbm_hierarchy *H) {
 void hier_fine_step(lbm_hierarchy *H, const void *src, void *dst, bool sensor, int64_t fine_step,
                     void *restrict_out = nullptr) {
     with_hier_types(H, [&]<int Q, typename T, typename C, bool SH>() {
-        PatchLaunch l{H->coarse->stream, sensor, H->coarse->d.sensor_kind, restrict_out != nullptr, H->nwg};
+        PatchLaunch l{H->coarse->stream, sensor, H->coarse->d.sensor_kind, restrict_out != nullptr, H->nwg,
+                      H->wmax == kBandMaxW};
         launch_patch_step<Q, T, C, SH>(patch_args<C>(H, src, dst, fine_step),
                                        coarse_view<C>(H, restrict_out, restrict_out, 0.0, restrict_out), l);
     });
+}
+
+// The fine step's default tiling: bands (patch_band_step); LBM_HIER_TILES=8,
+// 16 or 32 selects W x 8 x 8 tiles of patch_step (for comparison).
+int fine_tiling_setting() {
+    const char *s = std::getenv("LBM_HIER_TILES");
+    if (s) {
+        const int v = std::atoi(s);
+        if (v == 8 || v == 16 || v == 32) return v;
+    }
+    return kBandMaxW;
 }
 
 // The restriction runs inside the second fine step unless LBM_HIER_RESTRICT
@@ -401,7 +418,7 @@ lbm_status lbm_create_hierarchy(lbm_blocks *coarse, int32_t nbox, const lbm_box 
     }
     H->coarse = coarse;
     H->cur = 0;
-    build_tiles(H, 32);
+    build_tiles(H, fine_tiling_setting());
     H->nwg = (int)std::min<int64_t>(H->ntiles, 8 * kHierCUs);
     const bool sr = coarse->d.storage == LBM_F16_SHIFTED_SR || coarse->d.storage == LBM_BF16_SHIFTED_SR;
     if (use_graph != 0 && sr) {
@@ -678,7 +695,7 @@ lbm_status lbm_hierarchy_autotune(lbm_hierarchy *H, int32_t reps, int32_t *tile_
     int best_w = H->wmax, best_nwg = H->nwg;
     const int per_cu[4] = {2, 4, 8, 16};
     hipError_t e = hipSuccess;
-    for (int w : {8, 16, 32}) {
+    for (int w : {8, 16, 32, kBandMaxW}) {
         build_tiles(H, w);
         e = upload_tiles(H);
         if (e != hipSuccess) break;

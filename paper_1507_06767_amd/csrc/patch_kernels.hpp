@@ -178,6 +178,22 @@ __device__ __forceinline__ int64_t padded_index(const PatchRec &p, int x, int y,
     return (int64_t)p.off + ((int64_t)(z + 1) * (p.e[1] + 2) + (y + 1)) * (p.e[0] + 2) + (x + 1);
 }
 
+// Restriction sums in 64-bit fixed point with 2^-59 resolution: integer
+// additions are exact and associative, so the sum of a coarse cell's 8 fine
+// values does not depend on the order in which its contributions arrive
+// (LDS atomics in the band step) and equals the exact sum for float32 values
+// (multiples of 2^-59 down to |r| = 2^-35); float64 values are rounded to
+// 2^-59 each.  Deviations |r| < 1 keep the sum of 8 within range.
+constexpr double kFixScale = 0x1p59;
+template <typename C>
+__device__ __forceinline__ long long to_fixed(C r) {
+    return __double2ll_rn(static_cast<double>(r) * kFixScale);
+}
+template <typename C>
+__device__ __forceinline__ C fixed_mean8(long long sum) {
+    return static_cast<C>(static_cast<double>(sum) * (0.125 / kFixScale));
+}
+
 // One fine step of every patch.  A workgroup of 512 threads owns one tile
 // (W x 8 x 8 cells) at a time: thread t takes x = t mod W, y = (t / W) mod 8
 // and marches z from t / 8W in steps of 64 / W, so a wave reads W
@@ -202,7 +218,7 @@ __global__ __launch_bounds__(512) void patch_step(const PatchArgs<C> a, const Co
     // restriction: per coarse cell of the tile (at most 16 x 4 x 4) and
     // population, the sum of its 8 fine cells (two partial sums of 4)
     constexpr int kCoarsePerTile = 256;
-    __shared__ C racc[RESTRICT ? Q * kCoarsePerTile : 1];
+    __shared__ long long racc[RESTRICT ? Q * kCoarsePerTile : 1];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     using R = raw_t<T>;
     const char *src = static_cast<const char *>(a.src);
@@ -240,7 +256,7 @@ __global__ __launch_bounds__(512) void patch_step(const PatchArgs<C> a, const Co
         const R *xg0 = static_cast<const R *>(a.src) + a.xg_base + p.xoff + (xhi ? xg_side : 0) + (tl.y0 + y + 1);
         C m = C(0);
         if constexpr (RESTRICT) {
-            for (int r = t; r < Q * kCoarsePerTile; r += 512) racc[r] = C(0);
+            for (int r = t; r < Q * kCoarsePerTile; r += 512) racc[r] = 0;
             __syncthreads();
         }
 #pragma unroll 1
@@ -293,15 +309,12 @@ __global__ __launch_bounds__(512) void patch_step(const PatchArgs<C> a, const Co
                 *reinterpret_cast<R *>(dst + i * plane_bytes + cb) = stored;
                 if (xedge) *reinterpret_cast<R *>(dst + i * plane_bytes + cb + xoff) = stored;
                 if constexpr (RESTRICT) {
-                    // the value the level below reads back, summed over the x pair
-                    // (lanes t, t^1) and the y pair (lanes t, t^W) in a fixed order;
-                    // the two z halves meet in LDS (two additions to a zeroed slot,
-                    // so the result does not depend on their order)
+                    // the value the level below reads back, as a deviation, added
+                    // to its coarse cell's sum in fixed point (exact, any order)
                     C r = static_cast<C>(stored);
                     if constexpr (!SH) r -= a.shift[i];
-                    r += static_cast<C>(__shfl_xor(r, 1));
-                    r += static_cast<C>(__shfl_xor(r, W));
-                    if (((x | y) & 1) == 0) atomicAdd(&racc[i * kCoarsePerTile + rslot], r);
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&racc[i * kCoarsePerTile + rslot]),
+                              static_cast<unsigned long long>(to_fixed(r)));
                 }
             };
             relax(std::integral_constant<int, 0>{}, drho + (a.rho0 * m15usq + drho * m15usq));
@@ -331,7 +344,7 @@ __global__ __launch_bounds__(512) void patch_step(const PatchArgs<C> a, const Co
                 C dr[Q];
                 static_for<0, Q>([&](auto ic) {
                     constexpr int i = decltype(ic)::value;
-                    dr[i] = racc[i * kCoarsePerTile + t] * C(0.125);
+                    dr[i] = fixed_mean8<C>(racc[i * kCoarsePerTile + t]);
                 });
                 const Moments<Q, C> mo = moments_of<Q>(dr, a.rho0);
                 const C inv_alpha = C(1) / v.alpha;
@@ -363,6 +376,190 @@ __global__ __launch_bounds__(512) void patch_step(const PatchArgs<C> a, const Co
             }
             __syncthreads();
         }
+    }
+}
+
+// Widest tile of the band step (interior cells along x).
+constexpr int kBandMaxW = 48;
+
+// One fine step of every patch, band form.  A tile is a band of one patch:
+// W <= 48 interior cells along x (the whole row when it fits) by 8 rows by 8
+// slices, i.e. one row of 8^3 sensor blocks.  Its cells are numbered row by
+// row, slice by slice, and the 512 threads take consecutive numbers, so a
+// wave's 64 lanes read and write 64 consecutive cells of every population
+// plane: where the tile spans the patch row, the row-end ghost slots are
+// numbered too and a row's 8 rows are one contiguous run of memory.  Lanes on
+// a ghost slot (never read: x-face ghosts live in the compact arrays) store
+// zeros, so every line is written whole.  Per cell: the pull, BGK collision
+// and stores of patch_step, the same arithmetic in the same order (the same
+// bits).  Sensor: an LDS atomic max per block; restriction: each stored
+// value, as a deviation, is added to its coarse cell's LDS sum in fixed
+// point (exact and order independent), then one thread per coarse cell
+// takes the mean and rescales the non-equilibrium part by 1/alpha.
+template <int Q, typename T, typename C, bool SH, bool SENSOR, int SKIND, bool RESTRICT>
+__global__ __launch_bounds__(512) void patch_band_step(const PatchArgs<C> a, const CoarseView<C> v) {
+    static_assert(Lattice<Q>::D == 3, "3D patches");
+    using R = raw_t<T>;
+    constexpr int kRC = 4 * 4 * (kBandMaxW / 2);   // coarse cells of a tile: 4 slices x 4 rows x W/2
+    // block maxima as the bits of the sensor value: it is >= 0, +inf or NaN,
+    // so the unsigned order of its bits is a NaN-propagating max order
+    using U = std::conditional_t<sizeof(C) == 8, unsigned long long, unsigned>;
+    __shared__ U red[kBandMaxW / 8];
+    __shared__ long long racc[RESTRICT ? Q * kRC : 1];
+    const int t = threadIdx.x;
+    const char *src = static_cast<const char *>(a.src);
+    char *dst = static_cast<char *>(a.dst);
+    const int64_t plane_bytes = a.pitch * (int64_t)sizeof(R);
+    int k0 = blockIdx.x, k1 = a.ntiles, kstep = gridDim.x;
+    if (gridDim.x >= 8) {   // XCD j works through the j-th eighth of the tile list
+        const int xcd = blockIdx.x & 7;
+        k0 = (int)((int64_t)a.ntiles * xcd / 8) + (int)(blockIdx.x >> 3);
+        k1 = (int)((int64_t)a.ntiles * (xcd + 1) / 8);
+        kstep = (int)((gridDim.x - xcd + 7) >> 3);
+    }
+    for (int k = k0; k < k1; k += kstep) {
+        const PatchTile tl = a.tile[k];
+        const PatchRec p = a.patch[tl.patch];
+        const int W = tl.w, hx = W >> 1;
+        const int sy = p.e[0] + 2, sz = sy * (p.e[1] + 2);
+        const int P1 = p.e[1] + 2;
+        const int64_t xg_side = (int64_t)P1 * (p.e[2] + 2);
+        // lanes of a row segment: the W interior cells, plus a row-end ghost
+        // slot where the tile reaches the patch's end
+        const int g0 = tl.x0 == 0, g1 = tl.x0 + W == p.e[0];
+        const int L = W + g0 + g1, xs = tl.x0 + 1 - g0;   // first padded x of a segment
+        const int per_slice = 8 * L, total = 8 * per_slice;
+        if (SENSOR && t < W / 8) red[t] = U(0);
+        if constexpr (RESTRICT)
+            for (int r = t; r < Q * kRC; r += 512) racc[r] = 0;
+        __syncthreads();
+        // (slice, row, lane of the segment) of number j = t, then advanced by 512
+        int sl = t / per_slice;
+        int rem = t - sl * per_slice;
+        int row = rem / L, xl = rem - row * L;
+        const int drow = 512 / L, dxl = 512 - drow * L;
+#pragma unroll 1
+        for (int j = t; j < total; j += 512) {
+            const int xp = xs + xl;                   // padded x
+            const uint32_t cidx = (uint32_t)(p.off + (tl.z0 + sl + 1) * sz + (tl.y0 + row + 1) * sy + xp);
+            const uint32_t cb = cidx * (uint32_t)sizeof(R);
+            const int x = xp - 1;                     // interior x; -1 or e_x on a ghost slot
+            if (x < 0 || x >= p.e[0]) {
+                static_for<0, Q>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    *reinterpret_cast<R *>(dst + i * plane_bytes + cb) = R(0);
+                });
+            } else {
+                const bool xlo = x == 0, xhi = x == p.e[0] - 1;
+                const R *xgc = static_cast<const R *>(a.src) + a.xg_base + p.xoff + (xhi ? xg_side : 0) +
+                               (int64_t)(tl.z0 + sl + 1) * P1 + (tl.y0 + row + 1);
+                const uint32_t ckey = sr_cell_key<T>(cidx, kSaltFine, a.step);
+                C d[Q];
+                static_for<0, Q>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    using V = Vel<Q, i>;
+                    const int64_t delta = V::x + (int64_t)V::y * sy + (int64_t)V::z * sz;
+                    const char *base = src + i * plane_bytes - delta * (int64_t)sizeof(R);
+                    const R *from = reinterpret_cast<const R *>(base + cb);
+                    if constexpr (V::x > 0) {
+                        if (xlo) from = xgc + (i * a.xg_pitch - (V::z * P1 + V::y));
+                    } else if constexpr (V::x < 0) {
+                        if (xhi) from = xgc + (i * a.xg_pitch - (V::z * P1 + V::y));
+                    }
+                    const C vv = static_cast<C>(*from);
+                    if constexpr (SH) d[i] = vv;
+                    else d[i] = vv - a.shift[i];
+                });
+                C drho, j3[3];
+                cell_moments<Q>(d, drho, j3);
+                const C inv_rho = C(1) / (a.rho0 + drho);
+                const C u[3] = {j3[0] * inv_rho, j3[1] * inv_rho, j3[2] * inv_rho};
+                const C m15usq = C(-1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+                C num = C(0), den = C(0), kkn = C(0);
+                const int rslot = ((sl >> 1) * 4 + (row >> 1)) * hx + ((x - tl.x0) >> 1);
+                (void)rslot;
+                auto relax = [&](auto ic, C br) {
+                    constexpr int i = decltype(ic)::value;
+                    const C deq = wmul<C, Vel<Q, i>::w>(br);
+                    const C fneq = d[i] - deq;
+                    if constexpr (SENSOR) {
+                        const C feq = a.shift[i] + deq;
+                        if constexpr (SKIND == kSensorL2) {
+                            num += fneq * fneq;
+                            den += feq * feq;
+                        } else {
+                            kkn += fabs(fneq / feq);
+                        }
+                    }
+                    C out = d[i] - a.omega * fneq;
+                    if constexpr (!SH) out += a.shift[i];
+                    const R stored = to_storage<T>(out, Storage<T>::sr ? round_key(ckey, i) : 0u);
+                    *reinterpret_cast<R *>(dst + i * plane_bytes + cb) = stored;
+                    if constexpr (RESTRICT) {
+                        C r = static_cast<C>(stored);
+                        if constexpr (!SH) r -= a.shift[i];
+                        atomicAdd(reinterpret_cast<unsigned long long *>(&racc[i * kRC + rslot]),
+                                  static_cast<unsigned long long>(to_fixed(r)));
+                    }
+                };
+                relax(std::integral_constant<int, 0>{}, drho + (a.rho0 * m15usq + drho * m15usq));
+                static_for<0, (Q - 1) / 2>([&](auto kc) {
+                    constexpr int i = 2 * decltype(kc)::value + 1;
+                    const C cu = dot_c<Q, i>(u);
+                    const C cj = dot_c<Q, i>(j3);
+                    const C p2 = C(4.5) * cu * cu + m15usq;
+                    const C even = drho + (a.rho0 * p2 + drho * p2);
+                    relax(std::integral_constant<int, i>{}, even + C(3) * cj);
+                    relax(std::integral_constant<int, i + 1>{}, even - C(3) * cj);
+                });
+                if constexpr (SENSOR) {
+                    const C sv = SKIND == kSensorL2 ? num / den : kkn * C(1.0 / Q);
+                    atomicMax(&red[(x - tl.x0) >> 3], __builtin_bit_cast(U, sv));
+                }
+            }
+            xl += dxl;
+            row += drow;
+            if (xl >= L) {
+                xl -= L;
+                ++row;
+            }
+            sl += row >> 3;
+            row &= 7;
+        }
+        __syncthreads();
+        if constexpr (SENSOR) {
+            if (t < W / 8) {
+                const C M = finish<SKIND>(__builtin_bit_cast(C, red[t]));
+                a.block_max[tl.blk + t] = M;
+                a.flags[tl.blk + t] = block_flag(static_cast<double>(M), a.theta_r, a.theta_c);
+            }
+        }
+        if constexpr (RESTRICT) {
+            // each coarse cell of the tile takes the mean of its 8 fine cells,
+            // rescaled to the coarse level: d_c = deq + (d - deq) / alpha
+            for (int c = t; c < 16 * hx; c += 512) {
+                const int cxl = c % hx, cyl = (c / hx) & 3, czl = c / (4 * hx);
+                const int cx = ((p.o[0] + tl.x0) >> 1) + cxl;
+                const int cy = ((p.o[1] + tl.y0) >> 1) + cyl;
+                const int cz = ((p.o[2] + tl.z0) >> 1) + czl;
+                const int64_t cc = ((int64_t)cz * v.ny + cy) * v.nx + cx;
+                const int slot = (czl * 4 + cyl) * hx + cxl;
+                C dr[Q];
+                static_for<0, Q>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    dr[i] = fixed_mean8<C>(racc[i * kRC + slot]);
+                });
+                const Moments<Q, C> mo = moments_of<Q>(dr, a.rho0);
+                const C inv_alpha = C(1) / v.alpha;
+                const uint32_t rkey = sr_cell_key<T>((uint32_t)cc, kSaltRestrict, a.step);
+                static_for<0, Q>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    const C deq = deq_of<Q, i>(mo, a.rho0);
+                    store_dev<T>(v.out, i * v.pitch + cc, deq + inv_alpha * (dr[i] - deq), a.shift[i], SH, rkey, i);
+                });
+            }
+        }
+        __syncthreads();   // the next tile clears red and racc
     }
 }
 
@@ -546,17 +743,18 @@ __global__ __launch_bounds__(256) void patch_restrict(const PatchArgs<C> a, cons
     const PatchRec &p = a.patch[rp[t]];
     const int64_t sy = p.e[0] + 2, sz = sy * (p.e[1] + 2);
     const int64_t c0 = rf[t];
-    C d[Q];
-    static_for<0, Q>([&](auto ic) { d[decltype(ic)::value] = C(0); });
+    long long acc[Q];
+    static_for<0, Q>([&](auto ic) { acc[decltype(ic)::value] = 0; });
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const int64_t c = c0 + (k & 1) + ((k >> 1) & 1) * sy + (k >> 2) * sz;
         static_for<0, Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            d[i] += load_dev<T>(fine, i * a.pitch + c, a.shift[i], SH);
+            acc[i] += to_fixed(load_dev<T>(fine, i * a.pitch + c, a.shift[i], SH));
         });
     }
-    static_for<0, Q>([&](auto ic) { d[decltype(ic)::value] *= C(0.125); });
+    C d[Q];
+    static_for<0, Q>([&](auto ic) { d[decltype(ic)::value] = fixed_mean8<C>(acc[decltype(ic)::value]); });
     const Moments<Q, C> mo = moments_of<Q>(d, a.rho0);
     const int64_t cc = rc[t];
     const C inv_alpha = C(1) / v.alpha;
@@ -610,6 +808,7 @@ struct PatchLaunch {
     int sensor_kind;
     bool restrict_to_coarse;   // also restrict to the coarse state (CoarseView::out)
     int nwg;         // workgroups of the persistent launch
+    bool bands;      // the tile list holds bands (patch_band_step), else W x 8 x 8 tiles
 };
 
 // Lists the fine step and the coupling kernels read (device pointers).
@@ -645,7 +844,17 @@ template <int Q, typename T, typename C, bool SH>
 void launch_patch_step(const PatchArgs<C> &a, const CoarseView<C> &v, const PatchLaunch &l) {
     const dim3 g(l.nwg), b(512);
     auto go = [&](auto kern) { hipLaunchKernelGGL(kern, g, b, 0, l.stream, a, v); };
-    if (l.restrict_to_coarse) {
+    if (l.bands) {
+        if (l.restrict_to_coarse) {
+            if (!l.sensor) go(patch_band_step<Q, T, C, SH, false, kSensorL2, true>);
+            else if (l.sensor_kind == kSensorL2) go(patch_band_step<Q, T, C, SH, true, kSensorL2, true>);
+            else go(patch_band_step<Q, T, C, SH, true, kSensorKKn, true>);
+        } else {
+            if (!l.sensor) go(patch_band_step<Q, T, C, SH, false, kSensorL2, false>);
+            else if (l.sensor_kind == kSensorL2) go(patch_band_step<Q, T, C, SH, true, kSensorL2, false>);
+            else go(patch_band_step<Q, T, C, SH, true, kSensorKKn, false>);
+        }
+    } else if (l.restrict_to_coarse) {
         if (!l.sensor) go(patch_step<Q, T, C, SH, false, kSensorL2, true>);
         else if (l.sensor_kind == kSensorL2) go(patch_step<Q, T, C, SH, true, kSensorL2, true>);
         else go(patch_step<Q, T, C, SH, true, kSensorKKn, true>);
