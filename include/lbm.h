@@ -367,15 +367,20 @@ lbm_status lbm_hierarchy_patch_fields(lbm_hierarchy *H, int32_t patch, double *r
 lbm_status lbm_hierarchy_info(lbm_hierarchy *H, int64_t *fine_cells, int64_t *fine_blocks, double *n_eff,
                               double *tau_fine, int32_t *tile_x, int32_t *workgroups);
 
-/* Picks the fine step's tiling and its persistent workgroup count (2 to 16
+/* Picks the fine step's tiling and its persistent workgroup count (1 to 16
  * per compute unit) by timing `reps` launches of each with HIP events on the
- * handle's stream; the state is not changed.  Tilings (512 threads): bands
+ * handle's stream, then the workgroup count (1, 2 or 4 per compute unit) of
+ * the fine step that also restricts to the coarse level, on that tiling; the
+ * state is not changed (the timed launches write the buffers that the next
+ * fine and coarse steps overwrite).  Tilings (512 threads): bands
  * (*tile_x = 48, the default) of 8 rows x 8 slices of a patch, the whole row
  * when it is at most 48 cells wide, whose cells the threads take in memory
- * order; or tiles of W x 8 x 8 cells, W the widest of 8, 16, 32 not above
- * tile_x that fits the patch row.  Every tiling gives the same bits.  step_us (NULL allowed) receives the chosen configuration's mean
- * duration of one fine step over all patches, in microseconds.
- * Synchronises. */
+ * order (only on fine buffers below 4 GiB: they address them with 32-bit
+ * offsets); or tiles of W x 8 x 8 cells, W the widest of 8, 16, 32 not above
+ * tile_x that fits the patch row.  Every tiling gives the same bits.
+ * *workgroups receives the plain fine step's count; step_us (NULL allowed)
+ * the chosen configuration's mean duration of one plain fine step over all
+ * patches, in microseconds.  Synchronises. */
 lbm_status lbm_hierarchy_autotune(lbm_hierarchy *H, int32_t reps, int32_t *tile_x, int32_t *workgroups,
                                   double *step_us);
 

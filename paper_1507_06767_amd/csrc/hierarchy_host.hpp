@@ -42,6 +42,7 @@ struct lbm_hierarchy {
     int cur;                  // fine state in F_A (0) or F_B (1)
     double tau_f, alpha;
     int wmax, nwg;            // widest fine tile (8, 16, 32; kBandMaxW: bands) and persistent workgroups
+    int nwg_restrict;         // persistent workgroups of the restricting fine step
     bool use_graph;
     hipGraphExec_t graph[2];  // two coarse steps, by the coarse buffer parity
     int64_t step;             // coarse steps taken through the hierarchy
@@ -244,8 +245,10 @@ PatchLists patch_lists(lbm_hierarchy *H) {
 // into the widest of 32, 16, 8 cells (at most wmax) that still fit (the
 // W x 8 x 8 tiles of patch_step), or for wmax = kBandMaxW into bands of
 // patch_band_step: the whole row when it is at most 48 cells wide, else
-// pieces of 48 cells and the rest (a multiple of 8).
+// pieces of 48 cells and the rest (a multiple of 8).  Bands address a state
+// buffer with 32-bit byte offsets: above 4 GiB the tiles of 32 take over.
 void build_tiles(lbm_hierarchy *H, int wmax) {
+    if (wmax == kBandMaxW && H->bytes[LBM_HBUF_F_A] > (size_t(1) << 32)) wmax = 32;
     H->tiles.clear();
     for (int p = 0; p < H->npatch; ++p) {
         const PatchRec &r = H->rec[p];
@@ -283,8 +286,8 @@ hipError_t upload_tiles(lbm_hierarchy *H) {
 void hier_fine_step(lbm_hierarchy *H, const void *src, void *dst, bool sensor, int64_t fine_step,
                     void *restrict_out = nullptr) {
     with_hier_types(H, [&]<int Q, typename T, typename C, bool SH>() {
-        PatchLaunch l{H->coarse->stream, sensor, H->coarse->d.sensor_kind, restrict_out != nullptr, H->nwg,
-                      H->wmax == kBandMaxW};
+        PatchLaunch l{H->coarse->stream, sensor, H->coarse->d.sensor_kind, restrict_out != nullptr,
+                      restrict_out ? H->nwg_restrict : H->nwg, H->wmax == kBandMaxW};
         launch_patch_step<Q, T, C, SH>(patch_args<C>(H, src, dst, fine_step),
                                        coarse_view<C>(H, restrict_out, restrict_out, 0.0, restrict_out), l);
     });
@@ -420,6 +423,8 @@ lbm_status lbm_create_hierarchy(lbm_blocks *coarse, int32_t nbox, const lbm_box 
     H->cur = 0;
     build_tiles(H, fine_tiling_setting());
     H->nwg = (int)std::min<int64_t>(H->ntiles, 8 * kHierCUs);
+    // the restricting step's LDS sums leave room for one or two workgroups per CU
+    H->nwg_restrict = (int)std::min<int64_t>(H->ntiles, kHierCUs);
     const bool sr = coarse->d.storage == LBM_F16_SHIFTED_SR || coarse->d.storage == LBM_BF16_SHIFTED_SR;
     if (use_graph != 0 && sr) {
         delete H;
@@ -688,27 +693,34 @@ lbm_status lbm_hierarchy_autotune(lbm_hierarchy *H, int32_t reps, int32_t *tile_
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     // the timed launches read the fine state and write the other fine buffer,
-    // which the next step overwrites: the state is left unchanged
+    // which the next step overwrites, and the restricting ones also write the
+    // coarse buffer that the next coarse step overwrites: the state is left
+    // unchanged
     const void *src = fine_buf(H, H->cur);
     void *dst = fine_buf(H, H->cur ^ 1);
+    lbm_blocks *h = H->coarse;
+    void *coarse_next = h->d.buf[h->cur ? LBM_BUF_F_A : LBM_BUF_F_B];
+    hipError_t e = hipSuccess;
+    auto time_steps = [&](void *restrict_out, float &ms) {
+        hier_fine_step(H, src, dst, false, 0, restrict_out);   // warm-up
+        e = hipEventRecord(e0, s);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) hier_fine_step(H, src, dst, false, 0, restrict_out);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        return e == hipSuccess;
+    };
     float best = 1e30f;
     int best_w = H->wmax, best_nwg = H->nwg;
-    const int per_cu[4] = {2, 4, 8, 16};
-    hipError_t e = hipSuccess;
+    const int per_cu[5] = {1, 2, 4, 8, 16};
     for (int w : {8, 16, 32, kBandMaxW}) {
         build_tiles(H, w);
         e = upload_tiles(H);
         if (e != hipSuccess) break;
         for (int pc : per_cu) {
             H->nwg = (int)std::min<int64_t>(H->ntiles, (int64_t)pc * kHierCUs);
-            hier_fine_step(H, src, dst, false, 0);   // warm-up
-            e = hipEventRecord(e0, s);
-            for (int r = 0; r < reps && e == hipSuccess; ++r) hier_fine_step(H, src, dst, false, 0);
-            if (e == hipSuccess) e = hipEventRecord(e1, s);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) break;
+            if (!time_steps(nullptr, ms)) break;
             if (ms < best) {
                 best = ms;
                 best_w = w;
@@ -717,12 +729,27 @@ lbm_status lbm_hierarchy_autotune(lbm_hierarchy *H, int32_t reps, int32_t *tile_
         }
         if (e != hipSuccess) break;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    // the restricting step on the chosen tiling: its LDS sums hold the
+    // resident workgroups to one or two per CU, so fewer candidates
     build_tiles(H, best_w);
     if (e == hipSuccess) e = upload_tiles(H);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
     H->nwg = best_nwg;
+    float best_r = 1e30f;
+    int best_nwg_r = H->nwg_restrict;
+    for (int pc : {1, 2, 4}) {
+        if (e != hipSuccess) break;
+        H->nwg_restrict = (int)std::min<int64_t>(H->ntiles, (int64_t)pc * kHierCUs);
+        float ms = 0.0f;
+        if (!time_steps(coarse_next, ms)) break;
+        if (ms < best_r) {
+            best_r = ms;
+            best_nwg_r = H->nwg_restrict;
+        }
+    }
+    H->nwg_restrict = best_nwg_r;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     // graphs captured with the old tile list are stale
     for (int p = 0; p < 2; ++p)
         if (H->graph[p]) {

@@ -396,11 +396,26 @@ constexpr int kBandMaxW = 48;
 // value, as a deviation, is added to its coarse cell's LDS sum in fixed
 // point (exact and order independent), then one thread per coarse cell
 // takes the mean and rescales the non-equilibrium part by 1/alpha.
+//
+// Addresses: the host runs bands only on state buffers below 4 GiB, so every
+// access is one 64-bit base plus a 32-bit byte offset (a per-population
+// scalar plus the cell's offset), which keeps the scalar registers of 2Q
+// plane pointers out of the loop; at most 128 VGPRs (4 waves per SIMD).
+// Barriers keep the waves of a workgroup on neighbouring cells, so that the
+// lines that two waves share are written while both halves are in L2 and
+// the chip's window of memory in use stays compact (measured: without
+// them the step is 25% slower): one at the start of every tile, and after
+// every pass of the 512 threads, except with the restriction, whose LDS
+// atomics make the passes uneven (there one barrier after the tile's last
+// pass completes the sums).  The epilogue's thread that reads an LDS sum
+// also clears it for the next tile.
 template <int Q, typename T, typename C, bool SH, bool SENSOR, int SKIND, bool RESTRICT>
-__global__ __launch_bounds__(512) void patch_band_step(const PatchArgs<C> a, const CoarseView<C> v) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void patch_band_step(
+    const PatchArgs<C> a, const CoarseView<C> v) {
     static_assert(Lattice<Q>::D == 3, "3D patches");
     using R = raw_t<T>;
     constexpr int kRC = 4 * 4 * (kBandMaxW / 2);   // coarse cells of a tile: 4 slices x 4 rows x W/2
+    constexpr bool kPassSync = !RESTRICT;
     // block maxima as the bits of the sensor value: it is >= 0, +inf or NaN,
     // so the unsigned order of its bits is a NaN-propagating max order
     using U = std::conditional_t<sizeof(C) == 8, unsigned long long, unsigned>;
@@ -409,7 +424,7 @@ __global__ __launch_bounds__(512) void patch_band_step(const PatchArgs<C> a, con
     const int t = threadIdx.x;
     const char *src = static_cast<const char *>(a.src);
     char *dst = static_cast<char *>(a.dst);
-    const int64_t plane_bytes = a.pitch * (int64_t)sizeof(R);
+    const uint32_t plane_bytes = (uint32_t)a.pitch * (uint32_t)sizeof(R);
     int k0 = blockIdx.x, k1 = a.ntiles, kstep = gridDim.x;
     if (gridDim.x >= 8) {   // XCD j works through the j-th eighth of the tile list
         const int xcd = blockIdx.x & 7;
@@ -417,104 +432,109 @@ __global__ __launch_bounds__(512) void patch_band_step(const PatchArgs<C> a, con
         k1 = (int)((int64_t)a.ntiles * (xcd + 1) / 8);
         kstep = (int)((gridDim.x - xcd + 7) >> 3);
     }
+    if constexpr (SENSOR)
+        if (t < kBandMaxW / 8) red[t] = U(0);
+    if constexpr (RESTRICT)
+        for (int r = t; r < Q * kRC; r += 512) racc[r] = 0;
     for (int k = k0; k < k1; k += kstep) {
+        __syncthreads();   // the previous tile's epilogue has read and cleared the LDS sums
         const PatchTile tl = a.tile[k];
         const PatchRec p = a.patch[tl.patch];
         const int W = tl.w, hx = W >> 1;
         const int sy = p.e[0] + 2, sz = sy * (p.e[1] + 2);
         const int P1 = p.e[1] + 2;
-        const int64_t xg_side = (int64_t)P1 * (p.e[2] + 2);
+        const uint32_t xg_side = (uint32_t)P1 * (uint32_t)(p.e[2] + 2);
         // lanes of a row segment: the W interior cells, plus a row-end ghost
         // slot where the tile reaches the patch's end
         const int g0 = tl.x0 == 0, g1 = tl.x0 + W == p.e[0];
         const int L = W + g0 + g1, xs = tl.x0 + 1 - g0;   // first padded x of a segment
         const int per_slice = 8 * L, total = 8 * per_slice;
-        if (SENSOR && t < W / 8) red[t] = U(0);
-        if constexpr (RESTRICT)
-            for (int r = t; r < Q * kRC; r += 512) racc[r] = 0;
-        __syncthreads();
         // (slice, row, lane of the segment) of number j = t, then advanced by 512
         int sl = t / per_slice;
         int rem = t - sl * per_slice;
         int row = rem / L, xl = rem - row * L;
         const int drow = 512 / L, dxl = 512 - drow * L;
 #pragma unroll 1
-        for (int j = t; j < total; j += 512) {
-            const int xp = xs + xl;                   // padded x
-            const uint32_t cidx = (uint32_t)(p.off + (tl.z0 + sl + 1) * sz + (tl.y0 + row + 1) * sy + xp);
-            const uint32_t cb = cidx * (uint32_t)sizeof(R);
-            const int x = xp - 1;                     // interior x; -1 or e_x on a ghost slot
-            if (x < 0 || x >= p.e[0]) {
-                static_for<0, Q>([&](auto ic) {
-                    constexpr int i = decltype(ic)::value;
-                    *reinterpret_cast<R *>(dst + i * plane_bytes + cb) = R(0);
-                });
-            } else {
-                const bool xlo = x == 0, xhi = x == p.e[0] - 1;
-                const R *xgc = static_cast<const R *>(a.src) + a.xg_base + p.xoff + (xhi ? xg_side : 0) +
-                               (int64_t)(tl.z0 + sl + 1) * P1 + (tl.y0 + row + 1);
-                const uint32_t ckey = sr_cell_key<T>(cidx, kSaltFine, a.step);
-                C d[Q];
-                static_for<0, Q>([&](auto ic) {
-                    constexpr int i = decltype(ic)::value;
-                    using V = Vel<Q, i>;
-                    const int64_t delta = V::x + (int64_t)V::y * sy + (int64_t)V::z * sz;
-                    const char *base = src + i * plane_bytes - delta * (int64_t)sizeof(R);
-                    const R *from = reinterpret_cast<const R *>(base + cb);
-                    if constexpr (V::x > 0) {
-                        if (xlo) from = xgc + (i * a.xg_pitch - (V::z * P1 + V::y));
-                    } else if constexpr (V::x < 0) {
-                        if (xhi) from = xgc + (i * a.xg_pitch - (V::z * P1 + V::y));
-                    }
-                    const C vv = static_cast<C>(*from);
-                    if constexpr (SH) d[i] = vv;
-                    else d[i] = vv - a.shift[i];
-                });
-                C drho, j3[3];
-                cell_moments<Q>(d, drho, j3);
-                const C inv_rho = C(1) / (a.rho0 + drho);
-                const C u[3] = {j3[0] * inv_rho, j3[1] * inv_rho, j3[2] * inv_rho};
-                const C m15usq = C(-1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-                C num = C(0), den = C(0), kkn = C(0);
-                const int rslot = ((sl >> 1) * 4 + (row >> 1)) * hx + ((x - tl.x0) >> 1);
-                (void)rslot;
-                auto relax = [&](auto ic, C br) {
-                    constexpr int i = decltype(ic)::value;
-                    const C deq = wmul<C, Vel<Q, i>::w>(br);
-                    const C fneq = d[i] - deq;
-                    if constexpr (SENSOR) {
-                        const C feq = a.shift[i] + deq;
-                        if constexpr (SKIND == kSensorL2) {
-                            num += fneq * fneq;
-                            den += feq * feq;
-                        } else {
-                            kkn += fabs(fneq / feq);
+        for (int j0 = 0; j0 < total; j0 += 512) {
+            if (j0 + t < total) {
+                const int xp = xs + xl;                   // padded x
+                const uint32_t cidx = (uint32_t)(p.off + (tl.z0 + sl + 1) * sz + (tl.y0 + row + 1) * sy + xp);
+                const uint32_t cb = cidx * (uint32_t)sizeof(R);
+                const int x = xp - 1;                     // interior x; -1 or e_x on a ghost slot
+                if (x < 0 || x >= p.e[0]) {
+                    static_for<0, Q>([&](auto ic) {
+                        constexpr int i = decltype(ic)::value;
+                        *reinterpret_cast<R *>(dst + (cb + i * plane_bytes)) = R(0);
+                    });
+                } else {
+                    const bool xlo = x == 0, xhi = x == p.e[0] - 1;
+                    // element of the cell's row in the x-face ghost arrays of its side
+                    const uint32_t xgc = (uint32_t)a.xg_base + (uint32_t)p.xoff + (xhi ? xg_side : 0u) +
+                                         (uint32_t)((tl.z0 + sl + 1) * P1 + (tl.y0 + row + 1));
+                    const uint32_t ckey = sr_cell_key<T>(cidx, kSaltFine, a.step);
+                    C d[Q];
+                    static_for<0, Q>([&](auto ic) {
+                        constexpr int i = decltype(ic)::value;
+                        using V = Vel<Q, i>;
+                        // byte offsets modulo 2^32: the true offset lies in [0, 2^32)
+                        const uint32_t delta = (uint32_t)(V::x + V::y * sy + V::z * sz) * (uint32_t)sizeof(R);
+                        uint32_t off = cb + i * plane_bytes - delta;
+                        if constexpr (V::x != 0) {
+                            const uint32_t xoff =
+                                (xgc + (uint32_t)i * (uint32_t)a.xg_pitch - (uint32_t)(V::z * P1 + V::y)) *
+                                (uint32_t)sizeof(R);
+                            if (V::x > 0 ? xlo : xhi) off = xoff;
                         }
+                        const C vv = static_cast<C>(*reinterpret_cast<const R *>(src + off));
+                        if constexpr (SH) d[i] = vv;
+                        else d[i] = vv - a.shift[i];
+                    });
+                    C drho, j3[3];
+                    cell_moments<Q>(d, drho, j3);
+                    const C inv_rho = C(1) / (a.rho0 + drho);
+                    const C u[3] = {j3[0] * inv_rho, j3[1] * inv_rho, j3[2] * inv_rho};
+                    const C m15usq = C(-1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+                    C num = C(0), den = C(0), kkn = C(0);
+                    const int rslot = ((sl >> 1) * 4 + (row >> 1)) * hx + ((x - tl.x0) >> 1);
+                    (void)rslot;
+                    auto relax = [&](auto ic, C br) {
+                        constexpr int i = decltype(ic)::value;
+                        const C deq = wmul<C, Vel<Q, i>::w>(br);
+                        const C fneq = d[i] - deq;
+                        if constexpr (SENSOR) {
+                            const C feq = a.shift[i] + deq;
+                            if constexpr (SKIND == kSensorL2) {
+                                num += fneq * fneq;
+                                den += feq * feq;
+                            } else {
+                                kkn += fabs(fneq / feq);
+                            }
+                        }
+                        C out = d[i] - a.omega * fneq;
+                        if constexpr (!SH) out += a.shift[i];
+                        const R stored = to_storage<T>(out, Storage<T>::sr ? round_key(ckey, i) : 0u);
+                        *reinterpret_cast<R *>(dst + (cb + i * plane_bytes)) = stored;
+                        if constexpr (RESTRICT) {
+                            C r = static_cast<C>(stored);
+                            if constexpr (!SH) r -= a.shift[i];
+                            atomicAdd(reinterpret_cast<unsigned long long *>(&racc[i * kRC + rslot]),
+                                      static_cast<unsigned long long>(to_fixed(r)));
+                        }
+                    };
+                    relax(std::integral_constant<int, 0>{}, drho + (a.rho0 * m15usq + drho * m15usq));
+                    static_for<0, (Q - 1) / 2>([&](auto kc) {
+                        constexpr int i = 2 * decltype(kc)::value + 1;
+                        const C cu = dot_c<Q, i>(u);
+                        const C cj = dot_c<Q, i>(j3);
+                        const C p2 = C(4.5) * cu * cu + m15usq;
+                        const C even = drho + (a.rho0 * p2 + drho * p2);
+                        relax(std::integral_constant<int, i>{}, even + C(3) * cj);
+                        relax(std::integral_constant<int, i + 1>{}, even - C(3) * cj);
+                    });
+                    if constexpr (SENSOR) {
+                        const C sv = SKIND == kSensorL2 ? num / den : kkn * C(1.0 / Q);
+                        atomicMax(&red[(x - tl.x0) >> 3], __builtin_bit_cast(U, sv));
                     }
-                    C out = d[i] - a.omega * fneq;
-                    if constexpr (!SH) out += a.shift[i];
-                    const R stored = to_storage<T>(out, Storage<T>::sr ? round_key(ckey, i) : 0u);
-                    *reinterpret_cast<R *>(dst + i * plane_bytes + cb) = stored;
-                    if constexpr (RESTRICT) {
-                        C r = static_cast<C>(stored);
-                        if constexpr (!SH) r -= a.shift[i];
-                        atomicAdd(reinterpret_cast<unsigned long long *>(&racc[i * kRC + rslot]),
-                                  static_cast<unsigned long long>(to_fixed(r)));
-                    }
-                };
-                relax(std::integral_constant<int, 0>{}, drho + (a.rho0 * m15usq + drho * m15usq));
-                static_for<0, (Q - 1) / 2>([&](auto kc) {
-                    constexpr int i = 2 * decltype(kc)::value + 1;
-                    const C cu = dot_c<Q, i>(u);
-                    const C cj = dot_c<Q, i>(j3);
-                    const C p2 = C(4.5) * cu * cu + m15usq;
-                    const C even = drho + (a.rho0 * p2 + drho * p2);
-                    relax(std::integral_constant<int, i>{}, even + C(3) * cj);
-                    relax(std::integral_constant<int, i + 1>{}, even - C(3) * cj);
-                });
-                if constexpr (SENSOR) {
-                    const C sv = SKIND == kSensorL2 ? num / den : kkn * C(1.0 / Q);
-                    atomicMax(&red[(x - tl.x0) >> 3], __builtin_bit_cast(U, sv));
                 }
             }
             xl += dxl;
@@ -525,11 +545,14 @@ __global__ __launch_bounds__(512) void patch_band_step(const PatchArgs<C> a, con
             }
             sl += row >> 3;
             row &= 7;
+            if constexpr (kPassSync) __syncthreads();
         }
-        __syncthreads();
+        if constexpr (RESTRICT) __syncthreads();   // the tile's LDS sums are complete
+        // epilogue: each sum is read and cleared by one thread
         if constexpr (SENSOR) {
             if (t < W / 8) {
                 const C M = finish<SKIND>(__builtin_bit_cast(C, red[t]));
+                red[t] = U(0);
                 a.block_max[tl.blk + t] = M;
                 a.flags[tl.blk + t] = block_flag(static_cast<double>(M), a.theta_r, a.theta_c);
             }
@@ -543,11 +566,11 @@ __global__ __launch_bounds__(512) void patch_band_step(const PatchArgs<C> a, con
                 const int cy = ((p.o[1] + tl.y0) >> 1) + cyl;
                 const int cz = ((p.o[2] + tl.z0) >> 1) + czl;
                 const int64_t cc = ((int64_t)cz * v.ny + cy) * v.nx + cx;
-                const int slot = (czl * 4 + cyl) * hx + cxl;
                 C dr[Q];
                 static_for<0, Q>([&](auto ic) {
                     constexpr int i = decltype(ic)::value;
-                    dr[i] = fixed_mean8<C>(racc[i * kRC + slot]);
+                    dr[i] = fixed_mean8<C>(racc[i * kRC + c]);
+                    racc[i * kRC + c] = 0;
                 });
                 const Moments<Q, C> mo = moments_of<Q>(dr, a.rho0);
                 const C inv_alpha = C(1) / v.alpha;
@@ -559,7 +582,6 @@ __global__ __launch_bounds__(512) void patch_band_step(const PatchArgs<C> a, con
                 });
             }
         }
-        __syncthreads();   // the next tile clears red and racc
     }
 }
 
