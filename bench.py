@@ -6,7 +6,7 @@ and the refine/coarsen flags evaluated at every step.  A "step" is one
 launch of the fused kernel over the whole grid.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W]
-                  [--workload cavity128|cavity256|channel256|refined256|predictor|cavity64_2d]
+                  [--workload cavity128|cavity256|channel256|refined256|predictor|cavity64_2d|conv_sweep]
                   [--storage f32|f32s|f64|f16s|bf16s|f16sr|bf16sr] [--lattice 19|27]
                   [--smagorinsky C] [--no-cpu-baseline] [--no-copy-calibration]
 
@@ -51,6 +51,10 @@ entry prices one 16 -> 16 channel convolution at its algorithmic flops
 against the dense BF16 matrix-core peak.  The batch stays on the device and
 one iteration is replayed from a HIP graph (eager_iterations_per_s gives the
 same loop launched kernel by kernel).
+
+--workload conv_sweep: the predictor's 16 -> 16 convolution (forward and
+weight gradient) on 8, 32, 128 and 512 block grids of 16^3, each timed over
+20 graph-replayed launches; one JSON line with a row per batch.
 """
 import argparse
 import hashlib
@@ -422,6 +426,56 @@ def run_predictor(args, lbm, torch):
     }
 
 
+def run_conv_sweep(args, lbm, torch):
+    """Batch sweep of the predictor's 16 -> 16 convolution: forward and
+    weight gradient on 8, 32, 128 and 512 block grids of 16^3 (random
+    activations), each timed over 20 launches captured into a HIP graph;
+    returns the JSON dict."""
+    import lbm_inputs
+    from paper_1507_06767_amd import cnn
+    from paper_1507_06767_amd.predictor import FlagPredictor
+    torch.cuda.set_device(0)
+    rows = []
+    for nb in (8, 32, 128, 512):
+        shape = (nb, 16, 16, 16)
+        nv = int(np.prod(shape))
+        net = FlagPredictor(channels=(16, 16, 16, 16, 1), seed=0)
+        B = net._buffers(shape)
+        L = net.layers[1]
+        x, y = B["acts"][0], B["acts"][1]
+        x.copy_(torch.from_numpy((2.0 * lbm_inputs.uniform(13, x.numel()) - 1.0).astype(np.float32)))
+        reps = 20
+        timing = {}
+        for name, call in (("forward", lambda: cnn.lbm_cnn_conv3d_forward(x, *shape, L.ci, L.packed, L.co, L.b, 1,
+                                                                            None, y)),
+                           ("wgrad", lambda: cnn.lbm_cnn_conv3d_wgrad(x, y, *shape, L.ci, L.co, B["work"], L.gw,
+                                                                        L.gb))):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                for _ in range(reps):
+                    assert call() == 0
+            g.replay()
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            g.replay()
+            b.record()
+            torch.cuda.synchronize()
+            timing[name] = a.elapsed_time(b) / reps * 1e3
+        flops = 2.0 * nv * 16 * 27 * 16
+        rows.append({"batch": nb, "voxels": nv, "forward_us": round(timing["forward"], 2),
+                     "forward_tflops": round(flops / timing["forward"] / 1e6, 1),
+                     "wgrad_us": round(timing["wgrad"], 2),
+                     "wgrad_tflops": round(flops / timing["wgrad"] / 1e6, 1)})
+        del net, B
+        torch.cuda.empty_cache()
+    return {"metric": "16 -> 16 conv3d forward and weight-gradient time per batch (BF16 MFMA)",
+            "unit": "us", "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+            "config": {"workload": "predictor convolution batch sweep, block grids of 16^3"},
+            "peak_tflops": 2500.0, "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -448,8 +502,9 @@ def main():
     import torch
     import paper_1507_06767_amd as lbm
 
-    if args.workload in ("refined256", "predictor", "cavity64_2d"):
-        run = {"refined256": run_refined, "predictor": run_predictor, "cavity64_2d": run_cavity2d}[args.workload]
+    if args.workload in ("refined256", "predictor", "cavity64_2d", "conv_sweep"):
+        run = {"refined256": run_refined, "predictor": run_predictor, "cavity64_2d": run_cavity2d,
+               "conv_sweep": run_conv_sweep}[args.workload]
         print(json.dumps(run(args, lbm, torch)), flush=True)
         return
 

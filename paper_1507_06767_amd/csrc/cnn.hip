@@ -38,13 +38,15 @@ __device__ inline short to_bf16(float v) {
     return __builtin_bit_cast(short, static_cast<__bf16>(v));   // round to nearest even
 }
 
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+
+// Four floats to bfloat16 (round to nearest even), two per packed conversion.
 __device__ inline bf16x4 to_bf16x4(float a, float b, float c, float d) {
-    bf16x4 r;
-    r[0] = to_bf16(a);
-    r[1] = to_bf16(b);
-    r[2] = to_bf16(c);
-    r[3] = to_bf16(d);
-    return r;
+    const bf16x2v lo = __builtin_convertvector((f32x2v){a, b}, bf16x2v);
+    const bf16x2v hi = __builtin_convertvector((f32x2v){c, d}, bf16x2v);
+    const unsigned u[2] = {__builtin_bit_cast(unsigned, lo), __builtin_bit_cast(unsigned, hi)};
+    return __builtin_bit_cast(bf16x4, u);
 }
 
 struct Vox {
@@ -119,6 +121,78 @@ __global__ __launch_bounds__(256) void conv_forward_kernel(const float *x, int n
             if (kc0 + 16 * q < k16)
                 acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(to_bf16x4(a[q].x, a[q].y, a[q].z, a[q].w), B[q],
                                                                 acc, 0, 0, 0);
+    }
+    const int oc = co0 + r;
+    if (oc >= co4) return;
+    const float b = (bias && oc < co) ? bias[oc] : 0.0f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int v = v0 + 4 * kg + j;
+        if (v >= nv) continue;
+        float o = acc[j] + b;
+        if (relu) o = o > 0.0f ? o : 0.0f;
+        if (mask) o = mask[(int64_t)v * co4 + oc] > 0.0f ? o : 0.0f;
+        y[(int64_t)v * co4 + oc] = o;
+    }
+}
+
+// The same convolution for 4 or 16 (padded) input channels, the
+// predictor's: with CI a compile-time constant, the tap of K step s is s
+// itself (CI = 16) or 4 s + lane group (CI = 4), so its neighbour offset and
+// its bounds test come from the lane's voxel, decomposed once, instead of a
+// division and a 64-bit index per step; a step's source is the lane's base
+// pointer plus the tap's offset.  (The generic kernel spends ~30 VALU per
+// MFMA on that index arithmetic.)  The same operands in the same order as
+// conv_forward_kernel: the same bits.
+template <int CI>
+__global__ __launch_bounds__(256) void conv_forward_ci(const float *x, int n, int d, int h, int w,
+                                                       const uint16_t *packed, int co, const float *bias,
+                                                       int relu, const float *mask, float *y) {
+    constexpr int K16 = (kTaps * CI + 15) / 16 * 16, NK = K16 / 16;
+    const int co4 = pad4(co);
+    const int nv = n * d * h * w;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int v0 = (blockIdx.x * 4 + wave) * 16;
+    const int co0 = blockIdx.y * 16;
+    if (v0 >= nv) return;
+    const int r = lane & 15, kg = lane >> 4;
+    const int va = v0 + r;
+    const bool vok = va < nv;
+    const Vox pa = decompose(vok ? va : 0, d, h, w);
+    // is the neighbour at offset -1, 0, +1 along each axis inside the grid
+    const bool zok[3] = {pa.z > 0, true, pa.z < d - 1};
+    const bool yok[3] = {pa.y > 0, true, pa.y < h - 1};
+    const bool xok[3] = {pa.x > 0, true, pa.x < w - 1};
+    const int hw = h * w;
+    const float *xb = x + (int64_t)(vok ? va : 0) * CI + (CI == 16 ? 4 * kg : 0);
+    const uint16_t *wrow = packed + (int64_t)(co0 + r) * K16 + 4 * kg;
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    constexpr int kPass = 9;
+#pragma unroll
+    for (int s0 = 0; s0 < NK; s0 += kPass) {
+        float4 a[kPass];
+        bool ok[kPass];
+        bf16x4 B[kPass];
+#pragma unroll
+        for (int q = 0; q < kPass; ++q) {
+            const int s = s0 + q;
+            if (s < NK) {
+                const int tap = (CI == 16) ? s : 4 * s + kg;   // k = 16 s + 4 kg, tap = k / CI
+                const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;   // offsets + 1
+                ok[q] = vok && tap < kTaps && zok[dz] && yok[dy] && xok[dx];
+                const int off = ((dz - 1) * hw + (dy - 1) * w + (dx - 1)) * CI;
+                a[q] = *reinterpret_cast<const float4 *>(xb + (ok[q] ? off : 0));
+                B[q] = *reinterpret_cast<const bf16x4 *>(wrow + 16 * s);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kPass; ++q)
+            if (s0 + q < NK) {
+                // outside the grid: zeros (the load above read the lane's own voxel)
+                const bf16x4 A = to_bf16x4(a[q].x, a[q].y, a[q].z, a[q].w);
+                const bf16x4 zero = {0, 0, 0, 0};
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ok[q] ? A : zero, B[q], acc, 0, 0, 0);
+            }
     }
     const int oc = co0 + r;
     if (oc >= co4) return;
@@ -229,6 +303,94 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(const float *x, const f
         for (int wv = 0; wv < 4; ++wv)
             for (int g = 0; g < 4; ++g) b += bias[wv][g][t];
         work[(int64_t)gridDim.x * co16 * k16 + (int64_t)chunk * co16 + c0 + t] = b;
+    }
+}
+
+// The same weight-gradient partials for 4 or 16 (padded) input channels and
+// rows of a multiple of 4 voxels: the lane's first voxel is decomposed once
+// and then advanced by 16 voxels per step (carrying into y, z, n), its
+// gradient and input pointers by 16 voxels' strides, so a step is its
+// bounds tests, eight loads and one MFMA.  The same operands in the same
+// order as conv_wgrad_kernel: the same bits.
+template <int CI>
+__global__ __launch_bounds__(256) void conv_wgrad_ci(const float *x, const float *gz, int n, int d, int h, int w,
+                                                     int ci, int co, float *work) {
+    constexpr int K16 = (kTaps * CI + 15) / 16 * 16;
+    const int co4 = pad4(co), co16 = pad16(co);
+    const int nv = n * d * h * w;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int chunk = blockIdx.x, k0 = blockIdx.y * 16, c0 = blockIdx.z * 16;
+    const int r = lane & 15, kg = lane >> 4;
+    const int kcol = k0 + r;                       // this lane's B column
+    const int tap = kcol / CI, cch = kcol % CI;
+    const bool col_ok = tap < kTaps && cch < ci;
+    const int ocol = c0 + r;                       // this lane's A row (output channel)
+    const bool row_ok = ocol < co;
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    float bsum = 0.0f;
+    const int vbeg = chunk * kWgradVoxels + wave * (kWgradVoxels / 4);
+    const int vend = min(vbeg + kWgradVoxels / 4, nv);
+    const int tdz = tap / 9 - 1, tdy = (tap / 3) % 3 - 1, tdx = tap % 3 - 1;
+    const int tdelta = (tdz * h + tdy) * w + tdx;
+    // the lane's 4 voxels of step 0: vq .. vq + 3, one row (w is a multiple of 4)
+    int vq = vbeg + 4 * kg;
+    Vox p = decompose(vq < nv ? vq : 0, d, h, w);
+    const float *gp = gz + (int64_t)vq * co4 + ocol;
+    const float *xp = x + ((int64_t)vq + tdelta) * CI + cch;
+    auto step = [&](const float (&a)[4], const float (&b)[4]) {
+        bsum += ((a[0] + a[1]) + a[2]) + a[3];
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(to_bf16x4(a[0], a[1], a[2], a[3]),
+                                                        to_bf16x4(b[0], b[1], b[2], b[3]), acc, 0, 0, 0);
+    };
+    constexpr int kPass = 4;
+    for (int v0 = vbeg; v0 < vend; v0 += 16 * kPass) {
+        float a[kPass][4], b[kPass][4];
+#pragma unroll
+        for (int q = 0; q < kPass; ++q) {
+            const bool zy_ok = col_ok && p.z + tdz >= 0 && p.z + tdz < d && p.y + tdy >= 0 && p.y + tdy < h;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int v = vq + j;
+                const int xx = p.x + j + tdx;
+                const bool oka = v < vend && row_ok;
+                const bool okb = v < vend && zy_ok && xx >= 0 && xx < w;
+                const float av = *(oka ? gp + j * co4 : gz);
+                const float bv = *(okb ? xp + j * CI : x);
+                a[q][j] = oka ? av : 0.0f;
+                b[q][j] = okb ? bv : 0.0f;
+            }
+            // the next 16 voxels
+            vq += 16;
+            gp += 16 * co4;
+            xp += 16 * CI;
+            p.x += 16;
+            while (p.x >= w) {
+                p.x -= w;
+                if (++p.y == h) {
+                    p.y = 0;
+                    if (++p.z == d) p.z = 0;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kPass; ++q)
+            if (v0 + 16 * q < vend) step(a[q], b[q]);
+    }
+    __shared__ float tile[4][16][16];
+    __shared__ float bias[4][4][16];   // [wave][lane group][channel]
+#pragma unroll
+    for (int j = 0; j < 4; ++j) tile[wave][4 * kg + j][r] = acc[j];
+    bias[wave][kg][r] = bsum;
+    __syncthreads();
+    const int t = threadIdx.x;   // 256 threads = one 16x16 tile
+    const int row = t / 16, col = t % 16;
+    const float sum = ((tile[0][row][col] + tile[1][row][col]) + tile[2][row][col]) + tile[3][row][col];
+    work[((int64_t)chunk * co16 + c0 + row) * K16 + k0 + col] = sum;
+    if (blockIdx.y == 0 && t < 16) {
+        float bb = 0.0f;
+        for (int wv = 0; wv < 4; ++wv)
+            for (int g = 0; g < 4; ++g) bb += bias[wv][g][t];
+        work[(int64_t)gridDim.x * co16 * K16 + (int64_t)chunk * co16 + c0 + t] = bb;
     }
 }
 
@@ -416,8 +578,15 @@ int32_t lbm_cnn_conv3d_forward(const float *x, int32_t n, int32_t d, int32_t h, 
     const int64_t nv = (int64_t)n * d * h * wd;
     if (nv >= (int64_t(1) << 31)) return -1;
     const dim3 grid(blocks_for(nv, 64), pad16(co) / 16);
-    hipLaunchKernelGGL(conv_forward_kernel, grid, dim3(256), 0, (hipStream_t)stream, x, n, d, h, wd, ci, packed,
-                       co, bias, relu, mask, y);
+    if (pad4(ci) == 16)
+        hipLaunchKernelGGL(conv_forward_ci<16>, grid, dim3(256), 0, (hipStream_t)stream, x, n, d, h, wd, packed,
+                           co, bias, relu, mask, y);
+    else if (pad4(ci) == 4)
+        hipLaunchKernelGGL(conv_forward_ci<4>, grid, dim3(256), 0, (hipStream_t)stream, x, n, d, h, wd, packed,
+                           co, bias, relu, mask, y);
+    else
+        hipLaunchKernelGGL(conv_forward_kernel, grid, dim3(256), 0, (hipStream_t)stream, x, n, d, h, wd, ci,
+                           packed, co, bias, relu, mask, y);
     return launched();
 }
 
@@ -436,7 +605,12 @@ int32_t lbm_cnn_conv3d_wgrad(const float *x, const float *gz, int32_t n, int32_t
     const int nchunk = (int)((nv + kWgradVoxels - 1) / kWgradVoxels);
     hipStream_t st = (hipStream_t)stream;
     const dim3 grid(nchunk, pad16(kTaps * pad4(ci)) / 16, pad16(co) / 16);
-    hipLaunchKernelGGL(conv_wgrad_kernel, grid, dim3(256), 0, st, x, gz, n, d, h, wd, ci, co, work);
+    if (wd % 4 == 0 && pad4(ci) == 16)
+        hipLaunchKernelGGL(conv_wgrad_ci<16>, grid, dim3(256), 0, st, x, gz, n, d, h, wd, ci, co, work);
+    else if (wd % 4 == 0 && pad4(ci) == 4)
+        hipLaunchKernelGGL(conv_wgrad_ci<4>, grid, dim3(256), 0, st, x, gz, n, d, h, wd, ci, co, work);
+    else
+        hipLaunchKernelGGL(conv_wgrad_kernel, grid, dim3(256), 0, st, x, gz, n, d, h, wd, ci, co, work);
     hipLaunchKernelGGL(grad_fold_kernel, dim3(blocks_for((int64_t)co * kTaps * ci + co, 64)), dim3(64 * kFoldWaves),
                        0, st, work, nchunk, ci, co, gw, gb);
     return launched();

@@ -56,7 +56,12 @@ def _forward(torch, cnn, x, w, b, relu, flip=False):
     return y.cpu().numpy().astype(np.float64).reshape(n, d, h, wd, cnn.pad4(cout))
 
 
-_SHAPES = [((2, 5, 6, 7), 5, 16), ((1, 9, 4, 11), 16, 16), ((3, 3, 5, 4), 16, 1), ((1, 16, 16, 16), 16, 7)]
+# channel counts 5 and 128 take the generic kernels; 4 (padded: 3, 4) and 16 the
+# specialised ones (rows of any width in the forward, of a multiple of 4 voxels
+# in the weight gradient, whose voxel walk then wraps rows, slices and batch
+# entries within a step when a row is shorter than 16)
+_SHAPES = [((2, 5, 6, 7), 5, 16), ((1, 9, 4, 11), 16, 16), ((3, 3, 5, 4), 16, 1), ((1, 16, 16, 16), 16, 7),
+           ((2, 5, 6, 7), 3, 16), ((2, 4, 3, 5), 4, 5)]
 
 
 @pytest.mark.parametrize("relu", [0, 1])
@@ -131,8 +136,9 @@ def test_conv_mask_is_relu_backward(env):
     assert (b[~(act > 0)] == 0).all()
 
 
-# the last case: a wide layer (216 x 8 output tiles of 16 x 16)
-_WSHAPES = [((2, 5, 6, 7), 5, 16), ((1, 16, 16, 17), 16, 16), ((2, 8, 8, 8), 16, 1), ((1, 3, 4, 5), 128, 128)]
+# the fourth case: a wide layer (216 x 8 output tiles of 16 x 16)
+_WSHAPES = [((2, 5, 6, 7), 5, 16), ((1, 16, 16, 17), 16, 16), ((2, 8, 8, 8), 16, 1), ((1, 3, 4, 5), 128, 128),
+            ((2, 6, 8, 12), 4, 16), ((3, 5, 2, 4), 16, 16), ((2, 3, 3, 8), 3, 7)]
 
 
 @pytest.mark.parametrize("case", _WSHAPES, ids=[f"{c[0]}_{c[1]}to{c[2]}" for c in _WSHAPES])
