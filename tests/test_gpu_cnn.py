@@ -59,9 +59,11 @@ def _forward(torch, cnn, x, w, b, relu, flip=False):
 # channel counts 5 and 128 take the generic kernels; 4 (padded: 3, 4) and 16 the
 # specialised ones (rows of any width in the forward, of a multiple of 4 voxels
 # in the weight gradient, whose voxel walk then wraps rows, slices and batch
-# entries within a step when a row is shorter than 16)
+# entries within a step when a row is shorter than 16); rows of 16 voxels, as
+# in the predictor's block grids, with 4 and 16 channels
 _SHAPES = [((2, 5, 6, 7), 5, 16), ((1, 9, 4, 11), 16, 16), ((3, 3, 5, 4), 16, 1), ((1, 16, 16, 16), 16, 7),
-           ((2, 5, 6, 7), 3, 16), ((2, 4, 3, 5), 4, 5)]
+           ((2, 5, 6, 7), 3, 16), ((2, 4, 3, 5), 4, 5), ((2, 3, 5, 16), 4, 16), ((3, 2, 8, 16), 16, 20)]
+_DSHAPES = _SHAPES[:3] + [((2, 3, 5, 16), 16, 1), ((1, 4, 6, 16), 16, 16)]
 
 
 @pytest.mark.parametrize("relu", [0, 1])
@@ -86,7 +88,7 @@ def test_conv_forward(env, case, relu):
     assert (y[..., co:] == 0).all(), "padding channels must be zero"
 
 
-@pytest.mark.parametrize("case", _SHAPES[:3], ids=[f"{c[0]}_{c[1]}to{c[2]}" for c in _SHAPES[:3]])
+@pytest.mark.parametrize("case", _DSHAPES, ids=[f"{c[0]}_{c[1]}to{c[2]}" for c in _DSHAPES])
 def test_conv_data_gradient(env, case):
     """Forward kernel with flip-packed weights = gradient with respect to the
     input."""
