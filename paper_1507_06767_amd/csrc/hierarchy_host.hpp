@@ -447,7 +447,10 @@ lbm_status lbm_create_hierarchy(lbm_blocks *coarse, int32_t nbox, const lbm_box 
     // ghost copies from the patch that holds its cell, else it carries the low
     // corner of its coarse interpolation stencil and the 3/4-weight bits.
     // Faces own their cells without overlap: x faces whole, y faces without
-    // the x rims, z faces without the x and y rims.
+    // the x rims, z faces without the x and y rims.  The two faces normal to
+    // an axis alternate piece by piece: the pieces of the low and the high x
+    // face at the same (y, z) read the same coarse rows (two cells at each
+    // end), and as neighbours in the list they run side by side on one XCD.
     std::vector<uint32_t> gdst;
     std::vector<int> gsrc;
     std::vector<GhostTile> gtiles;
@@ -463,78 +466,80 @@ lbm_status lbm_create_hierarchy(lbm_blocks *coarse, int32_t nbox, const lbm_box 
     for (int p = 0; p < H->npatch; ++p) {
         const PatchRec &r = H->rec[p];
         const int P[3] = {r.e[0] + 2, r.e[1] + 2, r.e[2] + 2};
-        for (int f = 0; f < 6; ++f) {
-            const int na = f / 2, ua = (na == 0) ? 1 : 0, va = (na == 2) ? 1 : 2;
-            const int pn = (f & 1) ? P[na] - 1 : 0;
+        for (int na = 0; na < 3; ++na) {
+            const int ua = (na == 0) ? 1 : 0, va = (na == 2) ? 1 : 2;
             const int ulo = (na == 0) ? 0 : 1, uhi = (na == 0) ? P[1] : P[0] - 1;
             const int vlo = (na == 2) ? 1 : 0, vhi = (na == 2) ? P[1] - 1 : P[2];
             for (int v0 = vlo; v0 < vhi; v0 += 16)
-                for (int u0 = ulo; u0 < uhi; u0 += 16) {
-                    GhostTile t{};
-                    t.k0 = (int)gdst.size();
-                    std::vector<std::array<int, 3>> corner;   // stencil corner of each entry (-1: copy)
-                    int bmin[3] = {1 << 30, 1 << 30, 1 << 30}, bmax[3] = {-1, -1, -1};
-                    for (int vv = v0; vv < std::min(v0 + 16, vhi); ++vv)
-                        for (int uu = u0; uu < std::min(u0 + 16, uhi); ++uu) {
-                            int pc[3];
-                            pc[na] = pn;
-                            pc[ua] = uu;
-                            pc[va] = vv;
-                            const int g[3] = {r.o[0] + pc[0] - 1, r.o[1] + pc[1] - 1, r.o[2] + pc[2] - 1};
-                            // an x-face ghost lives in its side's compact array [pc2][pc1]
-                            const uint32_t dst =
-                                (na == 0) ? (uint32_t)(r.xoff + ((int64_t)(f & 1) * P[2] + pc[2]) * P[1] + pc[1])
-                                          : (uint32_t)(r.off + ((int64_t)pc[2] * P[1] + pc[1]) * P[0] + pc[0]);
-                            uint32_t need = 0;   // populations an interior cell pulls from this ghost
-                            for (int i = 0; i < H->q; ++i) {
-                                bool in = true;
-                                for (int a = 0; a < 3; ++a) {
-                                    const int t2 = pc[a] + vel[i][a];
-                                    in = in && t2 >= 1 && t2 <= P[a] - 2;
+                for (int u0 = ulo; u0 < uhi; u0 += 16)
+                    for (int f = 2 * na; f < 2 * na + 2; ++f) {   // the low face's piece, then the high face's
+                        const int pn = (f & 1) ? P[na] - 1 : 0;
+                        GhostTile t{};
+                        t.k0 = (int)gdst.size();
+                        std::vector<std::array<int, 3>> corner;   // stencil corner of each entry (-1: copy)
+                        int bmin[3] = {1 << 30, 1 << 30, 1 << 30}, bmax[3] = {-1, -1, -1};
+                        for (int vv = v0; vv < std::min(v0 + 16, vhi); ++vv)
+                            for (int uu = u0; uu < std::min(u0 + 16, uhi); ++uu) {
+                                int pc[3];
+                                pc[na] = pn;
+                                pc[ua] = uu;
+                                pc[va] = vv;
+                                const int g[3] = {r.o[0] + pc[0] - 1, r.o[1] + pc[1] - 1, r.o[2] + pc[2] - 1};
+                                // an x-face ghost lives in its side's compact array [pc2][pc1]
+                                const uint32_t dst =
+                                    (na == 0) ? (uint32_t)(r.xoff + ((int64_t)(f & 1) * P[2] + pc[2]) * P[1] + pc[1])
+                                              : (uint32_t)(r.off + ((int64_t)pc[2] * P[1] + pc[1]) * P[0] + pc[0]);
+                                uint32_t need = 0;   // populations an interior cell pulls from this ghost
+                                for (int i = 0; i < H->q; ++i) {
+                                    bool in = true;
+                                    for (int a = 0; a < 3; ++a) {
+                                        const int t2 = pc[a] + vel[i][a];
+                                        in = in && t2 >= 1 && t2 <= P[a] - 2;
+                                    }
+                                    if (in) need |= 1u << i;
                                 }
-                                if (in) need |= 1u << i;
+                                if (na == 0) need |= kGhostXFace;
+                                gmask.push_back(need);
+                                const int owner = cover[((size_t)(g[2] >> 1) * ny + (g[1] >> 1)) * nx + (g[0] >> 1)];
+                                if (owner >= 0) {
+                                    const PatchRec &o = H->rec[owner];
+                                    const int64_t src =
+                                        o.off + ((int64_t)(g[2] - o.o[2] + 1) * (o.e[1] + 2) + (g[1] - o.o[1] + 1)) *
+                                                    (o.e[0] + 2) + (g[0] - o.o[0] + 1);
+                                    gdst.push_back(dst);
+                                    gsrc.push_back((int)src);
+                                    corner.push_back({-1, -1, -1});
+                                    continue;
+                                }
+                                // centre (g + 1/2) / 2 - 1/2: even g -> g/2 - 1 + 3/4, odd g -> (g - 1)/2 + 1/4
+                                uint32_t code = 0;
+                                int b[3];
+                                for (int a = 0; a < 3; ++a) {
+                                    const bool even = (g[a] & 1) == 0;
+                                    b[a] = even ? g[a] / 2 - 1 : (g[a] - 1) / 2;
+                                    if (even) code |= 1u << (29 + a);
+                                    bmin[a] = std::min(bmin[a], b[a]);
+                                    bmax[a] = std::max(bmax[a], b[a] + 1);
+                                }
+                                gdst.push_back(dst | code);
+                                gsrc.push_back((int)(-(((int64_t)b[2] * ny + b[1]) * nx + b[0]) - 1));
+                                corner.push_back({b[0], b[1], b[2]});
                             }
-                            if (na == 0) need |= kGhostXFace;
-                            gmask.push_back(need);
-                            const int owner = cover[((size_t)(g[2] >> 1) * ny + (g[1] >> 1)) * nx + (g[0] >> 1)];
-                            if (owner >= 0) {
-                                const PatchRec &o = H->rec[owner];
-                                const int64_t src =
-                                    o.off + ((int64_t)(g[2] - o.o[2] + 1) * (o.e[1] + 2) + (g[1] - o.o[1] + 1)) *
-                                                (o.e[0] + 2) + (g[0] - o.o[0] + 1);
-                                gdst.push_back(dst);
-                                gsrc.push_back((int)src);
-                                corner.push_back({-1, -1, -1});
-                                continue;
-                            }
-                            // centre (g + 1/2) / 2 - 1/2: even g -> g/2 - 1 + 3/4, odd g -> (g - 1)/2 + 1/4
-                            uint32_t code = 0;
-                            int b[3];
-                            for (int a = 0; a < 3; ++a) {
-                                const bool even = (g[a] & 1) == 0;
-                                b[a] = even ? g[a] / 2 - 1 : (g[a] - 1) / 2;
-                                if (even) code |= 1u << (29 + a);
-                                bmin[a] = std::min(bmin[a], b[a]);
-                                bmax[a] = std::max(bmax[a], b[a] + 1);
-                            }
-                            gdst.push_back(dst | code);
-                            gsrc.push_back((int)(-(((int64_t)b[2] * ny + b[1]) * nx + b[0]) - 1));
-                            corner.push_back({b[0], b[1], b[2]});
+                        t.n = (int)gdst.size() - t.k0;
+                        if (bmax[0] >= 0) {
+                            t.ox = bmin[0];
+                            t.oy = bmin[1];
+                            t.oz = bmin[2];
+                            t.dx = bmax[0] - bmin[0] + 1;
+                            t.dy = bmax[1] - bmin[1] + 1;
+                            t.dz = bmax[2] - bmin[2] + 1;
+                            if (t.dx * t.dy * t.dz > kGhostBox || t.n > 256) tiles_ok = false;
                         }
-                    t.n = (int)gdst.size() - t.k0;
-                    if (bmax[0] >= 0) {
-                        t.ox = bmin[0];
-                        t.oy = bmin[1];
-                        t.oz = bmin[2];
-                        t.dx = bmax[0] - bmin[0] + 1;
-                        t.dy = bmax[1] - bmin[1] + 1;
-                        t.dz = bmax[2] - bmin[2] + 1;
-                        if (t.dx * t.dy * t.dz > kGhostBox || t.n > 256) tiles_ok = false;
+                        for (const auto &c : corner)
+                            gloc.push_back(c[0] < 0 ? 0
+                                                    : ((c[2] - t.oz) * t.dy + (c[1] - t.oy)) * t.dx + (c[0] - t.ox));
+                        gtiles.push_back(t);
                     }
-                    for (const auto &c : corner)
-                        gloc.push_back(c[0] < 0 ? 0 : ((c[2] - t.oz) * t.dy + (c[1] - t.oy)) * t.dx + (c[0] - t.ox));
-                    gtiles.push_back(t);
-                }
         }
     }
     H->ngtile = tiles_ok ? (int64_t)gtiles.size() : 0;
