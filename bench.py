@@ -292,7 +292,8 @@ def run_refined(args, lbm, torch):
                    "work_vs_uniform_fine": round((coarse_cells + 2 * fine_cells) / uniform_fine_updates, 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "patch_step (all patches, one persistent launch)",
+                     "kernel": ("patch_band_step" if tx == 48 else f"patch_step (W = {tx})")
+                               + " (the fine step over all patches, one persistent launch)",
                      "algorithmic_bytes_per_launch": fine_bytes,
                      "per_kernel_us": {"patch_step": round(prof["fine"], 2), "patch_ghosts": round(prof["ghosts"], 2),
                                        "patch_step_with_restriction": round(prof["fine_restrict"], 2),
