@@ -65,6 +65,13 @@ int64_t lbm_cnn_wgrad_workspace(int32_t n, int32_t d, int32_t h, int32_t wd, int
 int32_t lbm_cnn_conv3d_wgrad(const float *x, const float *gz, int32_t n, int32_t d, int32_t h, int32_t wd,
                              int32_t ci, int32_t co, float *work, float *gw, float *gb, void *stream);
 
+/* The first half of lbm_cnn_conv3d_wgrad: only the per-chunk partial sums,
+ * in `work` (lbm_cnn_wgrad_workspace bytes), for a later
+ * lbm_cnn_adam_layer_fold, which folds them; the workspace must then stay
+ * untouched until that call. */
+int32_t lbm_cnn_conv3d_wgrad_partials(const float *x, const float *gz, int32_t n, int32_t d, int32_t h, int32_t wd,
+                                      int32_t ci, int32_t co, float *work, void *stream);
+
 /* g[i] = (a[i] > 0) ? g[i] : 0 for i < count (ReLU backward, in place). */
 int32_t lbm_cnn_relu_backward(const float *a, float *g, int64_t count, void *stream);
 
@@ -106,6 +113,16 @@ int32_t lbm_cnn_adam_dev(float *w, const float *g, float *m, float *v, int64_t c
 int32_t lbm_cnn_adam_layer(float *w, float *b, const float *gw, const float *gb, float *mw, float *vw, float *mb,
                            float *vb, int32_t co, int32_t ci, uint16_t *packed, uint16_t *packed_flip,
                            const float *hyper, void *stream);
+
+/* lbm_cnn_adam_layer taking the gradient as the partial sums that
+ * lbm_cnn_conv3d_wgrad_partials left in `work` for the batch shape
+ * (n, d, h, wd): the fold of lbm_cnn_conv3d_wgrad and the update in one
+ * launch, the same bits as lbm_cnn_conv3d_wgrad followed by
+ * lbm_cnn_adam_layer.  gw [co][27][ci] and gb [co] receive the folded
+ * gradient when not NULL.  -1 on a NULL pointer or a size < 1. */
+int32_t lbm_cnn_adam_layer_fold(float *w, float *b, const float *work, int32_t n, int32_t d, int32_t h, int32_t wd,
+                                float *mw, float *vw, float *mb, float *vb, int32_t co, int32_t ci, uint16_t *packed,
+                                uint16_t *packed_flip, const float *hyper, float *gw, float *gb, void *stream);
 
 #ifdef __cplusplus
 }

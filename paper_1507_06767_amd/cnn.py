@@ -33,6 +33,9 @@ _SIG = {
     "lbm_cnn_adam_begin": ([_P, _F, _F, _F, _F, _P], _I32),
     "lbm_cnn_adam_dev": ([_P, _P, _P, _P, _I64, _P, _P], _I32),
     "lbm_cnn_adam_layer": ([_P] * 8 + [_I32, _I32, _P, _P, _P, _P], _I32),
+    "lbm_cnn_conv3d_wgrad_partials": ([_P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P], _I32),
+    "lbm_cnn_adam_layer_fold": ([_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _I32, _I32, _P, _P, _P, _P,
+                                 _P, _P], _I32),
 }
 for _name, (_args, _res) in _SIG.items():
     _fn = getattr(_lib, _name)
@@ -96,6 +99,14 @@ def lbm_cnn_conv3d_wgrad(x, gz, n, d, h, wd, ci, co, work, gw, gb, stream=None):
         _stream(stream))
 
 
+def lbm_cnn_conv3d_wgrad_partials(x, gz, n, d, h, wd, ci, co, work, stream=None):
+    nv = n * d * h * wd
+    ws = lbm_cnn_wgrad_workspace(n, d, h, wd, ci, co) // 4
+    return _lib.lbm_cnn_conv3d_wgrad_partials(
+        _ptr(x, torch.float32, nv * pad4(ci), "x"), _ptr(gz, torch.float32, nv * pad4(co), "gz"),
+        n, d, h, wd, ci, co, _ptr(work, torch.float32, ws, "work"), _stream(stream))
+
+
 def lbm_cnn_relu_backward(a, g, count, stream=None):
     return _lib.lbm_cnn_relu_backward(_ptr(a, torch.float32, count, "a"), _ptr(g, torch.float32, count, "g"),
                                       int(count), _stream(stream))
@@ -136,3 +147,17 @@ def lbm_cnn_adam_layer(w, b, gw, gb, mw, vw, mb, vb, co, ci, packed, packed_flip
                                    _ptr(packed, torch.int16, lbm_cnn_packed_size(co, ci), "packed", 8),
                                    _ptr(packed_flip, torch.int16, lbm_cnn_packed_size(ci, co), "packed_flip", 8),
                                    _ptr(hyper, torch.float32, LBM_CNN_HYPER_FLOATS, "hyper"), _stream(stream))
+
+
+def lbm_cnn_adam_layer_fold(w, b, work, n, d, h, wd, mw, vw, mb, vb, co, ci, packed, packed_flip, hyper,
+                            gw=None, gb=None, stream=None):
+    nw, nb = co * LBM_CNN_TAPS * ci, co
+    ws = lbm_cnn_wgrad_workspace(n, d, h, wd, ci, co) // 4
+    return _lib.lbm_cnn_adam_layer_fold(
+        _ptr(w, torch.float32, nw, "w"), _ptr(b, torch.float32, nb, "b"), _ptr(work, torch.float32, ws, "work"),
+        n, d, h, wd, _ptr(mw, torch.float32, nw, "mw"), _ptr(vw, torch.float32, nw, "vw"),
+        _ptr(mb, torch.float32, nb, "mb"), _ptr(vb, torch.float32, nb, "vb"), int(co), int(ci),
+        _ptr(packed, torch.int16, lbm_cnn_packed_size(co, ci), "packed", 8),
+        _ptr(packed_flip, torch.int16, lbm_cnn_packed_size(ci, co), "packed_flip", 8),
+        _ptr(hyper, torch.float32, LBM_CNN_HYPER_FLOATS, "hyper"), _ptr(gw, torch.float32, nw, "gw"),
+        _ptr(gb, torch.float32, nb, "gb"), _stream(stream))

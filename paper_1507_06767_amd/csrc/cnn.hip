@@ -402,13 +402,15 @@ __global__ __launch_bounds__(256) void conv_wgrad_ci(const float *x, const float
 // is deterministic, with 8 loads per lane in flight instead of a chain of
 // nchunk.
 constexpr int kFoldWaves = 8;
-__global__ __launch_bounds__(64 * kFoldWaves) void grad_fold_kernel(const float *work, int nchunk, int ci, int co,
-                                                                    float *gw, float *gb) {
+// The fold of output blockIdx.x * 64 + lane (with_bias: biases included);
+// valid in wave 0, whose lanes return the sums; ok tells whether the
+// lane's output exists.
+__device__ inline float fold_output(const float *work, int nchunk, int ci, int co, bool with_bias, bool &ok) {
     const int ci4 = pad4(ci), k16 = pad16(kTaps * ci4), co16 = pad16(co);
     const int nw = co * kTaps * ci;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int idx = blockIdx.x * 64 + lane;
-    const bool is_w = idx < nw, is_b = !is_w && gb && idx < nw + co;
+    const bool is_w = idx < nw, is_b = !is_w && with_bias && idx < nw + co;
     // partial of chunk ch for this output: base + ch * stride
     int64_t base = 0, stride = 0;
     if (is_w) {
@@ -427,12 +429,21 @@ __global__ __launch_bounds__(64 * kFoldWaves) void grad_fold_kernel(const float 
     __shared__ float part[kFoldWaves][64];
     part[wave][lane] = s;
     __syncthreads();
-    if (wave != 0 || !(is_w || is_b)) return;
-    const float t = ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) +
-                    ((part[4][lane] + part[5][lane]) + (part[6][lane] + part[7][lane]));
-    if (is_w) gw[idx] = t;
+    ok = is_w || is_b;
+    return ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) +
+           ((part[4][lane] + part[5][lane]) + (part[6][lane] + part[7][lane]));
+}
+
+__global__ __launch_bounds__(64 * kFoldWaves) void grad_fold_kernel(const float *work, int nchunk, int ci, int co,
+                                                                    float *gw, float *gb) {
+    bool ok;
+    const float t = fold_output(work, nchunk, ci, co, gb != nullptr, ok);
+    if (threadIdx.x >= 64 || !ok) return;
+    const int nw = co * kTaps * ci, idx = blockIdx.x * 64 + threadIdx.x;
+    if (idx < nw) gw[idx] = t;
     else gb[idx - nw] = t;
 }
+
 
 __global__ void relu_backward_kernel(const float *a, float *g, int64_t count) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -508,12 +519,12 @@ __device__ inline uint16_t to_bf16_bits(float v) { return __builtin_bit_cast(uin
 // [co] in one launch, the arithmetic of adam_dev_kernel; each updated weight
 // is also written to both packed forms (the layouts of pack_kernel with flip
 // 0 and 1), whose padding entries stay as they are.
-__global__ void adam_layer_kernel(float *w, float *b, const float *gw, const float *gb, float *mw, float *vw,
-                                  float *mb, float *vb, int co, int ci, uint16_t *packed, uint16_t *packed_flip,
-                                  const float *hyper) {
+// The Adam step of parameter idx of a layer (weights [co][27][ci] first, then
+// the co biases) with gradient gi, and the packed BF16 copies of a weight.
+__device__ inline void adam_layer_param(int idx, float gi, float *w, float *b, float *mw, float *vw, float *mb,
+                                        float *vb, int co, int ci, uint16_t *packed, uint16_t *packed_flip,
+                                        const float *hyper) {
     const int nw = co * kTaps * ci;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= nw + co) return;
     const float lr = hyper[0], b1 = hyper[1], b2 = hyper[2], eps = hyper[3], t = hyper[4];
     const float c1 = 1.0f - powf(b1, t), c2 = 1.0f - powf(b2, t);
     const bool is_w = idx < nw;
@@ -521,7 +532,6 @@ __global__ void adam_layer_kernel(float *w, float *b, const float *gw, const flo
     float *p = is_w ? w : b;
     float *m = is_w ? mw : mb;
     float *v = is_w ? vw : vb;
-    const float gi = is_w ? gw[i] : gb[i];
     const float mi = b1 * m[i] + (1.0f - b1) * gi;
     const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
     m[i] = mi;
@@ -537,6 +547,37 @@ __global__ void adam_layer_kernel(float *w, float *b, const float *gw, const flo
     }
 }
 
+__global__ void adam_layer_kernel(float *w, float *b, const float *gw, const float *gb, float *mw, float *vw,
+                                  float *mb, float *vb, int co, int ci, uint16_t *packed, uint16_t *packed_flip,
+                                  const float *hyper) {
+    const int nw = co * kTaps * ci;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nw + co) return;
+    const float gi = idx < nw ? gw[idx] : gb[idx - nw];
+    adam_layer_param(idx, gi, w, b, mw, vw, mb, vb, co, ci, packed, packed_flip, hyper);
+}
+
+// The fold and the Adam step of a layer in one launch: wave 0 of each
+// workgroup applies Adam to the 64 sums it folded (the same sums, and the
+// same update, as grad_fold_kernel followed by adam_layer_kernel; gw, gb
+// receive the gradient when given).
+__global__ __launch_bounds__(64 * kFoldWaves) void adam_fold_kernel(const float *work, int nchunk, float *w, float *b,
+                                                                    float *mw, float *vw, float *mb, float *vb,
+                                                                    int co, int ci, uint16_t *packed,
+                                                                    uint16_t *packed_flip, const float *hyper,
+                                                                    float *gw, float *gb) {
+    bool ok;
+    const float t = fold_output(work, nchunk, ci, co, true, ok);
+    if (threadIdx.x >= 64 || !ok) return;
+    const int nw = co * kTaps * ci, idx = blockIdx.x * 64 + threadIdx.x;
+    if (idx < nw) {
+        if (gw) gw[idx] = t;
+    } else if (gb) {
+        gb[idx - nw] = t;
+    }
+    adam_layer_param(idx, t, w, b, mw, vw, mb, vb, co, ci, packed, packed_flip, hyper);
+}
+
 // Opens an optimizer step: hyper[0..3] = (lr, beta1, beta2, eps), hyper[4] += 1.
 __global__ void adam_begin_kernel(float *hyper, float lr, float b1, float b2, float eps) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -550,6 +591,18 @@ __global__ void adam_begin_kernel(float *hyper, float lr, float b1, float b2, fl
 int32_t launched() { return hipGetLastError() == hipSuccess ? 0 : -3; }
 
 unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// The weight-gradient partials (the specialised kernel where it applies).
+void launch_wgrad(const float *x, const float *gz, int n, int d, int h, int wd, int ci, int co, float *work,
+                  int nchunk, hipStream_t st) {
+    const dim3 grid(nchunk, pad16(kTaps * pad4(ci)) / 16, pad16(co) / 16);
+    if (wd % 4 == 0 && pad4(ci) == 16)
+        hipLaunchKernelGGL(conv_wgrad_ci<16>, grid, dim3(256), 0, st, x, gz, n, d, h, wd, ci, co, work);
+    else if (wd % 4 == 0 && pad4(ci) == 4)
+        hipLaunchKernelGGL(conv_wgrad_ci<4>, grid, dim3(256), 0, st, x, gz, n, d, h, wd, ci, co, work);
+    else
+        hipLaunchKernelGGL(conv_wgrad_kernel, grid, dim3(256), 0, st, x, gz, n, d, h, wd, ci, co, work);
+}
 
 }  // namespace
 
@@ -604,15 +657,19 @@ int32_t lbm_cnn_conv3d_wgrad(const float *x, const float *gz, int32_t n, int32_t
     if (nv >= (int64_t(1) << 31)) return -1;
     const int nchunk = (int)((nv + kWgradVoxels - 1) / kWgradVoxels);
     hipStream_t st = (hipStream_t)stream;
-    const dim3 grid(nchunk, pad16(kTaps * pad4(ci)) / 16, pad16(co) / 16);
-    if (wd % 4 == 0 && pad4(ci) == 16)
-        hipLaunchKernelGGL(conv_wgrad_ci<16>, grid, dim3(256), 0, st, x, gz, n, d, h, wd, ci, co, work);
-    else if (wd % 4 == 0 && pad4(ci) == 4)
-        hipLaunchKernelGGL(conv_wgrad_ci<4>, grid, dim3(256), 0, st, x, gz, n, d, h, wd, ci, co, work);
-    else
-        hipLaunchKernelGGL(conv_wgrad_kernel, grid, dim3(256), 0, st, x, gz, n, d, h, wd, ci, co, work);
+    launch_wgrad(x, gz, n, d, h, wd, ci, co, work, nchunk, st);
     hipLaunchKernelGGL(grad_fold_kernel, dim3(blocks_for((int64_t)co * kTaps * ci + co, 64)), dim3(64 * kFoldWaves),
                        0, st, work, nchunk, ci, co, gw, gb);
+    return launched();
+}
+
+int32_t lbm_cnn_conv3d_wgrad_partials(const float *x, const float *gz, int32_t n, int32_t d, int32_t h, int32_t wd,
+                                      int32_t ci, int32_t co, float *work, void *stream) {
+    if (!x || !gz || !work || n < 1 || d < 1 || h < 1 || wd < 1 || ci < 1 || co < 1) return -1;
+    const int64_t nv = (int64_t)n * d * h * wd;
+    if (nv >= (int64_t(1) << 31)) return -1;
+    const int nchunk = (int)((nv + kWgradVoxels - 1) / kWgradVoxels);
+    launch_wgrad(x, gz, n, d, h, wd, ci, co, work, nchunk, (hipStream_t)stream);
     return launched();
 }
 
@@ -660,6 +717,21 @@ int32_t lbm_cnn_adam_layer(float *w, float *b, const float *gw, const float *gb,
     const int64_t n = (int64_t)co * kTaps * ci + co;
     hipLaunchKernelGGL(adam_layer_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, w, b, gw, gb,
                        mw, vw, mb, vb, co, ci, packed, packed_flip, hyper);
+    return launched();
+}
+
+int32_t lbm_cnn_adam_layer_fold(float *w, float *b, const float *work, int32_t n, int32_t d, int32_t h, int32_t wd,
+                                float *mw, float *vw, float *mb, float *vb, int32_t co, int32_t ci, uint16_t *packed,
+                                uint16_t *packed_flip, const float *hyper, float *gw, float *gb, void *stream) {
+    if (!w || !b || !work || !mw || !vw || !mb || !vb || !packed || !packed_flip || !hyper || co < 1 || ci < 1 ||
+        n < 1 || d < 1 || h < 1 || wd < 1)
+        return -1;
+    const int64_t nv = (int64_t)n * d * h * wd;
+    if (nv >= (int64_t(1) << 31) || (int64_t)co * kTaps * ci + co >= (int64_t(1) << 31)) return -1;
+    const int nchunk = (int)((nv + kWgradVoxels - 1) / kWgradVoxels);
+    hipLaunchKernelGGL(adam_fold_kernel, dim3(blocks_for((int64_t)co * kTaps * ci + co, 64)), dim3(64 * kFoldWaves),
+                       0, (hipStream_t)stream, work, nchunk, w, b, mw, vw, mb, vb, co, ci, packed, packed_flip, hyper,
+                       gw, gb);
     return launched();
 }
 

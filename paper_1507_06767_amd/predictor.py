@@ -120,7 +120,11 @@ class FlagPredictor:
             acts = [z(L.co) for L in self.layers]
             grads = [z(c) for c in self.channels[:-1]] + [z(self.channels[-1])]
             ws = max(cnn.lbm_cnn_wgrad_workspace(n, d, h, w, L.ci, L.co) for L in self.layers) // 4
-            self._bufs[shape] = dict(x=z(self.channels[0]), acts=acts, grads=grads,
+            # per-layer partial sums of the weight gradients, kept until the
+            # fused fold-and-Adam launches of a training step
+            works = [torch.zeros(cnn.lbm_cnn_wgrad_workspace(n, d, h, w, L.ci, L.co) // 4, dtype=torch.float32,
+                                 device=self.device) for L in self.layers]
+            self._bufs[shape] = dict(x=z(self.channels[0]), acts=acts, grads=grads, works=works,
                                      work=torch.zeros(ws, dtype=torch.float32, device=self.device),
                                      target=torch.zeros(nv, dtype=torch.float32, device=self.device),
                                      loss=torch.zeros(cnn.LBM_CNN_LOSS_FLOATS, dtype=torch.float32,
@@ -148,8 +152,10 @@ class FlagPredictor:
             a = out
         return a
 
-    def backward_device(self, shape):
-        """Gradients of the loss whose output gradient is in grads[-1]."""
+    def backward_device(self, shape, partials=False):
+        """Gradients of the loss whose output gradient is in grads[-1]; with
+        `partials`, the weight gradients stay as per-layer partial sums for
+        adam_step_partials (which folds them)."""
         B = self._buffers(shape)
         n, d, h, w = shape
         nv = n * d * h * w
@@ -160,8 +166,12 @@ class FlagPredictor:
         for k in range(len(self.layers) - 1, -1, -1):
             L = self.layers[k]
             inp = B["x"] if k == 0 else B["acts"][k - 1]
-            _check(cnn.lbm_cnn_conv3d_wgrad(inp, g, n, d, h, w, L.ci, L.co, B["work"], L.gw, L.gb, self.stream),
-                   "wgrad")
+            if partials:
+                _check(cnn.lbm_cnn_conv3d_wgrad_partials(inp, g, n, d, h, w, L.ci, L.co, B["works"][k],
+                                                         self.stream), "wgrad partials")
+            else:
+                _check(cnn.lbm_cnn_conv3d_wgrad(inp, g, n, d, h, w, L.ci, L.co, B["work"], L.gw, L.gb,
+                                                self.stream), "wgrad")
             if k > 0:
                 # gradient at the input of layer k, through the ReLU of layer k - 1
                 gin = B["grads"][k]
@@ -178,15 +188,16 @@ class FlagPredictor:
         B["target"].copy_(torch.from_numpy(np.ascontiguousarray(target, dtype=np.float32).reshape(-1)))
         return shape
 
-    def loss_and_grads_device(self, shape):
-        """Loss and gradients (in each layer's gw, gb) on the loaded batch;
-        returns the device loss tensor (element 0)."""
+    def loss_and_grads_device(self, shape, partials=False):
+        """Loss and gradients (in each layer's gw, gb; with `partials`, as
+        per-layer partial sums) on the loaded batch; returns the device loss
+        tensor (element 0)."""
         B = self._buffers(shape)
         y = self.forward_device(shape)
         nv = int(np.prod(shape))
         _check(cnn.lbm_cnn_mse(y, cnn.pad4(self.channels[-1]), B["target"], nv, B["grads"][-1], B["loss"],
                                self.stream), "mse")
-        self.backward_device(shape)
+        self.backward_device(shape, partials)
         return B["loss"]
 
     def loss_and_grads(self, x, target):
@@ -203,11 +214,25 @@ class FlagPredictor:
             _check(cnn.lbm_cnn_adam_layer(L.w, L.b, L.gw, L.gb, L.mw, L.vw, L.mb, L.vb, L.co, L.ci, L.packed,
                                           L.packed_flip, self.hyper, self.stream), "adam")
 
+    def adam_step_partials(self, shape, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        """adam_step from the per-layer partial sums that
+        backward_device(shape, partials=True) left: each layer's fold and
+        update in one launch (the same bits; gw, gb are filled too)."""
+        B = self._buffers(shape)
+        n, d, h, w = shape
+        self.t += 1
+        _check(cnn.lbm_cnn_adam_begin(self.hyper, lr, beta1, beta2, eps, self.stream), "adam begin")
+        for L, work in zip(self.layers, B["works"]):
+            _check(cnn.lbm_cnn_adam_layer_fold(L.w, L.b, work, n, d, h, w, L.mw, L.vw, L.mb, L.vb, L.co, L.ci,
+                                               L.packed, L.packed_flip, self.hyper, L.gw, L.gb, self.stream),
+                   "adam fold")
+
     def train_step(self, shape, lr):
         """One training iteration (forward, loss, backward, Adam) on the
-        loaded batch, without host transfers."""
-        self.loss_and_grads_device(shape)
-        self.adam_step(lr)
+        loaded batch, without host transfers: the weight gradients' folds
+        run inside the Adam launches (18 launches)."""
+        self.loss_and_grads_device(shape, partials=True)
+        self.adam_step_partials(shape, lr)
 
     def capture_train_step(self, shape, lr):
         """A HIP graph of one training iteration on the loaded batch at a
@@ -265,8 +290,9 @@ class FlagPredictor:
         S = raw.shape[0]
         for it in range(iters):
             idx = rng.choice(S, size=min(batch, S), replace=False)
-            loss = self.loss_and_grads(xs[idx], dy[idx])
-            self.adam_step(lr * 0.5 * (1.0 + math.cos(math.pi * it / iters)))
+            shape = self.load_batch(xs[idx], dy[idx])
+            loss = self.loss_and_grads_device(shape, partials=True)[0]
+            self.adam_step_partials(shape, lr * 0.5 * (1.0 + math.cos(math.pi * it / iters)))
             if log_every and (it % log_every == 0 or it + 1 == iters):
                 hist.append((it, float(loss.item())))
         return hist

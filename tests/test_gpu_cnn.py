@@ -284,6 +284,54 @@ def test_relu_backward_mse_adam(env):
     assert torch.equal(pk[0], pk[1]) and torch.equal(pkf[0], pkf[1])
 
 
+@pytest.mark.parametrize("case", [((2, 8, 8, 16), 4, 16), ((1, 5, 6, 7), 16, 1), ((2, 16, 16, 16), 16, 16)],
+                         ids=["4to16", "16to1_generic", "16to16"])
+def test_adam_layer_fold_matches_wgrad_then_adam(env, case):
+    """lbm_cnn_conv3d_wgrad_partials + lbm_cnn_adam_layer_fold (the fold
+    inside the Adam launch) against lbm_cnn_conv3d_wgrad + lbm_cnn_adam_layer,
+    three steps: identical bits in the weights, biases, both moments, both
+    packed forms and the folded gradients."""
+    torch, cnn = env
+    shape, ci, co = case
+    n, d, h, wd = shape
+    nv = n * d * h * wd
+    print(f"\n[case] fused fold + adam {shape} {ci}->{co}", flush=True)
+    rng = np.random.default_rng(23 + ci + co)
+    nw = co * 27 * ci
+    lay = {k: _dev(torch, rng.standard_normal(m) * 0.1) for k, m in
+           (("w", nw), ("b", co), ("mw", nw), ("vw", nw), ("mb", co), ("vb", co))}
+    lay["vw"].abs_()
+    lay["vb"].abs_()
+    ref = {k: v.clone() for k, v in lay.items()}
+    pk = [torch.zeros(cnn.lbm_cnn_packed_size(co, ci), dtype=torch.int16, device="cuda") for _ in range(2)]
+    pkf = [torch.zeros(cnn.lbm_cnn_packed_size(ci, co), dtype=torch.int16, device="cuda") for _ in range(2)]
+    for j in range(2):
+        assert cnn.lbm_cnn_pack_weights(lay["w"], co, ci, 0, pk[j]) == 0
+        assert cnn.lbm_cnn_pack_weights(lay["w"], co, ci, 1, pkf[j]) == 0
+    hyper = [torch.zeros(cnn.LBM_CNN_HYPER_FLOATS, dtype=torch.float32, device="cuda") for _ in range(2)]
+    ws = cnn.lbm_cnn_wgrad_workspace(n, d, h, wd, ci, co) // 4
+    work = [torch.zeros(ws, dtype=torch.float32, device="cuda") for _ in range(2)]
+    g = [torch.full((nw,), float("nan"), dtype=torch.float32, device="cuda") for _ in range(2)]
+    gb = [torch.full((co,), float("nan"), dtype=torch.float32, device="cuda") for _ in range(2)]
+    for step in range(3):
+        x = _dev(torch, _padded(rng.standard_normal(shape + (ci,)).astype(np.float32), cnn.pad4(ci)))
+        gz = _dev(torch, _padded(rng.standard_normal(shape + (co,)).astype(np.float32), cnn.pad4(co)))
+        for hp in hyper:
+            assert cnn.lbm_cnn_adam_begin(hp, 3e-3, 0.9, 0.999, 1e-8) == 0
+        assert cnn.lbm_cnn_conv3d_wgrad_partials(x, gz, n, d, h, wd, ci, co, work[0]) == 0
+        assert cnn.lbm_cnn_adam_layer_fold(lay["w"], lay["b"], work[0], n, d, h, wd, lay["mw"], lay["vw"], lay["mb"],
+                                           lay["vb"], co, ci, pk[0], pkf[0], hyper[0], g[0], gb[0]) == 0
+        assert cnn.lbm_cnn_conv3d_wgrad(x, gz, n, d, h, wd, ci, co, work[1], g[1], gb[1]) == 0
+        assert cnn.lbm_cnn_adam_layer(ref["w"], ref["b"], g[1], gb[1], ref["mw"], ref["vw"], ref["mb"], ref["vb"],
+                                      co, ci, pk[1], pkf[1], hyper[1]) == 0
+    torch.cuda.synchronize()
+    assert nv > 0 and torch.isfinite(g[0]).all()
+    for k in lay:
+        assert torch.equal(lay[k], ref[k]), k
+    assert torch.equal(pk[0], pk[1]) and torch.equal(pkf[0], pkf[1])
+    assert torch.equal(g[0], g[1]) and torch.equal(gb[0], gb[1])
+
+
 @pytest.mark.parametrize("case", [(5, 2), (6, 8)], ids=["5ch_2x16^3", "6ch_8x16^3"])
 def test_network_gradients_against_oracle(env, case):
     """A C -> 16 -> 16 -> 16 -> 1 network on B 16^3 block grids (the second
