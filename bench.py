@@ -496,7 +496,7 @@ def main():
                     help="skip the 256^3 leg of the default workload (roofline_cache_proof)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the domain would shard into z-slabs; see the design notes).", file=sys.stderr)
         sys.exit(2)
 

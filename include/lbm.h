@@ -69,7 +69,7 @@ typedef int32_t lbm_status;
 enum {
     LBM_OK = 0,
     LBM_EINVAL = -1,      /* bad argument or descriptor; nothing was enqueued */
-    LBM_ENOTSUP = -2,     /* valid but not supported by this build */
+    LBM_ENOTSUP = -2,     /* valid but not supported by this library */
     LBM_EHIP = -3,        /* a HIP call failed; lbm_last_error() has its text */
     LBM_ESTATE = -4,      /* call not valid in the handle's state */
     LBM_ENONFINITE = -5   /* a sensor block holds a NaN or Inf (data still written) */

@@ -2,7 +2,7 @@
 solver (seeded 128^3 lid-driven cavities, tests/predictor_data.py), training
 with the library's own matrix-core forward/backward kernels and Adam, and
 refine flags 64 steps ahead (M_b > 1e-3 at t + 64, the exact kinetic sensor
-of Sec. 3.2 as the judge) on held-out cavities that nothing else touches.
+of Sec. 3.2 as the reference) on held-out cavities that nothing else touches.
 
 Two networks: the configured one reads the per-block means of (rho - rho0,
 u) only; the extension also reads log10 M_b now and 64 steps earlier.  Their
