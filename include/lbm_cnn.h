@@ -72,6 +72,19 @@ int32_t lbm_cnn_conv3d_wgrad(const float *x, const float *gz, int32_t n, int32_t
 int32_t lbm_cnn_conv3d_wgrad_partials(const float *x, const float *gz, int32_t n, int32_t d, int32_t h, int32_t wd,
                                       int32_t ci, int32_t co, float *work, void *stream);
 
+/* One layer's backward pass in a single launch: the weight-gradient partial
+ * sums of lbm_cnn_conv3d_wgrad_partials (input x with ci channels, output
+ * gradient gz with co channels, into `work`) and the data gradient of
+ * lbm_cnn_conv3d_forward(gz, ..., co, packed_flip, ci, NULL, 0, mask, gin)
+ * (packed_flip from lbm_cnn_pack_weights with flip 1).  The same results as
+ * those two calls, which it makes itself for shapes outside its fused forms
+ * (4 or 16 padded channels each way, rows of a multiple of 4 voxels).  gz 16-
+ * and packed_flip 8-byte aligned; -1 on a NULL pointer (mask may be NULL)
+ * or a size < 1. */
+int32_t lbm_cnn_backward_layer(const float *x, const float *gz, int32_t n, int32_t d, int32_t h, int32_t wd,
+                               int32_t ci, int32_t co, float *work, const uint16_t *packed_flip, const float *mask,
+                               float *gin, void *stream);
+
 /* g[i] = (a[i] > 0) ? g[i] : 0 for i < count (ReLU backward, in place). */
 int32_t lbm_cnn_relu_backward(const float *a, float *g, int64_t count, void *stream);
 

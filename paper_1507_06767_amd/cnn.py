@@ -34,6 +34,7 @@ _SIG = {
     "lbm_cnn_adam_dev": ([_P, _P, _P, _P, _I64, _P, _P], _I32),
     "lbm_cnn_adam_layer": ([_P] * 8 + [_I32, _I32, _P, _P, _P, _P], _I32),
     "lbm_cnn_conv3d_wgrad_partials": ([_P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P], _I32),
+    "lbm_cnn_backward_layer": ([_P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _P], _I32),
     "lbm_cnn_adam_layer_fold": ([_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _I32, _I32, _P, _P, _P, _P,
                                  _P, _P], _I32),
 }
@@ -105,6 +106,17 @@ def lbm_cnn_conv3d_wgrad_partials(x, gz, n, d, h, wd, ci, co, work, stream=None)
     return _lib.lbm_cnn_conv3d_wgrad_partials(
         _ptr(x, torch.float32, nv * pad4(ci), "x"), _ptr(gz, torch.float32, nv * pad4(co), "gz"),
         n, d, h, wd, ci, co, _ptr(work, torch.float32, ws, "work"), _stream(stream))
+
+
+def lbm_cnn_backward_layer(x, gz, n, d, h, wd, ci, co, work, packed_flip, mask, gin, stream=None):
+    nv = n * d * h * wd
+    ws = lbm_cnn_wgrad_workspace(n, d, h, wd, ci, co) // 4
+    return _lib.lbm_cnn_backward_layer(
+        _ptr(x, torch.float32, nv * pad4(ci), "x"), _ptr(gz, torch.float32, nv * pad4(co), "gz", 16),
+        n, d, h, wd, ci, co, _ptr(work, torch.float32, ws, "work"),
+        _ptr(packed_flip, torch.int16, lbm_cnn_packed_size(ci, co), "packed_flip", 8),
+        _ptr(mask, torch.float32, nv * pad4(ci), "mask"), _ptr(gin, torch.float32, nv * pad4(ci), "gin", 16),
+        _stream(stream))
 
 
 def lbm_cnn_relu_backward(a, g, count, stream=None):

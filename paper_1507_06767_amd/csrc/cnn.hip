@@ -144,16 +144,18 @@ __global__ __launch_bounds__(256) void conv_forward_kernel(const float *x, int n
 // pointer plus the tap's offset.  (The generic kernel spends ~30 VALU per
 // MFMA on that index arithmetic.)  The same operands in the same order as
 // conv_forward_kernel: the same bits.
+// (Workgroup (bx, by) of the launch: voxel tiles 4 bx .. 4 bx + 3, output
+// channels 16 by ..; a body of its own so that a fused launch can run it.)
 template <int CI>
-__global__ __launch_bounds__(256) void conv_forward_ci(const float *x, int n, int d, int h, int w,
-                                                       const uint16_t *packed, int co, const float *bias,
-                                                       int relu, const float *mask, float *y) {
+__device__ __forceinline__ void conv_forward_ci_body(const float *x, int n, int d, int h, int w,
+                                                     const uint16_t *packed, int co, const float *bias, int relu,
+                                                     const float *mask, float *y, int bx, int by) {
     constexpr int K16 = (kTaps * CI + 15) / 16 * 16, NK = K16 / 16;
     const int co4 = pad4(co);
     const int nv = n * d * h * w;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int v0 = (blockIdx.x * 4 + wave) * 16;
-    const int co0 = blockIdx.y * 16;
+    const int v0 = (bx * 4 + wave) * 16;
+    const int co0 = by * 16;
     if (v0 >= nv) return;
     const int r = lane & 15, kg = lane >> 4;
     const int va = v0 + r;
@@ -306,20 +308,30 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(const float *x, const f
     }
 }
 
+template <int CI>
+__global__ __launch_bounds__(256) void conv_forward_ci(const float *x, int n, int d, int h, int w,
+                                                       const uint16_t *packed, int co, const float *bias,
+                                                       int relu, const float *mask, float *y) {
+    conv_forward_ci_body<CI>(x, n, d, h, w, packed, co, bias, relu, mask, y, blockIdx.x, blockIdx.y);
+}
+
 // The same weight-gradient partials for 4 or 16 (padded) input channels and
 // rows of a multiple of 4 voxels: the lane's first voxel is decomposed once
 // and then advanced by 16 voxels per step (carrying into y, z, n), its
 // gradient and input pointers by 16 voxels' strides, so a step is its
 // bounds tests, eight loads and one MFMA.  The same operands in the same
 // order as conv_wgrad_kernel: the same bits.
+// (Workgroup (chunk, bk, bc) of nchunk chunks: a body of its own so that a
+// fused launch can run it.)
 template <int CI>
-__global__ __launch_bounds__(256) void conv_wgrad_ci(const float *x, const float *gz, int n, int d, int h, int w,
-                                                     int ci, int co, float *work) {
+__device__ __forceinline__ void conv_wgrad_ci_body(const float *x, const float *gz, int n, int d, int h, int w,
+                                                   int ci, int co, float *work, int chunk, int bk, int bc,
+                                                   int nchunk) {
     constexpr int K16 = (kTaps * CI + 15) / 16 * 16;
     const int co4 = pad4(co), co16 = pad16(co);
     const int nv = n * d * h * w;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int chunk = blockIdx.x, k0 = blockIdx.y * 16, c0 = blockIdx.z * 16;
+    const int k0 = bk * 16, c0 = bc * 16;
     const int r = lane & 15, kg = lane >> 4;
     const int kcol = k0 + r;                       // this lane's B column
     const int tap = kcol / CI, cch = kcol % CI;
@@ -386,11 +398,40 @@ __global__ __launch_bounds__(256) void conv_wgrad_ci(const float *x, const float
     const int row = t / 16, col = t % 16;
     const float sum = ((tile[0][row][col] + tile[1][row][col]) + tile[2][row][col]) + tile[3][row][col];
     work[((int64_t)chunk * co16 + c0 + row) * K16 + k0 + col] = sum;
-    if (blockIdx.y == 0 && t < 16) {
+    if (bk == 0 && t < 16) {
         float bb = 0.0f;
         for (int wv = 0; wv < 4; ++wv)
             for (int g = 0; g < 4; ++g) bb += bias[wv][g][t];
-        work[(int64_t)gridDim.x * co16 * K16 + (int64_t)chunk * co16 + c0 + t] = bb;
+        work[(int64_t)nchunk * co16 * K16 + (int64_t)chunk * co16 + c0 + t] = bb;
+    }
+}
+
+template <int CI>
+__global__ __launch_bounds__(256) void conv_wgrad_ci(const float *x, const float *gz, int n, int d, int h, int w,
+                                                     int ci, int co, float *work) {
+    conv_wgrad_ci_body<CI>(x, gz, n, d, h, w, ci, co, work, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x);
+}
+
+// One layer's backward in one launch: the weight-gradient partials of the
+// layer (input x with ci channels, output gradient gz with co) and its data
+// gradient (the forward body with flip-packed weights, gz -> gin with ci
+// channels, masked by the ReLU of the layer below); the first nwg
+// workgroups take the former, the rest the latter.  The two read the same
+// gz and write different buffers, so the result is that of the two
+// launches.  CIW = ci padded to 4, CIF = co padded to 4.
+template <int CIW, int CIF>
+__global__ __launch_bounds__(256) void backward_layer_kernel(const float *x, const float *gz, int n, int d, int h,
+                                                             int w, int ci, int co, float *work, int nchunk,
+                                                             int nk, int nc, const uint16_t *packed_flip,
+                                                             const float *mask, float *gin, int fx) {
+    const int nwg = nchunk * nk * nc;
+    const int b = blockIdx.x;
+    if (b < nwg) {
+        conv_wgrad_ci_body<CIW>(x, gz, n, d, h, w, ci, co, work, b % nchunk, (b / nchunk) % nk, b / (nchunk * nk),
+                                nchunk);
+    } else {
+        const int f = b - nwg;
+        conv_forward_ci_body<CIF>(gz, n, d, h, w, packed_flip, ci, nullptr, 0, mask, gin, f % fx, f / fx);
     }
 }
 
@@ -671,6 +712,37 @@ int32_t lbm_cnn_conv3d_wgrad_partials(const float *x, const float *gz, int32_t n
     const int nchunk = (int)((nv + kWgradVoxels - 1) / kWgradVoxels);
     launch_wgrad(x, gz, n, d, h, wd, ci, co, work, nchunk, (hipStream_t)stream);
     return launched();
+}
+
+int32_t lbm_cnn_backward_layer(const float *x, const float *gz, int32_t n, int32_t d, int32_t h, int32_t wd,
+                               int32_t ci, int32_t co, float *work, const uint16_t *packed_flip, const float *mask,
+                               float *gin, void *stream) {
+    if (!x || !gz || !work || !packed_flip || !gin || n < 1 || d < 1 || h < 1 || wd < 1 || ci < 1 || co < 1)
+        return -1;
+    if (((uintptr_t)gz) % 16 || ((uintptr_t)packed_flip) % 8) return -1;
+    const int64_t nv = (int64_t)n * d * h * wd;
+    if (nv >= (int64_t(1) << 31)) return -1;
+    const int nchunk = (int)((nv + kWgradVoxels - 1) / kWgradVoxels);
+    const int nk = pad16(kTaps * pad4(ci)) / 16, nc = pad16(co) / 16;
+    const int fx = (int)blocks_for(nv, 64), fy = pad16(ci) / 16;
+    const int64_t total = (int64_t)nchunk * nk * nc + (int64_t)fx * fy;
+    hipStream_t st = (hipStream_t)stream;
+    const int wi = pad4(ci), fi = pad4(co);
+    if (wd % 4 == 0 && (wi == 4 || wi == 16) && (fi == 4 || fi == 16) && total < (int64_t(1) << 31)) {
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3((unsigned)total), dim3(256), 0, st, x, gz, n, d, h, wd, ci, co, work,
+                               nchunk, nk, nc, packed_flip, mask, gin, fx);
+        };
+        if (wi == 16 && fi == 16) go(backward_layer_kernel<16, 16>);
+        else if (wi == 16) go(backward_layer_kernel<16, 4>);
+        else if (fi == 16) go(backward_layer_kernel<4, 16>);
+        else go(backward_layer_kernel<4, 4>);
+        return launched();
+    }
+    // other shapes: the two launches
+    int32_t r = lbm_cnn_conv3d_wgrad_partials(x, gz, n, d, h, wd, ci, co, work, stream);
+    if (r != 0) return r;
+    return lbm_cnn_conv3d_forward(gz, n, d, h, wd, co, packed_flip, ci, nullptr, 0, mask, gin, stream);
 }
 
 int32_t lbm_cnn_relu_backward(const float *a, float *g, int64_t count, void *stream) {

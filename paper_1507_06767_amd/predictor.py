@@ -166,6 +166,15 @@ class FlagPredictor:
         for k in range(len(self.layers) - 1, -1, -1):
             L = self.layers[k]
             inp = B["x"] if k == 0 else B["acts"][k - 1]
+            if partials and k > 0:
+                # weight-gradient partials and the data gradient (through the
+                # ReLU of layer k - 1) in one launch
+                gin = B["grads"][k]
+                mask = B["acts"][k - 1] if self.layers[k - 1].relu else None
+                _check(cnn.lbm_cnn_backward_layer(inp, g, n, d, h, w, L.ci, L.co, B["works"][k], L.packed_flip,
+                                                  mask, gin, self.stream), "backward layer")
+                g = gin
+                continue
             if partials:
                 _check(cnn.lbm_cnn_conv3d_wgrad_partials(inp, g, n, d, h, w, L.ci, L.co, B["works"][k],
                                                          self.stream), "wgrad partials")
@@ -229,8 +238,9 @@ class FlagPredictor:
 
     def train_step(self, shape, lr):
         """One training iteration (forward, loss, backward, Adam) on the
-        loaded batch, without host transfers: the weight gradients' folds
-        run inside the Adam launches (18 launches)."""
+        loaded batch, without host transfers: a layer's weight-gradient
+        partials and data gradient share a launch, and the folds run inside
+        the Adam launches (15 launches)."""
         self.loss_and_grads_device(shape, partials=True)
         self.adam_step_partials(shape, lr)
 

@@ -332,6 +332,42 @@ def test_adam_layer_fold_matches_wgrad_then_adam(env, case):
     assert torch.equal(g[0], g[1]) and torch.equal(gb[0], gb[1])
 
 
+@pytest.mark.parametrize("case", [((2, 8, 8, 16), 16, 16), ((2, 3, 4, 8), 16, 1), ((2, 3, 4, 8), 4, 16),
+                                  ((3, 4, 4, 4), 3, 5), ((1, 5, 6, 7), 16, 16)],
+                         ids=["16to16", "16to1", "4to16", "3to5", "16to16_w7_two_launches"])
+def test_backward_layer_matches_separate_launches(env, case):
+    """lbm_cnn_backward_layer (weight-gradient partials and masked data
+    gradient in one launch) against lbm_cnn_conv3d_wgrad_partials and
+    lbm_cnn_conv3d_forward with the flip-packed weights: identical bits in
+    the partial sums and the data gradient."""
+    torch, cnn = env
+    shape, ci, co = case
+    n, d, h, wd = shape
+    nv = n * d * h * wd
+    print(f"\n[case] backward layer {shape} {ci}->{co}", flush=True)
+    rng = np.random.default_rng(31 + ci + co)
+    x = _dev(torch, _padded(rng.standard_normal(shape + (ci,)).astype(np.float32), cnn.pad4(ci)))
+    gz = _dev(torch, _padded(rng.standard_normal(shape + (co,)).astype(np.float32), cnn.pad4(co)))
+    w = (rng.standard_normal((co, 27, ci)) * 0.2).astype(np.float32)
+    pkf = _pack(torch, cnn, w, co, ci, True)
+    act = rng.standard_normal(nv * cnn.pad4(ci)).astype(np.float32)
+    act[::5] = 0.0
+    mask = _dev(torch, act)
+    ws = cnn.lbm_cnn_wgrad_workspace(n, d, h, wd, ci, co) // 4
+    work = [torch.full((ws,), float("nan"), dtype=torch.float32, device="cuda") for _ in range(2)]
+    gin = [torch.full((nv * cnn.pad4(ci),), float("nan"), dtype=torch.float32, device="cuda") for _ in range(2)]
+    assert cnn.lbm_cnn_backward_layer(x, gz, n, d, h, wd, ci, co, work[0], pkf, mask, gin[0]) == 0
+    assert cnn.lbm_cnn_conv3d_wgrad_partials(x, gz, n, d, h, wd, ci, co, work[1]) == 0
+    assert cnn.lbm_cnn_conv3d_forward(gz, n, d, h, wd, co, pkf, ci, None, 0, mask, gin[1]) == 0
+    torch.cuda.synchronize()
+    nchunk = (nv + 511) // 512
+    p16 = lambda k: (k + 15) // 16 * 16
+    used = nchunk * p16(co) * (p16(27 * cnn.pad4(ci)) + 1)   # partials, then the bias partials
+    w0, w1 = work[0][:used], work[1][:used]
+    assert torch.isfinite(w0).all() and torch.equal(w0.view(torch.int32), w1.view(torch.int32))
+    assert torch.isfinite(gin[0]).all() and torch.equal(gin[0].view(torch.int32), gin[1].view(torch.int32))
+
+
 @pytest.mark.parametrize("case", [(5, 2), (6, 8)], ids=["5ch_2x16^3", "6ch_8x16^3"])
 def test_network_gradients_against_oracle(env, case):
     """A C -> 16 -> 16 -> 16 -> 1 network on B 16^3 block grids (the second
