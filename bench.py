@@ -364,7 +364,7 @@ def run_predictor(args, lbm, torch):
     x = (2.0 * lbm_inputs.uniform(11, nv * 4) - 1.0).reshape(shape + (4,))
     t = (2.0 * lbm_inputs.uniform(12, nv) - 1.0).reshape(shape)
     net = FlagPredictor(channels=(4, 16, 16, 16, 1), residual=False, seed=0)
-    # the batch stays on the device; one iteration (15 launches) is captured
+    # the batch stays on the device; one iteration (12 launches) is captured
     # into a HIP graph and replayed
     net.load_batch(x, t)
     for _ in range(args.warmup):

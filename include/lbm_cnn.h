@@ -137,6 +137,27 @@ int32_t lbm_cnn_adam_layer_fold(float *w, float *b, const float *work, int32_t n
                                 float *mw, float *vw, float *mb, float *vb, int32_t co, int32_t ci, uint16_t *packed,
                                 uint16_t *packed_flip, const float *hyper, float *gw, float *gb, void *stream);
 
+/* One layer's state for lbm_cnn_adam_layers_fold: the arguments of
+ * lbm_cnn_adam_layer_fold (work: that layer's partial sums from
+ * lbm_cnn_conv3d_wgrad_partials or lbm_cnn_backward_layer; gw, gb may be
+ * NULL). */
+typedef struct lbm_cnn_layer {
+    float *w, *b;
+    const float *work;
+    float *mw, *vw, *mb, *vb;
+    uint16_t *packed, *packed_flip;
+    float *gw, *gb;
+    int32_t co, ci;
+} lbm_cnn_layer;
+#define LBM_CNN_MAX_LAYERS 8
+
+/* lbm_cnn_adam_layer_fold for nlayers <= LBM_CNN_MAX_LAYERS layers (a host
+ * array; their partials all for the batch shape (n, d, h, wd)) in a single
+ * launch: the same bits as one call per layer.  -1 on a NULL pointer, a
+ * size < 1 or too many layers. */
+int32_t lbm_cnn_adam_layers_fold(int32_t nlayers, const lbm_cnn_layer *layers, int32_t n, int32_t d, int32_t h,
+                                 int32_t wd, const float *hyper, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

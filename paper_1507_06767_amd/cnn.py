@@ -17,6 +17,14 @@ from . import abi
 LBM_CNN_TAPS = 27
 LBM_CNN_LOSS_FLOATS = 257
 LBM_CNN_HYPER_FLOATS = 8
+LBM_CNN_MAX_LAYERS = 8
+
+
+class lbm_cnn_layer(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_void_p), ("b", ctypes.c_void_p), ("work", ctypes.c_void_p),
+                ("mw", ctypes.c_void_p), ("vw", ctypes.c_void_p), ("mb", ctypes.c_void_p), ("vb", ctypes.c_void_p),
+                ("packed", ctypes.c_void_p), ("packed_flip", ctypes.c_void_p), ("gw", ctypes.c_void_p),
+                ("gb", ctypes.c_void_p), ("co", ctypes.c_int32), ("ci", ctypes.c_int32)]
 
 _lib = abi._lib
 _P = ctypes.c_void_p
@@ -37,6 +45,7 @@ _SIG = {
     "lbm_cnn_backward_layer": ([_P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _P], _I32),
     "lbm_cnn_adam_layer_fold": ([_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _I32, _I32, _P, _P, _P, _P,
                                  _P, _P], _I32),
+    "lbm_cnn_adam_layers_fold": ([_I32, ctypes.POINTER(lbm_cnn_layer), _I32, _I32, _I32, _I32, _P, _P], _I32),
 }
 for _name, (_args, _res) in _SIG.items():
     _fn = getattr(_lib, _name)
@@ -173,3 +182,26 @@ def lbm_cnn_adam_layer_fold(w, b, work, n, d, h, wd, mw, vw, mb, vb, co, ci, pac
         _ptr(packed_flip, torch.int16, lbm_cnn_packed_size(ci, co), "packed_flip", 8),
         _ptr(hyper, torch.float32, LBM_CNN_HYPER_FLOATS, "hyper"), _ptr(gw, torch.float32, nw, "gw"),
         _ptr(gb, torch.float32, nb, "gb"), _stream(stream))
+
+
+def lbm_cnn_adam_layers_fold(layers, n, d, h, wd, hyper, stream=None):
+    """layers: a sequence of dicts with the arguments of
+    lbm_cnn_adam_layer_fold (w, b, work, mw, vw, mb, vb, packed, packed_flip,
+    gw, gb, co, ci; gw, gb may be None)."""
+    if not 1 <= len(layers) <= LBM_CNN_MAX_LAYERS:
+        raise ValueError(f"1 to {LBM_CNN_MAX_LAYERS} layers")
+    arr = (lbm_cnn_layer * len(layers))()
+    for k, L in enumerate(layers):
+        co, ci = int(L["co"]), int(L["ci"])
+        nw, nb = co * LBM_CNN_TAPS * ci, co
+        ws = lbm_cnn_wgrad_workspace(n, d, h, wd, ci, co) // 4
+        arr[k] = lbm_cnn_layer(
+            _ptr(L["w"], torch.float32, nw, "w"), _ptr(L["b"], torch.float32, nb, "b"),
+            _ptr(L["work"], torch.float32, ws, "work"), _ptr(L["mw"], torch.float32, nw, "mw"),
+            _ptr(L["vw"], torch.float32, nw, "vw"), _ptr(L["mb"], torch.float32, nb, "mb"),
+            _ptr(L["vb"], torch.float32, nb, "vb"),
+            _ptr(L["packed"], torch.int16, lbm_cnn_packed_size(co, ci), "packed", 8),
+            _ptr(L["packed_flip"], torch.int16, lbm_cnn_packed_size(ci, co), "packed_flip", 8),
+            _ptr(L.get("gw"), torch.float32, nw, "gw"), _ptr(L.get("gb"), torch.float32, nb, "gb"), co, ci)
+    return _lib.lbm_cnn_adam_layers_fold(len(layers), arr, n, d, h, wd,
+                                         _ptr(hyper, torch.float32, LBM_CNN_HYPER_FLOATS, "hyper"), _stream(stream))

@@ -443,14 +443,15 @@ __global__ __launch_bounds__(256) void backward_layer_kernel(const float *x, con
 // is deterministic, with 8 loads per lane in flight instead of a chain of
 // nchunk.
 constexpr int kFoldWaves = 8;
-// The fold of output blockIdx.x * 64 + lane (with_bias: biases included);
-// valid in wave 0, whose lanes return the sums; ok tells whether the
-// lane's output exists.
-__device__ inline float fold_output(const float *work, int nchunk, int ci, int co, bool with_bias, bool &ok) {
+// The fold of output block * 64 + lane (with_bias: biases included); valid
+// in wave 0, whose lanes return the sums; ok tells whether the lane's output
+// exists.
+__device__ inline float fold_output(const float *work, int nchunk, int ci, int co, bool with_bias, bool &ok,
+                                    int block) {
     const int ci4 = pad4(ci), k16 = pad16(kTaps * ci4), co16 = pad16(co);
     const int nw = co * kTaps * ci;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int idx = blockIdx.x * 64 + lane;
+    const int idx = block * 64 + lane;
     const bool is_w = idx < nw, is_b = !is_w && with_bias && idx < nw + co;
     // partial of chunk ch for this output: base + ch * stride
     int64_t base = 0, stride = 0;
@@ -478,7 +479,7 @@ __device__ inline float fold_output(const float *work, int nchunk, int ci, int c
 __global__ __launch_bounds__(64 * kFoldWaves) void grad_fold_kernel(const float *work, int nchunk, int ci, int co,
                                                                     float *gw, float *gb) {
     bool ok;
-    const float t = fold_output(work, nchunk, ci, co, gb != nullptr, ok);
+    const float t = fold_output(work, nchunk, ci, co, gb != nullptr, ok, blockIdx.x);
     if (threadIdx.x >= 64 || !ok) return;
     const int nw = co * kTaps * ci, idx = blockIdx.x * 64 + threadIdx.x;
     if (idx < nw) gw[idx] = t;
@@ -602,21 +603,46 @@ __global__ void adam_layer_kernel(float *w, float *b, const float *gw, const flo
 // workgroup applies Adam to the 64 sums it folded (the same sums, and the
 // same update, as grad_fold_kernel followed by adam_layer_kernel; gw, gb
 // receive the gradient when given).
-__global__ __launch_bounds__(64 * kFoldWaves) void adam_fold_kernel(const float *work, int nchunk, float *w, float *b,
-                                                                    float *mw, float *vw, float *mb, float *vb,
-                                                                    int co, int ci, uint16_t *packed,
-                                                                    uint16_t *packed_flip, const float *hyper,
-                                                                    float *gw, float *gb) {
+__device__ __forceinline__ void adam_fold_body(const float *work, int nchunk, float *w, float *b, float *mw,
+                                               float *vw, float *mb, float *vb, int co, int ci, uint16_t *packed,
+                                               uint16_t *packed_flip, const float *hyper, float *gw, float *gb,
+                                               int block) {
     bool ok;
-    const float t = fold_output(work, nchunk, ci, co, true, ok);
+    const float t = fold_output(work, nchunk, ci, co, true, ok, block);
     if (threadIdx.x >= 64 || !ok) return;
-    const int nw = co * kTaps * ci, idx = blockIdx.x * 64 + threadIdx.x;
+    const int nw = co * kTaps * ci, idx = block * 64 + threadIdx.x;
     if (idx < nw) {
         if (gw) gw[idx] = t;
     } else if (gb) {
         gb[idx - nw] = t;
     }
     adam_layer_param(idx, t, w, b, mw, vw, mb, vb, co, ci, packed, packed_flip, hyper);
+}
+
+__global__ __launch_bounds__(64 * kFoldWaves) void adam_fold_kernel(const float *work, int nchunk, float *w, float *b,
+                                                                    float *mw, float *vw, float *mb, float *vb,
+                                                                    int co, int ci, uint16_t *packed,
+                                                                    uint16_t *packed_flip, const float *hyper,
+                                                                    float *gw, float *gb) {
+    adam_fold_body(work, nchunk, w, b, mw, vw, mb, vb, co, ci, packed, packed_flip, hyper, gw, gb, blockIdx.x);
+}
+
+// The same for up to LBM_CNN_MAX_LAYERS layers in one launch: layer l owns
+// workgroups first[l] .. first[l + 1] - 1.
+struct FoldLayers {
+    lbm_cnn_layer layer[LBM_CNN_MAX_LAYERS];
+    int first[LBM_CNN_MAX_LAYERS + 1];
+    int nlayers, nchunk;
+    const float *hyper;
+};
+
+__global__ __launch_bounds__(64 * kFoldWaves) void adam_fold_layers_kernel(const FoldLayers f) {
+    const int b = blockIdx.x;
+    int l = 0;
+    while (l + 1 < f.nlayers && b >= f.first[l + 1]) ++l;
+    const lbm_cnn_layer &L = f.layer[l];
+    adam_fold_body(L.work, f.nchunk, L.w, L.b, L.mw, L.vw, L.mb, L.vb, L.co, L.ci, L.packed, L.packed_flip,
+                   f.hyper, L.gw, L.gb, b - f.first[l]);
 }
 
 // Opens an optimizer step: hyper[0..3] = (lr, beta1, beta2, eps), hyper[4] += 1.
@@ -804,6 +830,33 @@ int32_t lbm_cnn_adam_layer_fold(float *w, float *b, const float *work, int32_t n
     hipLaunchKernelGGL(adam_fold_kernel, dim3(blocks_for((int64_t)co * kTaps * ci + co, 64)), dim3(64 * kFoldWaves),
                        0, (hipStream_t)stream, work, nchunk, w, b, mw, vw, mb, vb, co, ci, packed, packed_flip, hyper,
                        gw, gb);
+    return launched();
+}
+
+int32_t lbm_cnn_adam_layers_fold(int32_t nlayers, const lbm_cnn_layer *layers, int32_t n, int32_t d, int32_t h,
+                                 int32_t wd, const float *hyper, void *stream) {
+    if (!layers || !hyper || nlayers < 1 || nlayers > LBM_CNN_MAX_LAYERS || n < 1 || d < 1 || h < 1 || wd < 1)
+        return -1;
+    const int64_t nv = (int64_t)n * d * h * wd;
+    if (nv >= (int64_t(1) << 31)) return -1;
+    FoldLayers f{};
+    f.nlayers = nlayers;
+    f.nchunk = (int)((nv + kWgradVoxels - 1) / kWgradVoxels);
+    f.hyper = hyper;
+    int64_t first = 0;
+    for (int l = 0; l < nlayers; ++l) {
+        const lbm_cnn_layer &L = layers[l];
+        if (!L.w || !L.b || !L.work || !L.mw || !L.vw || !L.mb || !L.vb || !L.packed || !L.packed_flip ||
+            L.co < 1 || L.ci < 1)
+            return -1;
+        f.layer[l] = L;
+        f.first[l] = (int)first;
+        first += blocks_for((int64_t)L.co * kTaps * L.ci + L.co, 64);
+        if (first >= (int64_t(1) << 31)) return -1;
+    }
+    f.first[nlayers] = (int)first;
+    hipLaunchKernelGGL(adam_fold_layers_kernel, dim3((unsigned)first), dim3(64 * kFoldWaves), 0,
+                       (hipStream_t)stream, f);
     return launched();
 }
 

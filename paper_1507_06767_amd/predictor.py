@@ -231,16 +231,22 @@ class FlagPredictor:
         n, d, h, w = shape
         self.t += 1
         _check(cnn.lbm_cnn_adam_begin(self.hyper, lr, beta1, beta2, eps, self.stream), "adam begin")
-        for L, work in zip(self.layers, B["works"]):
-            _check(cnn.lbm_cnn_adam_layer_fold(L.w, L.b, work, n, d, h, w, L.mw, L.vw, L.mb, L.vb, L.co, L.ci,
-                                               L.packed, L.packed_flip, self.hyper, L.gw, L.gb, self.stream),
-                   "adam fold")
+        layers = [dict(w=L.w, b=L.b, work=work, mw=L.mw, vw=L.vw, mb=L.mb, vb=L.vb, packed=L.packed,
+                       packed_flip=L.packed_flip, gw=L.gw, gb=L.gb, co=L.co, ci=L.ci)
+                  for L, work in zip(self.layers, B["works"])]
+        if len(layers) <= cnn.LBM_CNN_MAX_LAYERS:   # every layer's fold and update in one launch
+            _check(cnn.lbm_cnn_adam_layers_fold(layers, n, d, h, w, self.hyper, self.stream), "adam fold")
+        else:
+            for L, work in zip(self.layers, B["works"]):
+                _check(cnn.lbm_cnn_adam_layer_fold(L.w, L.b, work, n, d, h, w, L.mw, L.vw, L.mb, L.vb, L.co,
+                                                   L.ci, L.packed, L.packed_flip, self.hyper, L.gw, L.gb,
+                                                   self.stream), "adam fold")
 
     def train_step(self, shape, lr):
         """One training iteration (forward, loss, backward, Adam) on the
         loaded batch, without host transfers: a layer's weight-gradient
-        partials and data gradient share a launch, and the folds run inside
-        the Adam launches (15 launches)."""
+        partials and data gradient share a launch, and the folds of all
+        layers run inside one Adam launch (12 launches)."""
         self.loss_and_grads_device(shape, partials=True)
         self.adam_step_partials(shape, lr)
 

@@ -332,6 +332,58 @@ def test_adam_layer_fold_matches_wgrad_then_adam(env, case):
     assert torch.equal(g[0], g[1]) and torch.equal(gb[0], gb[1])
 
 
+def test_adam_layers_fold_matches_one_launch_per_layer(env):
+    """lbm_cnn_adam_layers_fold (every layer's fold and update in one launch)
+    against lbm_cnn_adam_layer_fold layer by layer, two steps on the layers
+    4 -> 16 -> 16 -> 1: identical bits in every updated array."""
+    torch, cnn = env
+    shape = (2, 4, 6, 8)
+    n, d, h, wd = shape
+    print(f"\n[case] adam over all layers in one launch {shape}", flush=True)
+    rng = np.random.default_rng(41)
+    chans = [(4, 16), (16, 16), (16, 1)]
+    sets = []
+    for _ in range(2):
+        layers = []
+        for ci, co in chans:
+            nw = co * 27 * ci
+            L = {k: torch.zeros(m, dtype=torch.float32, device="cuda") for k, m in
+                 (("w", nw), ("b", co), ("mw", nw), ("vw", nw), ("mb", co), ("vb", co), ("gw", nw), ("gb", co))}
+            L["work"] = torch.zeros(cnn.lbm_cnn_wgrad_workspace(n, d, h, wd, ci, co) // 4, dtype=torch.float32,
+                                    device="cuda")
+            L["packed"] = torch.zeros(cnn.lbm_cnn_packed_size(co, ci), dtype=torch.int16, device="cuda")
+            L["packed_flip"] = torch.zeros(cnn.lbm_cnn_packed_size(ci, co), dtype=torch.int16, device="cuda")
+            L["co"], L["ci"] = co, ci
+            layers.append(L)
+        sets.append(layers)
+    for (ci, co), La, Lb in zip(chans, *sets):
+        for k in ("w", "b", "mw", "vw", "mb", "vb"):
+            v = rng.standard_normal(La[k].numel()) * 0.1
+            if k in ("vw", "vb"):
+                v = np.abs(v)
+            La[k].copy_(_dev(torch, v))
+            Lb[k].copy_(La[k])
+    hyper = [torch.zeros(cnn.LBM_CNN_HYPER_FLOATS, dtype=torch.float32, device="cuda") for _ in range(2)]
+    for step in range(2):
+        for (ci, co), La, Lb in zip(chans, *sets):
+            x = _dev(torch, _padded(rng.standard_normal(shape + (ci,)).astype(np.float32), cnn.pad4(ci)))
+            gz = _dev(torch, _padded(rng.standard_normal(shape + (co,)).astype(np.float32), cnn.pad4(co)))
+            assert cnn.lbm_cnn_conv3d_wgrad_partials(x, gz, n, d, h, wd, ci, co, La["work"]) == 0
+            Lb["work"].copy_(La["work"])
+        for hp in hyper:
+            assert cnn.lbm_cnn_adam_begin(hp, 2e-3, 0.9, 0.999, 1e-8) == 0
+        assert cnn.lbm_cnn_adam_layers_fold(sets[0], n, d, h, wd, hyper[0]) == 0
+        for L in sets[1]:
+            assert cnn.lbm_cnn_adam_layer_fold(L["w"], L["b"], L["work"], n, d, h, wd, L["mw"], L["vw"], L["mb"],
+                                               L["vb"], L["co"], L["ci"], L["packed"], L["packed_flip"], hyper[1],
+                                               L["gw"], L["gb"]) == 0
+    torch.cuda.synchronize()
+    for La, Lb in zip(*sets):
+        for k in ("w", "b", "mw", "vw", "mb", "vb", "gw", "gb", "packed", "packed_flip"):
+            assert torch.equal(La[k], Lb[k]), k
+    assert torch.isfinite(sets[0][1]["gw"]).all() and (sets[0][1]["gw"] != 0).any()
+
+
 @pytest.mark.parametrize("case", [((2, 8, 8, 16), 16, 16), ((2, 3, 4, 8), 16, 1), ((2, 3, 4, 8), 4, 16),
                                   ((3, 4, 4, 4), 3, 5), ((1, 5, 6, 7), 16, 16)],
                          ids=["16to16", "16to1", "4to16", "3to5", "16to16_w7_two_launches"])
