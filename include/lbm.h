@@ -138,7 +138,8 @@ typedef struct {
                                (1 - s^18)^2, s = (2 x + 1 - n) / n in (-1, 1) at the
                                fluid cell's centre (ignored on periodic faces) */
     int32_t streaming;      /* LBM_STREAMING_AUTO: in place (one buffer, the AA pattern)
-                               when a buffer is at most 512 MiB, except 3D float64;
+                               when a buffer is at most 512 MiB, except 3D float64
+                               and the 2D grids of lbm_set_multistep;
                                PINGPONG: read F_A, write F_B, swap (required by
                                lbm_create_hierarchy); INPLACE: in place (not for 3D
                                float64).  Results are identical bit for bit. */
@@ -247,6 +248,22 @@ lbm_status lbm_set_equilibrium(lbm_blocks *h, const double *rho_host, const doub
  * row, otherwise tiles of 8 rows).  Any pointer may be NULL.  Pure host
  * query. */
 lbm_status lbm_get_scheme(lbm_blocks *h, int32_t *inplace, int32_t *next_is_gather, int32_t *tile_x);
+
+/* Several steps per launch for small 2D grids (temporal blocking; not in the
+ * paper: a launch of one step of a 64^2 grid lasts about as long as the
+ * latency of one small kernel).  Runs of sensor-free steps of a ping-pong
+ * D2Q9 handle of at most 65,536 cells are taken up to `steps` at a time by
+ * one launch, in which each workgroup steps an 8 x 8 tile of the grid and a
+ * halo of 4 cells around it in LDS; the results equal one launch per step bit
+ * for bit (sensor steps are launched alone).  On by default with 5 steps
+ * where it applies: D2Q9, ping-pong (LBM_STREAMING_AUTO picks ping-pong for
+ * such grids), no stochastic rounding.  steps = 0 switches it off, 2 .. 5
+ * sets the most steps per launch; LBM_EINVAL for other values, LBM_ENOTSUP
+ * for steps > 0 on a handle where it does not apply.  Synchronises the stream
+ * and drops captured graphs.  lbm_get_multistep reads the setting (0: off);
+ * pure host query. */
+lbm_status lbm_set_multistep(lbm_blocks *h, int32_t steps);
+lbm_status lbm_get_multistep(lbm_blocks *h, int32_t *steps);
 
 /* Step counter (number of steps taken since it was last set). */
 lbm_status lbm_get_step(lbm_blocks *h, int64_t *step);

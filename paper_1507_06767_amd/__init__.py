@@ -16,6 +16,7 @@ from .abi import (  # noqa: F401
     LBM_STREAMING_AUTO, LBM_STREAMING_PINGPONG, LBM_STREAMING_INPLACE, lbm_desc, lbm_box, make_desc, library_path,
     lbm_required_bytes, lbm_create_blocks, lbm_step_n, lbm_sensor_flags, lbm_get_macros, lbm_block_means,
     lbm_get_populations, lbm_set_populations, lbm_set_equilibrium, lbm_get_step, lbm_set_step, lbm_get_scheme,
+    lbm_set_multistep, lbm_get_multistep,
     lbm_conservation, lbm_tau_from_reynolds, lbm_destroy, lbm_last_error,
     lbm_sensor_levels, lbm_sensor_average_begin, lbm_sensor_average, lbm_sensor_average_end,
     lbm_autotune, lbm_use_graphs, lbm_hierarchy_required_bytes, lbm_create_hierarchy, lbm_hierarchy_step, lbm_hierarchy_sensor,

@@ -96,6 +96,8 @@ def _load_library():
         "lbm_set_populations": [H, dp],
         "lbm_set_equilibrium": [H, dp, dp],
         "lbm_get_step": [H, ctypes.POINTER(ctypes.c_int64)],
+        "lbm_set_multistep": [H, ctypes.c_int32],
+        "lbm_get_multistep": [H, ctypes.POINTER(ctypes.c_int32)],
         "lbm_get_scheme": [H, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                            ctypes.POINTER(ctypes.c_int32)],
         "lbm_set_step": [H, ctypes.c_int64],
@@ -237,6 +239,16 @@ def lbm_set_equilibrium(h, cells: int, dim: int, rho=None, u=None):
 def lbm_get_step(h):
     s = ctypes.c_int64(0)
     st = _lib.lbm_get_step(h, ctypes.byref(s))
+    return st, s.value
+
+
+def lbm_set_multistep(h, steps: int):
+    return _lib.lbm_set_multistep(h, steps)
+
+
+def lbm_get_multistep(h):
+    s = ctypes.c_int32(0)
+    st = _lib.lbm_get_multistep(h, ctypes.byref(s))
     return st, s.value
 
 

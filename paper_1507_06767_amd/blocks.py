@@ -135,10 +135,16 @@ class Blocks:
         return tx
 
     def scheme(self):
-        """dict(inplace, next_is_gather, tile_x) of the handle."""
+        """dict(inplace, next_is_gather, tile_x, multistep) of the handle."""
         st, ip, nxt, tx = abi.lbm_get_scheme(self.h)
         _check(st)
-        return {"inplace": bool(ip), "next_is_gather": bool(nxt), "tile_x": tx}
+        st, ms = abi.lbm_get_multistep(self.h)
+        _check(st)
+        return {"inplace": bool(ip), "next_is_gather": bool(nxt), "tile_x": tx, "multistep": ms}
+
+    def set_multistep(self, steps: int):
+        """Most sensor-free steps per launch on small 2D grids (0: off)."""
+        _check(abi.lbm_set_multistep(self.h, steps))
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value is not None:

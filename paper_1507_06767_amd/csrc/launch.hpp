@@ -35,6 +35,12 @@ constexpr bool uses_zmarch() {
 template <int Q, typename T, typename C, bool SH>
 void launch_step_kernel(const StepArgs<C> &a, const LaunchCfg &c);
 
+// Enqueues nsteps (1 .. kMultiMaxSteps) sensor-free ping-pong steps of a 2D
+// grid as one step_multi launch (a.src -> a.dst); a no-op for 3D lattices
+// and stochastic rounding, which the host never sends here.
+template <int Q, typename T, typename C, bool SH>
+void launch_multi_kernel(const StepArgs<C> &a, int nsteps, const LaunchCfg &c);
+
 #ifdef LBM_LAUNCH_DEFINITIONS
 template <bool ZM, int Q, typename T, typename C, bool SH, bool SENS, int SK, int MODEL, int BX, int SCH>
 void launch_one(hipStream_t st, const StepArgs<C> &a) {
@@ -69,6 +75,29 @@ void launch_scheme(const StepArgs<C> &a, const LaunchCfg &c) {
         case kStream: launch_sk<false, Q, T, C, SH, BX, kStream>(a, c); break;
         case kLocal: launch_sk<false, Q, T, C, SH, BX, kLocal>(a, c); break;
         default: launch_sk<false, Q, T, C, SH, BX, kPingPong>(a, c); break;
+    }
+}
+
+template <int Q, typename T, typename C, bool SH>
+void launch_multi_kernel(const StepArgs<C> &a, int nsteps, const LaunchCfg &c) {
+    if constexpr (Lattice<Q>::D == 2 && !Storage<T>::sr) {
+        const int ntx = (a.nx + kMultiTile - 1) / kMultiTile, nty = (a.ny + kMultiTile - 1) / kMultiTile;
+        const dim3 g(ntx * nty), b(kMultiEdge * kMultiEdge);
+        switch ((c.force ? kModelForce : 0) | (c.smag ? kModelSmag : 0)) {
+            case kModelForce:
+                hipLaunchKernelGGL((step_multi<Q, T, C, SH, kModelForce>), g, b, 0, c.stream, a, nsteps);
+                break;
+            case kModelSmag:
+                hipLaunchKernelGGL((step_multi<Q, T, C, SH, kModelSmag>), g, b, 0, c.stream, a, nsteps);
+                break;
+            case kModelForce | kModelSmag:
+                hipLaunchKernelGGL((step_multi<Q, T, C, SH, kModelForce | kModelSmag>), g, b, 0, c.stream, a,
+                                   nsteps);
+                break;
+            default: hipLaunchKernelGGL((step_multi<Q, T, C, SH, 0>), g, b, 0, c.stream, a, nsteps); break;
+        }
+    } else {
+        (void)a, (void)nsteps, (void)c;
     }
 }
 

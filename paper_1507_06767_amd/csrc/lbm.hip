@@ -229,6 +229,8 @@ struct lbm_blocks {
     bool avg_started;         // the sums were cleared by lbm_sensor_average_begin
     int64_t avg_samples;      // sensor steps summed since averaging began
     uint32_t wall_mask;
+    int multi;                // most sensor-free steps per step_multi launch (small 2D
+                              // ping-pong grids), 0: one launch per step
     int graph_chunk;          // steps per graph replay (even), 0: launch step by step
     hipGraphExec_t graph[2];  // graph_chunk steps, by buffer parity
     std::vector<int8_t> flags_host;
@@ -244,6 +246,8 @@ namespace {
 // kernel).  An explicit choice in the descriptor wins; under
 // LBM_STREAMING_AUTO the environment variable LBM_STREAMING=pingpong|inplace
 // overrides the size rule (tests run both schemes that way).
+bool multi_setting(const lbm_desc *d, const Layout &L);
+
 bool inplace_setting(const lbm_desc *d, const Layout &L) {
     if (d->lattice != LBM_D2Q9 && d->storage == LBM_F64) return false;
     if (d->streaming == LBM_STREAMING_PINGPONG) return false;
@@ -251,7 +255,20 @@ bool inplace_setting(const lbm_desc *d, const Layout &L) {
     const char *s = std::getenv("LBM_STREAMING");
     if (s && std::strcmp(s, "pingpong") == 0) return false;
     if (s && std::strcmp(s, "inplace") == 0) return true;
+    if (multi_setting(d, L)) return false;   // small 2D grids: ping-pong, several steps per launch
     return L.bytes[LBM_BUF_F_A] <= (size_t(512) << 20);
+}
+
+// Several sensor-free steps per launch (step_multi, temporal blocking) for
+// 2D grids of at most kMultiMaxCells cells, whose single steps are too short
+// to fill the chip (4096 cells: 64 workgroups of 256 threads), in ping-pong
+// streaming, without stochastic rounding (its random bits key on the step
+// index); lbm_set_multistep switches it off or changes the step count.  Both
+// faces of an axis are walls or both periodic (checked at creation).
+constexpr int64_t kMultiMaxCells = int64_t(1) << 16;
+bool multi_setting(const lbm_desc *d, const Layout &L) {
+    if (d->lattice != LBM_D2Q9 || L.cells > kMultiMaxCells) return false;
+    return d->storage != LBM_F16_SHIFTED_SR && d->storage != LBM_BF16_SHIFTED_SR;
 }
 
 // Buffer the step kernel reads.
@@ -448,6 +465,35 @@ void launch_step_any(lbm_blocks *h, bool sens) {
     else launch_step_q<27>(h, sens);
 }
 
+template <typename T, typename C, bool SH>
+void launch_multi(lbm_blocks *h, int m) {
+    LaunchCfg c;
+    c.stream = h->stream;
+    c.tile_x = h->tile_x;
+    c.scheme = kPingPong;
+    c.sensor = false;
+    c.sensor_kind = h->d.sensor_kind;
+    c.force = h->has_force;
+    c.smag = h->d.smagorinsky > 0.0;
+    const StepArgs<C> a = step_args<9, C>(h, state_ptr(h), h->d.buf[h->cur ? LBM_BUF_F_A : LBM_BUF_F_B], false,
+                                          h->tile_x);
+    launch_multi_kernel<9, T, C, SH>(a, m, c);
+}
+
+// m (2 .. h->multi) sensor-free steps in one step_multi launch: the state
+// moves to the other buffer once, whatever m.
+void multi_once(lbm_blocks *h, int m) {
+    switch (h->d.storage) {
+        case LBM_F64: launch_multi<double, double, false>(h, m); break;
+        case LBM_F32: launch_multi<float, float, false>(h, m); break;
+        case LBM_F32_SHIFTED: launch_multi<float, float, true>(h, m); break;
+        case LBM_F16_SHIFTED: launch_multi<_Float16, float, true>(h, m); break;
+        default: launch_multi<__bf16, float, true>(h, m); break;   // LBM_BF16_SHIFTED
+    }
+    h->cur ^= 1;
+    h->step += m;
+}
+
 void drop_graphs(lbm_blocks *h) {
     for (int p = 0; p < 2; ++p)
         if (h->graph[p]) {
@@ -468,11 +514,26 @@ void step_once(lbm_blocks *h, int32_t sensor_every) {
     if (sens && h->averaging) ++h->avg_samples;
 }
 
+// c >= 2 sensor-free steps in an even number of step_multi launches (so that
+// the state ends in the buffer it started in, as a captured graph needs) of
+// at most h->multi steps each, as even as possible.
+void multi_run(lbm_blocks *h, int64_t c) {
+    int64_t nl = (c + h->multi - 1) / h->multi;
+    if (nl % 2) ++nl;   // c even (graph chunks): nl <= c
+    for (int64_t l = 0; l < nl; ++l) {
+        const int64_t m = c / nl + (l < c % nl ? 1 : 0);
+        if (m >= 2) multi_once(h, (int)m);
+        else step_once(h, 0);
+    }
+}
+
 // Captures graph_chunk sensor-free steps for the current buffer parity.
 lbm_status capture_steps(lbm_blocks *h, int parity) {
     const int64_t s0 = h->step;
     HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < h->graph_chunk; ++k) step_once(h, 0);
+    if (h->multi) multi_run(h, h->graph_chunk);
+    else
+        for (int k = 0; k < h->graph_chunk; ++k) step_once(h, 0);
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamEndCapture(h->stream, &g));
     h->step = s0;   // captured, not run; an even chunk leaves the parity as it was
@@ -556,6 +617,7 @@ lbm_status lbm_create_blocks(const lbm_desc *d, const double *f0_host, lbm_block
     h->has_force = d->force[0] != 0.0 || d->force[1] != 0.0 || d->force[2] != 0.0;
     h->wall_mask = 0;
     h->graph_chunk = 0;
+    h->multi = (!h->inplace && multi_setting(d, L)) ? kMultiMaxSteps : 0;
     h->graph[0] = h->graph[1] = nullptr;
     for (int f = 0; f < 6; ++f)
         if (d->face_bc[f] == LBM_BC_WALL) h->wall_mask |= 1u << f;
@@ -608,6 +670,17 @@ lbm_status lbm_step_n(lbm_blocks *h, int64_t n, int32_t sensor_every) {
             h->step += c;
             k += c;
             continue;
+        }
+        if (h->multi && !h->averaging) {
+            // the sensor-free steps before the next sensor step, in one launch
+            int64_t r = n - k;
+            if (sensor_every > 0) r = std::min(r, sensor_every - 1 - h->step % sensor_every);
+            if (r >= 2) {
+                const int m = (int)std::min<int64_t>(r, h->multi);
+                multi_once(h, m);
+                k += m;
+                continue;
+            }
         }
         step_once(h, sensor_every);
         ++k;
@@ -824,6 +897,26 @@ lbm_status lbm_get_scheme(lbm_blocks *h, int32_t *inplace, int32_t *next_is_gath
     if (inplace) *inplace = h->inplace ? 1 : 0;
     if (next_is_gather) *next_is_gather = (h->inplace && h->phase == 0) ? 1 : 0;
     if (tile_x) *tile_x = h->tile_x;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_multistep(lbm_blocks *h, int32_t steps) {
+    lbm_status st = check_handle(h);
+    if (st != LBM_OK) return st;
+    if (steps != 0 && (steps < 2 || steps > kMultiMaxSteps))
+        return fail(LBM_EINVAL, "steps = %d: 0 (off) or 2 .. %d", steps, kMultiMaxSteps);
+    if (steps > 0 && (h->inplace || !multi_setting(&h->d, h->L)))
+        return fail(LBM_ENOTSUP, "several steps per launch need a ping-pong D2Q9 handle of at most %lld cells "
+                                 "without stochastic rounding", (long long)kMultiMaxCells);
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    drop_graphs(h);   // captured with the old setting
+    h->multi = steps;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_multistep(lbm_blocks *h, int32_t *steps) {
+    if (!h || !steps) return fail(LBM_EINVAL, "NULL argument");
+    *steps = h->multi;
     return LBM_OK;
 }
 

@@ -11,4 +11,5 @@
 
 namespace lbm {
 template void launch_step_kernel<LBM_Q, LBM_T, LBM_C, LBM_SH>(const StepArgs<LBM_C> &, const LaunchCfg &);
+template void launch_multi_kernel<LBM_Q, LBM_T, LBM_C, LBM_SH>(const StepArgs<LBM_C> &, int, const LaunchCfg &);
 }  // namespace lbm

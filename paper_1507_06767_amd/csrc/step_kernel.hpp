@@ -458,11 +458,13 @@ __device__ __forceinline__ void store_pop(const StepArgs<C> &a, const Geo<C> &g,
     }
 }
 
-// Moments, equilibrium, sensor, BGK + Guo collision and the store of one
-// cell.  Returns the cell's sensor value: ||f^neq||^2 / ||f^eq||^2 (L2; the
-// square root is taken once per block) or K_Kn.
-template <int Q, typename T, typename C, bool SHIFTED, bool SENSOR, int SKIND, int MODEL, int SCHEME>
-__device__ __forceinline__ C collide_store(const StepArgs<C> &a, const Geo<C> &g, const C (&d)[Q]) {
+// Moments, equilibrium, sensor and BGK + Guo collision of one cell; each
+// post-collision value (a shifted population plus shift for the plain
+// storages) goes to sink(integral_constant<I>, value, cell key).  Returns the
+// cell's sensor value: ||f^neq||^2 / ||f^eq||^2 (L2; the square root is taken
+// once per block) or K_Kn.
+template <int Q, typename T, typename C, bool SHIFTED, bool SENSOR, int SKIND, int MODEL, typename Sink>
+__device__ __forceinline__ C collide(const StepArgs<C> &a, const Geo<C> &g, const C (&d)[Q], Sink &&sink) {
     constexpr bool FORCE = (MODEL & kModelForce) != 0;
     constexpr bool SMAG = (MODEL & kModelSmag) != 0;
     // moments (Eqs. rho and u), Guo's half-force shift
@@ -534,7 +536,7 @@ __device__ __forceinline__ C collide_store(const StepArgs<C> &a, const Geo<C> &g
             out += guo * wmul<C, V::w>(C(3) * (cF - uF) + C(9) * cu * cF);
         }
         if constexpr (!SHIFTED) out += a.shift[i];
-        store_pop<Q, i, T, C, SCHEME>(a, g, out, ckey);
+        sink(ic, out, ckey);
     };
     // rest population: xi = 0
     relax(std::integral_constant<int, 0>{}, drho + (a.rho0 * m15usq + drho * m15usq), C(0));
@@ -554,6 +556,14 @@ __device__ __forceinline__ C collide_store(const StepArgs<C> &a, const Geo<C> &g
         else return kkn * C(1.0 / Q);
     }
     return C(0);
+}
+
+// collide with the stores of the streaming scheme.
+template <int Q, typename T, typename C, bool SHIFTED, bool SENSOR, int SKIND, int MODEL, int SCHEME>
+__device__ __forceinline__ C collide_store(const StepArgs<C> &a, const Geo<C> &g, const C (&d)[Q]) {
+    return collide<Q, T, C, SHIFTED, SENSOR, SKIND, MODEL>(a, g, d, [&](auto ic, C out, uint32_t ckey) {
+        store_pop<Q, decltype(ic)::value, T, C, SCHEME>(a, g, out, ckey);
+    });
 }
 
 // Refine / keep / coarsen decision of a block maximum (non-finite: 2).
@@ -729,6 +739,85 @@ __global__ __launch_bounds__(BX *kTileY) void step_zmarch(const StepArgs<C> a) {
             const int bx = tix * (BX / kBlockEdge) + (int)threadIdx.x;
             if (bx < a.nbx) write_block(a, (tiz * a.nby + tiy) * a.nbx + bx, finish<SKIND>(M));
         }
+    }
+}
+
+// Several sensor-free ping-pong steps of a 2D grid in one launch (temporal
+// blocking), for grids too small to fill the chip, where a step lasts about
+// as long as the latency of one small kernel.  A workgroup owns a tile of
+// kMultiTile x kMultiTile cells and steps it together with a halo of
+// kMultiHalo cells on every side, one cell per thread, keeping the
+// post-collision populations in LDS between steps (two buffers, one barrier
+// per step).  The first step pulls from global memory exactly as step_cells
+// does; each later one pulls from the neighbours' LDS slots, a bounced link
+// from the cell's own opposite slot with the moving-wall term, and the last
+// stores the tile's own cells to the other buffer.  Across a periodic axis
+// the halo holds the wrapped cells; across a wall it lies outside the grid
+// and is never pulled from.  The outermost ring of the halo pulls from
+// beyond it and so turns wrong one cell deeper at every step after the
+// first: nsteps <= kMultiHalo + 1 leaves the tile exact.  The values kept in
+// LDS are the stored values of the storage type, and the arithmetic is
+// collide's, so the result equals nsteps launches of step_cells bit for bit.
+constexpr int kMultiTile = 8;
+constexpr int kMultiHalo = 4;
+constexpr int kMultiEdge = kMultiTile + 2 * kMultiHalo;   // one cell per thread
+constexpr int kMultiMaxSteps = kMultiHalo + 1;
+
+template <int Q, typename T, typename C, bool SHIFTED, int MODEL>
+__global__ __launch_bounds__(kMultiEdge *kMultiEdge) void step_multi(const StepArgs<C> a, int nsteps) {
+    static_assert(Lattice<Q>::D == 2, "temporal blocking is for 2D grids");
+    static_assert(!Storage<T>::sr, "stochastic rounding keys on the step index");
+    using R = typename Storage<T>::raw;
+    constexpr int E = kMultiEdge, NC = E * E;
+    __shared__ R pop[2][Q * NC];
+    const int me = threadIdx.x;
+    const int ex = me % E, ey = me / E;
+    const int ntx = (a.nx + kMultiTile - 1) / kMultiTile;
+    const int x0 = (int)(blockIdx.x % ntx) * kMultiTile, y0 = (int)(blockIdx.x / ntx) * kMultiTile;
+    const int ux = x0 - kMultiHalo + ex, uy = y0 - kMultiHalo + ey;   // unwrapped coordinates
+    // an axis is periodic when neither of its faces is a wall (the host runs
+    // this kernel only when both are, or neither)
+    const int x = (a.wall & 3u) ? ux : ((ux % a.nx) + a.nx) % a.nx;
+    const int y = (a.wall & 12u) ? uy : ((uy % a.ny) + a.ny) % a.ny;
+    const bool inside = x >= 0 && x < a.nx && y >= 0 && y < a.ny;
+    const bool own = ex >= kMultiHalo && ex < kMultiHalo + kMultiTile && ey >= kMultiHalo &&
+                     ey < kMultiHalo + kMultiTile && ux < a.nx && uy < a.ny;
+    Geo<C> g{};
+    if (inside) g = make_geo<2>(a, x, y, 0);
+    int cur = 0;
+#pragma unroll 1
+    for (int s = 0; s < nsteps; ++s) {
+        if (inside) {
+            C d[Q];
+            if (s == 0) {
+                load_cell<Q, T, C, SHIFTED, kPingPong>(a, g, d);
+            } else {
+                static_for<0, Q>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    using V = Vel<Q, i>;
+                    const Link<C> l = link<Q, i>(a, g);
+                    // the halo's outer ring reads a clamped (wrong, unused) neighbour
+                    const int sx = min(max(ex - V::x, 0), E - 1), sy = min(max(ey - V::y, 0), E - 1);
+                    const R raw = l.wall ? pop[cur][V::opp * NC + me] : pop[cur][i * NC + sy * E + sx];
+                    C v = static_cast<C>(raw);
+                    if constexpr (!SHIFTED) v -= a.shift[i];
+                    if constexpr (i == 0) d[i] = v;
+                    else d[i] = v + l.corr;
+                });
+            }
+            if (s == nsteps - 1) {
+                if (own)
+                    collide<Q, T, C, SHIFTED, false, kSensorL2, MODEL>(a, g, d, [&](auto ic, C out, uint32_t ckey) {
+                        store_pop<Q, decltype(ic)::value, T, C, kPingPong>(a, g, out, ckey);
+                    });
+            } else {
+                collide<Q, T, C, SHIFTED, false, kSensorL2, MODEL>(a, g, d, [&](auto ic, C out, uint32_t) {
+                    pop[cur ^ 1][decltype(ic)::value * NC + me] = to_storage<T>(out, 0u);
+                });
+            }
+        }
+        cur ^= 1;
+        if (s + 1 < nsteps) __syncthreads();
     }
 }
 
