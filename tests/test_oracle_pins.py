@@ -463,10 +463,57 @@ def test_level_map_buffer_layer(orc):
     assert (lev2 == expected2).all()
 
 
+@pytest.mark.parametrize("kind", [0, 1], ids=["L2", "KKn"])
+def test_time_averaged_sensor_matches_brute_force(orc, kind):
+    """Sec. 5.1 averages the cell sensor over time before building the mesh:
+    the oracle's running mean over the sensor steps after `start` equals the
+    mean of the sensors of brute.py (pull, SoA, its own equilibrium and
+    sensor), summed step by step in numpy, on a moving-lid cavity with a body
+    force (a skipped sample, an off-by-one in the window or a sum that is not
+    divided by the count fails it)."""
+    from oracle import brute
+    n = (11, 9, 1)
+    bc = (WALL, WALL, WALL, WALL, PERIODIC, PERIODIC)
+    wall_u = [[0.0] * 3 for _ in range(6)]
+    wall_u[3][0] = 0.08
+    F = (1e-4, -5e-5, 0.0)
+    G = orc.Grid(q=9, n=n, bc=bc, wall_u=wall_u, tau=0.66, force=F, sensor_kind=kind)
+    S0 = G.equilibrium_state(u=lbm_inputs.velocity_perturbation(n, 0.02, seed=8, dims=2))
+    # the window opens after step 9, itself a sensor step: samples 12, 15, ..., 39
+    S, mean, cnt = G.sensor_history(S0, 0, 40, 3, start=9)
+    assert cnt == 10
+    acc, Sb = np.zeros(G.shape), S0.copy()
+    for k in range(1, 41):
+        f = brute.stream(Sb, 9, n, bc, wall_u, 1.0)
+        if k % 3 == 0 and k > 9:
+            acc += brute.sensor(f, 9, F, kind)
+        Sb = brute.collide(f, 9, 0.66, F)
+    assert np.abs(mean - acc / 10).max() <= 1e-12 * np.abs(acc / 10).max()
+    assert np.abs(S - Sb).max() < 1e-14
+
+
+def test_time_averaged_sensor_of_a_steady_flow(orc):
+    """A flow that no longer changes has a time average equal to its
+    instantaneous sensor: forced Poiseuille flow between walls started from
+    its converged state, averaged over 50 steps, against the sensor of one
+    step (and at rest with no force and no moving wall the average is 0)."""
+    n = (4, 16, 1)
+    bc = (PERIODIC, PERIODIC, WALL, WALL, PERIODIC, PERIODIC)
+    F = (2e-6, 0.0, 0.0)
+    G = orc.Grid(q=9, n=n, bc=bc, wall_u=[[0.0] * 3 for _ in range(6)], tau=0.8, force=F)
+    S, _ = G.run(G.equilibrium_state(), 0, 6000, 0)
+    one = G.sensor(G.stream(S))
+    _, mean, cnt = G.sensor_history(S, 6000, 50, 1, start=6000)
+    assert cnt == 50 and one.max() > 1e-7
+    assert np.abs(mean - one).max() <= 1e-9 * one.max()
+    R = orc.Grid(q=9, n=n, bc=bc, wall_u=[[0.0] * 3 for _ in range(6)], tau=0.8)
+    _, mean0, _ = R.sensor_history(R.equilibrium_state(), 0, 12, 2, start=0)
+    assert np.abs(mean0).max() < 1e-15
+
+
 def test_time_averaged_sensor_matches_step_by_step(orc):
-    """Sec. 5.1 averages the sensor over time before building the mesh: the
-    running mean over sensor steps equals the mean of the per-step sensors
-    recomputed independently from stored states."""
+    """The running mean over sensor steps equals the mean of the per-step
+    sensors recomputed from stored states (the same oracle, step by step)."""
     n = (12, 10, 1)
     bc = (WALL, WALL, WALL, WALL, PERIODIC, PERIODIC)
     wall_u = [[0.0] * 3 for _ in range(6)]
