@@ -59,6 +59,7 @@ weight gradient) on 8, 32, 128 and 512 block grids of 16^3, each timed over
 20 graph-replayed launches; one JSON line with a row per batch.
 """
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -116,8 +117,23 @@ def host_env():
     except OSError:
         pass
     p = torch.cuda.get_device_properties(0)
+    rocm = None
+    try:
+        with open("/opt/rocm/.info/version") as fh:
+            rocm = fh.read().strip()
+    except OSError:
+        pass
+    clock = None
+    try:   # peak engine clock of device 0: hipDeviceGetAttribute(hipDeviceAttributeClockRate = 5), kHz
+        hip = ctypes.CDLL("libamdhip64.so")
+        khz = ctypes.c_int(0)
+        if hip.hipDeviceGetAttribute(ctypes.byref(khz), 5, 0) == 0:
+            clock = khz.value // 1000
+    except OSError:
+        pass
     return {"gpu": p.name, "gcn_arch": getattr(p, "gcnArchName", ""), "cus": p.multi_processor_count,
-            "hip": torch.version.hip, "torch": torch.__version__, "cpu": cpu, "cpu_count": os.cpu_count()}
+            "gpu_clock_mhz": clock, "rocm": rocm, "hip": torch.version.hip, "torch": torch.__version__,
+            "cpu": cpu, "cpu_count": os.cpu_count()}
 
 
 def copy_calibration(nbytes=1 << 30, reps=20):

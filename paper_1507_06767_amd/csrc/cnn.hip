@@ -406,6 +406,113 @@ __device__ __forceinline__ void conv_wgrad_ci_body(const float *x, const float *
     }
 }
 
+// The weight gradient for 16 (padded) input channels, three taps per
+// workgroup: the taps 3g, 3g + 1, 3g + 2 of one (z, y) offset, whose x
+// offsets are -1, 0, +1 (reduction columns 16 * tap .. + 15).  They share the
+// output-gradient operand, and their input operands are three overlapping
+// windows of one row, so a lane loads the gradient once and the 6 input
+// voxels x - 1 .. x + 4 of its channel once: 10 loads per voxel group
+// instead of 24 with one workgroup per tap (conv_wgrad_ci_body).  Each tap's
+// accumulation takes the same voxels, operands and order as there, so the
+// partials are the same bits; grid (nchunk, 9, co16 / 16).
+__device__ __forceinline__ void conv_wgrad_x3_body(const float *x, const float *gz, int n, int d, int h, int w,
+                                                   int ci, int co, float *work, int chunk, int g, int bc,
+                                                   int nchunk) {
+    constexpr int CI = 16, K16 = kTaps * CI;
+    const int co4 = pad4(co), co16 = pad16(co);
+    const int nv = n * d * h * w;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c0 = bc * 16;
+    const int r = lane & 15, kg = lane >> 4;
+    const bool col_ok = r < ci;                    // this lane's B column: input channel r
+    const int ocol = c0 + r;                       // this lane's A row (output channel)
+    const bool row_ok = ocol < co;
+    const int tdz = g / 3 - 1, tdy = g % 3 - 1;
+    f32x4 acc[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) acc[t] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+    float bsum = 0.0f;
+    const int vbeg = chunk * kWgradVoxels + wave * (kWgradVoxels / 4);
+    const int vend = min(vbeg + kWgradVoxels / 4, nv);
+    // the lane's 4 voxels of step 0: vq .. vq + 3, one row (w is a multiple of 4)
+    int vq = vbeg + 4 * kg;
+    Vox p = decompose(vq < nv ? vq : 0, d, h, w);
+    const float *gp = gz + (int64_t)vq * co4 + ocol;
+    const float *xp = x + ((int64_t)vq + (tdz * h + tdy) * w - 1) * CI + r;   // voxel x - 1 of the row
+    constexpr int kPass = 4;
+    for (int v0 = vbeg; v0 < vend; v0 += 16 * kPass) {
+        float a[kPass][4], b[kPass][6];
+#pragma unroll
+        for (int q = 0; q < kPass; ++q) {
+            // a group of 4 voxels lies wholly before vend or wholly after it
+            const bool vok = vq < vend;
+            const bool zy_ok = vok && col_ok && p.z + tdz >= 0 && p.z + tdz < d && p.y + tdy >= 0 && p.y + tdy < h;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool oka = vok && row_ok;
+                const float av = *(oka ? gp + j * co4 : gz);
+                a[q][j] = oka ? av : 0.0f;
+            }
+#pragma unroll
+            for (int m = 0; m < 6; ++m) {
+                const int xx = p.x + m - 1;
+                const bool okb = zy_ok && xx >= 0 && xx < w;
+                const float bv = *(okb ? xp + m * CI : x);
+                b[q][m] = okb ? bv : 0.0f;
+            }
+            // the next 16 voxels
+            vq += 16;
+            gp += 16 * co4;
+            xp += 16 * CI;
+            p.x += 16;
+            while (p.x >= w) {
+                p.x -= w;
+                if (++p.y == h) {
+                    p.y = 0;
+                    if (++p.z == d) p.z = 0;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kPass; ++q)
+            if (v0 + 16 * q < vend) {
+                bsum += ((a[q][0] + a[q][1]) + a[q][2]) + a[q][3];
+                const bf16x4 A = to_bf16x4(a[q][0], a[q][1], a[q][2], a[q][3]);
+#pragma unroll
+                for (int t = 0; t < 3; ++t)   // x offset t - 1: voxels j + t - 1 of the window
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+                        A, to_bf16x4(b[q][t], b[q][t + 1], b[q][t + 2], b[q][t + 3]), acc[t], 0, 0, 0);
+            }
+    }
+    __shared__ float tile[3][4][16][16];
+    __shared__ float bias[4][4][16];   // [wave][lane group][channel]
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) tile[t][wave][4 * kg + j][r] = acc[t][j];
+    bias[wave][kg][r] = bsum;
+    __syncthreads();
+    const int t = threadIdx.x;   // 256 threads = one 16x16 tile
+    const int row = t / 16, col = t % 16;
+#pragma unroll
+    for (int tt = 0; tt < 3; ++tt) {
+        const float sum = ((tile[tt][0][row][col] + tile[tt][1][row][col]) + tile[tt][2][row][col]) +
+                          tile[tt][3][row][col];
+        work[((int64_t)chunk * co16 + c0 + row) * K16 + (3 * g + tt) * 16 + col] = sum;
+    }
+    if (g == 0 && t < 16) {
+        float bb = 0.0f;
+        for (int wv = 0; wv < 4; ++wv)
+            for (int q = 0; q < 4; ++q) bb += bias[wv][q][t];
+        work[(int64_t)nchunk * co16 * K16 + (int64_t)chunk * co16 + c0 + t] = bb;
+    }
+}
+
+__global__ __launch_bounds__(256) void conv_wgrad_x3(const float *x, const float *gz, int n, int d, int h, int w,
+                                                     int ci, int co, float *work) {
+    conv_wgrad_x3_body(x, gz, n, d, h, w, ci, co, work, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x);
+}
+
 template <int CI>
 __global__ __launch_bounds__(256) void conv_wgrad_ci(const float *x, const float *gz, int n, int d, int h, int w,
                                                      int ci, int co, float *work) {
@@ -427,8 +534,12 @@ __global__ __launch_bounds__(256) void backward_layer_kernel(const float *x, con
     const int nwg = nchunk * nk * nc;
     const int b = blockIdx.x;
     if (b < nwg) {
-        conv_wgrad_ci_body<CIW>(x, gz, n, d, h, w, ci, co, work, b % nchunk, (b / nchunk) % nk, b / (nchunk * nk),
-                                nchunk);
+        if constexpr (CIW == 16)   // nk = 9 groups of three taps
+            conv_wgrad_x3_body(x, gz, n, d, h, w, ci, co, work, b % nchunk, (b / nchunk) % nk, b / (nchunk * nk),
+                               nchunk);
+        else
+            conv_wgrad_ci_body<CIW>(x, gz, n, d, h, w, ci, co, work, b % nchunk, (b / nchunk) % nk,
+                                    b / (nchunk * nk), nchunk);
     } else {
         const int f = b - nwg;
         conv_forward_ci_body<CIF>(gz, n, d, h, w, packed_flip, ci, nullptr, 0, mask, gin, f % fx, f / fx);
@@ -664,7 +775,8 @@ void launch_wgrad(const float *x, const float *gz, int n, int d, int h, int wd, 
                   int nchunk, hipStream_t st) {
     const dim3 grid(nchunk, pad16(kTaps * pad4(ci)) / 16, pad16(co) / 16);
     if (wd % 4 == 0 && pad4(ci) == 16)
-        hipLaunchKernelGGL(conv_wgrad_ci<16>, grid, dim3(256), 0, st, x, gz, n, d, h, wd, ci, co, work);
+        hipLaunchKernelGGL(conv_wgrad_x3, dim3(nchunk, kTaps / 3, pad16(co) / 16), dim3(256), 0, st, x, gz, n, d, h,
+                           wd, ci, co, work);
     else if (wd % 4 == 0 && pad4(ci) == 4)
         hipLaunchKernelGGL(conv_wgrad_ci<4>, grid, dim3(256), 0, st, x, gz, n, d, h, wd, ci, co, work);
     else
@@ -749,11 +861,13 @@ int32_t lbm_cnn_backward_layer(const float *x, const float *gz, int32_t n, int32
     const int64_t nv = (int64_t)n * d * h * wd;
     if (nv >= (int64_t(1) << 31)) return -1;
     const int nchunk = (int)((nv + kWgradVoxels - 1) / kWgradVoxels);
-    const int nk = pad16(kTaps * pad4(ci)) / 16, nc = pad16(co) / 16;
+    const int wi = pad4(ci), fi = pad4(co);
+    // weight-gradient workgroups per (chunk, output tile): 16-column tiles, or
+    // for 16 input channels groups of three taps
+    const int nk = wi == 16 ? kTaps / 3 : pad16(kTaps * wi) / 16, nc = pad16(co) / 16;
     const int fx = (int)blocks_for(nv, 64), fy = pad16(ci) / 16;
     const int64_t total = (int64_t)nchunk * nk * nc + (int64_t)fx * fy;
     hipStream_t st = (hipStream_t)stream;
-    const int wi = pad4(ci), fi = pad4(co);
     if (wd % 4 == 0 && (wi == 4 || wi == 16) && (fi == 4 || fi == 16) && total < (int64_t(1) << 31)) {
         auto go = [&](auto kern) {
             hipLaunchKernelGGL(kern, dim3((unsigned)total), dim3(256), 0, st, x, gz, n, d, h, wd, ci, co, work,
