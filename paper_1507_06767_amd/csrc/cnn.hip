@@ -146,6 +146,24 @@ __global__ __launch_bounds__(256) void conv_forward_kernel(const float *x, int n
 // conv_forward_kernel: the same bits.
 // (Workgroup (bx, by) of the launch: voxel tiles 4 bx .. 4 bx + 3, output
 // channels 16 by ..; a body of its own so that a fused launch can run it.)
+// Bias, ReLU, mask and store of a forward output tile: lane (r, kg) holds
+// voxels v0 + 4 kg .. + 3 of output channel co0 + r.
+__device__ __forceinline__ void store_tile(const f32x4 &acc, int v0, int nv, int co0, int r, int kg, int co,
+                                           int co4, const float *bias, int relu, const float *mask, float *y) {
+    const int oc = co0 + r;
+    if (oc >= co4) return;
+    const float b = (bias && oc < co) ? bias[oc] : 0.0f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int v = v0 + 4 * kg + j;
+        if (v >= nv) continue;
+        float o = acc[j] + b;
+        if (relu) o = o > 0.0f ? o : 0.0f;
+        if (mask) o = mask[(int64_t)v * co4 + oc] > 0.0f ? o : 0.0f;
+        y[(int64_t)v * co4 + oc] = o;
+    }
+}
+
 template <int CI>
 __device__ __forceinline__ void conv_forward_ci_body(const float *x, int n, int d, int h, int w,
                                                      const uint16_t *packed, int co, const float *bias, int relu,
@@ -169,6 +187,50 @@ __device__ __forceinline__ void conv_forward_ci_body(const float *x, int n, int 
     const float *xb = x + (int64_t)(vok ? va : 0) * CI + (CI == 16 ? 4 * kg : 0);
     const uint16_t *wrow = packed + (int64_t)(co0 + r) * K16 + 4 * kg;
     f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    if constexpr (CI == 16) {
+        if (w == 16) {
+            // A tile's 16 voxels are one whole grid row (v0 is a multiple of
+            // 16 = w), lane r holding x = r.  The taps 3g, 3g + 1, 3g + 2 of
+            // one (z, y) offset read the same row of the input shifted by x
+            // offsets -1, 0, +1, and a shift of one voxel is a shift of one
+            // lane within each 16-lane row of the operand: load the 9 rows
+            // once and form the other two taps' operands with DPP row shifts
+            // (zero where the shift leaves the row: x = -1 or 16, outside
+            // the grid).  The operands, and so the bits, are those of the
+            // general loop below.  (A row past nv cannot occur: nv is a
+            // multiple of 16.)
+            float4 a[9];
+            bool rok[9];
+            bf16x4 B[kTaps];
+#pragma unroll
+            for (int g = 0; g < 9; ++g) {
+                const int dz = g / 3, dy = g % 3;
+                rok[g] = vok && zok[dz] && yok[dy];
+                const int off = ((dz - 1) * hw + (dy - 1) * w) * CI;
+                a[g] = *reinterpret_cast<const float4 *>(xb + (rok[g] ? off : 0));
+            }
+#pragma unroll
+            for (int s = 0; s < kTaps; ++s) B[s] = *reinterpret_cast<const bf16x4 *>(wrow + 16 * s);
+#pragma unroll
+            for (int g = 0; g < 9; ++g) {
+                const bf16x4 zero = {0, 0, 0, 0};
+                const bf16x4 A = rok[g] ? to_bf16x4(a[g].x, a[g].y, a[g].z, a[g].w) : zero;
+                const int2 ai = __builtin_bit_cast(int2, A);
+                // row_shr:1 (lane r takes lane r - 1) and row_shl:1 (lane r + 1), 0 at the row's end
+                const int2 lo = {__builtin_amdgcn_update_dpp(0, ai.x, 0x111, 0xF, 0xF, true),
+                                 __builtin_amdgcn_update_dpp(0, ai.y, 0x111, 0xF, 0xF, true)};
+                const int2 hi = {__builtin_amdgcn_update_dpp(0, ai.x, 0x101, 0xF, 0xF, true),
+                                 __builtin_amdgcn_update_dpp(0, ai.y, 0x101, 0xF, 0xF, true)};
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(bf16x4, lo), B[3 * g], acc, 0, 0,
+                                                                0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B[3 * g + 1], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(bf16x4, hi), B[3 * g + 2], acc, 0,
+                                                                0, 0);
+            }
+            store_tile(acc, v0, nv, co0, r, kg, co, co4, bias, relu, mask, y);
+            return;
+        }
+    }
     constexpr int kPass = 9;
 #pragma unroll
     for (int s0 = 0; s0 < NK; s0 += kPass) {
@@ -196,18 +258,7 @@ __device__ __forceinline__ void conv_forward_ci_body(const float *x, int n, int 
                 acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ok[q] ? A : zero, B[q], acc, 0, 0, 0);
             }
     }
-    const int oc = co0 + r;
-    if (oc >= co4) return;
-    const float b = (bias && oc < co) ? bias[oc] : 0.0f;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int v = v0 + 4 * kg + j;
-        if (v >= nv) continue;
-        float o = acc[j] + b;
-        if (relu) o = o > 0.0f ? o : 0.0f;
-        if (mask) o = mask[(int64_t)v * co4 + oc] > 0.0f ? o : 0.0f;
-        y[(int64_t)v * co4 + oc] = o;
-    }
+    store_tile(acc, v0, nv, co0, r, kg, co, co4, bias, relu, mask, y);
 }
 
 // Weight gradient partials.  Workgroup (chunk, kt, ct): output channels
