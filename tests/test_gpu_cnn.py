@@ -62,7 +62,8 @@ def _forward(torch, cnn, x, w, b, relu, flip=False):
 # entries within a step when a row is shorter than 16); rows of 16 voxels, as
 # in the predictor's block grids, with 4 and 16 channels
 _SHAPES = [((2, 5, 6, 7), 5, 16), ((1, 9, 4, 11), 16, 16), ((3, 3, 5, 4), 16, 1), ((1, 16, 16, 16), 16, 7),
-           ((2, 5, 6, 7), 3, 16), ((2, 4, 3, 5), 4, 5), ((2, 3, 5, 16), 4, 16), ((3, 2, 8, 16), 16, 20)]
+           ((2, 5, 6, 7), 3, 16), ((2, 4, 3, 5), 4, 5), ((2, 3, 5, 16), 4, 16), ((3, 2, 8, 16), 16, 20),
+           ((2, 3, 4, 16), 13, 16)]
 _DSHAPES = _SHAPES[:3] + [((2, 3, 5, 16), 16, 1), ((1, 4, 6, 16), 16, 16)]
 
 
@@ -140,7 +141,7 @@ def test_conv_mask_is_relu_backward(env):
 
 # the fourth case: a wide layer (216 x 8 output tiles of 16 x 16)
 _WSHAPES = [((2, 5, 6, 7), 5, 16), ((1, 16, 16, 17), 16, 16), ((2, 8, 8, 8), 16, 1), ((1, 3, 4, 5), 128, 128),
-            ((2, 6, 8, 12), 4, 16), ((3, 5, 2, 4), 16, 16), ((2, 3, 3, 8), 3, 7)]
+            ((2, 6, 8, 12), 4, 16), ((3, 5, 2, 4), 16, 16), ((2, 3, 3, 8), 3, 7), ((2, 4, 4, 8), 13, 16)]
 
 
 @pytest.mark.parametrize("case", _WSHAPES, ids=[f"{c[0]}_{c[1]}to{c[2]}" for c in _WSHAPES])
