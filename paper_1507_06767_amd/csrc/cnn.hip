@@ -174,6 +174,16 @@ __device__ __forceinline__ void conv_forward_ci_body(const float *x, int n, int 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int v0 = (bx * 4 + wave) * 16;
     const int co0 = by * 16;
+    // the workgroup's weight operands, the same for its 4 tiles, staged once
+    // in LDS ([K step][lane], the lane layout of the MFMA operand) before any
+    // wave may leave
+    __shared__ bf16x4 wsh[NK * 64];
+    for (int e = threadIdx.x; e < NK * 64; e += 256) {
+        const int l = e & 63;
+        wsh[e] = *reinterpret_cast<const bf16x4 *>(packed + (int64_t)(co0 + (l & 15)) * K16 + 16 * (e >> 6) +
+                                                   4 * (l >> 4));
+    }
+    __syncthreads();
     if (v0 >= nv) return;
     const int r = lane & 15, kg = lane >> 4;
     const int va = v0 + r;
@@ -185,7 +195,7 @@ __device__ __forceinline__ void conv_forward_ci_body(const float *x, int n, int 
     const bool xok[3] = {pa.x > 0, true, pa.x < w - 1};
     const int hw = h * w;
     const float *xb = x + (int64_t)(vok ? va : 0) * CI + (CI == 16 ? 4 * kg : 0);
-    const uint16_t *wrow = packed + (int64_t)(co0 + r) * K16 + 4 * kg;
+    const bf16x4 *B = wsh + lane;   // B[64 s]: the weight operand of K step s
     f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
     if constexpr (CI == 16) {
         if (w == 16) {
@@ -201,7 +211,6 @@ __device__ __forceinline__ void conv_forward_ci_body(const float *x, int n, int 
             // multiple of 16.)
             float4 a[9];
             bool rok[9];
-            bf16x4 B[kTaps];
 #pragma unroll
             for (int g = 0; g < 9; ++g) {
                 const int dz = g / 3, dy = g % 3;
@@ -209,8 +218,6 @@ __device__ __forceinline__ void conv_forward_ci_body(const float *x, int n, int 
                 const int off = ((dz - 1) * hw + (dy - 1) * w) * CI;
                 a[g] = *reinterpret_cast<const float4 *>(xb + (rok[g] ? off : 0));
             }
-#pragma unroll
-            for (int s = 0; s < kTaps; ++s) B[s] = *reinterpret_cast<const bf16x4 *>(wrow + 16 * s);
 #pragma unroll
             for (int g = 0; g < 9; ++g) {
                 const bf16x4 zero = {0, 0, 0, 0};
@@ -221,11 +228,11 @@ __device__ __forceinline__ void conv_forward_ci_body(const float *x, int n, int 
                                  __builtin_amdgcn_update_dpp(0, ai.y, 0x111, 0xF, 0xF, true)};
                 const int2 hi = {__builtin_amdgcn_update_dpp(0, ai.x, 0x101, 0xF, 0xF, true),
                                  __builtin_amdgcn_update_dpp(0, ai.y, 0x101, 0xF, 0xF, true)};
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(bf16x4, lo), B[3 * g], acc, 0, 0,
-                                                                0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B[3 * g + 1], acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(bf16x4, hi), B[3 * g + 2], acc, 0,
-                                                                0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(bf16x4, lo), B[64 * (3 * g)], acc,
+                                                                0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B[64 * (3 * g + 1)], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(bf16x4, hi), B[64 * (3 * g + 2)],
+                                                                acc, 0, 0, 0);
             }
             store_tile(acc, v0, nv, co0, r, kg, co, co4, bias, relu, mask, y);
             return;
@@ -236,7 +243,6 @@ __device__ __forceinline__ void conv_forward_ci_body(const float *x, int n, int 
     for (int s0 = 0; s0 < NK; s0 += kPass) {
         float4 a[kPass];
         bool ok[kPass];
-        bf16x4 B[kPass];
 #pragma unroll
         for (int q = 0; q < kPass; ++q) {
             const int s = s0 + q;
@@ -246,7 +252,6 @@ __device__ __forceinline__ void conv_forward_ci_body(const float *x, int n, int 
                 ok[q] = vok && tap < kTaps && zok[dz] && yok[dy] && xok[dx];
                 const int off = ((dz - 1) * hw + (dy - 1) * w + (dx - 1)) * CI;
                 a[q] = *reinterpret_cast<const float4 *>(xb + (ok[q] ? off : 0));
-                B[q] = *reinterpret_cast<const bf16x4 *>(wrow + 16 * s);
             }
         }
 #pragma unroll
@@ -255,7 +260,7 @@ __device__ __forceinline__ void conv_forward_ci_body(const float *x, int n, int 
                 // outside the grid: zeros (the load above read the lane's own voxel)
                 const bf16x4 A = to_bf16x4(a[q].x, a[q].y, a[q].z, a[q].w);
                 const bf16x4 zero = {0, 0, 0, 0};
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ok[q] ? A : zero, B[q], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ok[q] ? A : zero, B[64 * (s0 + q)], acc, 0, 0, 0);
             }
     }
     store_tile(acc, v0, nv, co0, r, kg, co, co4, bias, relu, mask, y);
