@@ -164,7 +164,9 @@ __device__ __forceinline__ void store_tile(const f32x4 &acc, int v0, int nv, int
     }
 }
 
-template <int CI>
+// WAVES waves per workgroup, one 16-voxel tile each (8 in conv_forward_ci, 4
+// in the data-gradient part of backward_layer_kernel).
+template <int CI, int WAVES = 4>
 __device__ __forceinline__ void conv_forward_ci_body(const float *x, int n, int d, int h, int w,
                                                      const uint16_t *packed, int co, const float *bias, int relu,
                                                      const float *mask, float *y, int bx, int by) {
@@ -172,13 +174,13 @@ __device__ __forceinline__ void conv_forward_ci_body(const float *x, int n, int 
     const int co4 = pad4(co);
     const int nv = n * d * h * w;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int v0 = (bx * 4 + wave) * 16;
+    const int v0 = (bx * WAVES + wave) * 16;
     const int co0 = by * 16;
-    // the workgroup's weight operands, the same for its 4 tiles, staged once
+    // the workgroup's weight operands, the same for all its tiles, staged once
     // in LDS ([K step][lane], the lane layout of the MFMA operand) before any
     // wave may leave
     __shared__ bf16x4 wsh[NK * 64];
-    for (int e = threadIdx.x; e < NK * 64; e += 256) {
+    for (int e = threadIdx.x; e < NK * 64; e += 64 * WAVES) {
         const int l = e & 63;
         wsh[e] = *reinterpret_cast<const bf16x4 *>(packed + (int64_t)(co0 + (l & 15)) * K16 + 16 * (e >> 6) +
                                                    4 * (l >> 4));
@@ -365,10 +367,10 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(const float *x, const f
 }
 
 template <int CI>
-__global__ __launch_bounds__(256) void conv_forward_ci(const float *x, int n, int d, int h, int w,
+__global__ __launch_bounds__(512) void conv_forward_ci(const float *x, int n, int d, int h, int w,
                                                        const uint16_t *packed, int co, const float *bias,
                                                        int relu, const float *mask, float *y) {
-    conv_forward_ci_body<CI>(x, n, d, h, w, packed, co, bias, relu, mask, y, blockIdx.x, blockIdx.y);
+    conv_forward_ci_body<CI, 8>(x, n, d, h, w, packed, co, bias, relu, mask, y, blockIdx.x, blockIdx.y);
 }
 
 // The same weight-gradient partials for 4 or 16 (padded) input channels and
@@ -865,12 +867,12 @@ int32_t lbm_cnn_conv3d_forward(const float *x, int32_t n, int32_t d, int32_t h, 
     if (((uintptr_t)x) % 16 || ((uintptr_t)packed) % 8) return -1;
     const int64_t nv = (int64_t)n * d * h * wd;
     if (nv >= (int64_t(1) << 31)) return -1;
-    const dim3 grid(blocks_for(nv, 64), pad16(co) / 16);
+    const dim3 grid(blocks_for(nv, 64), pad16(co) / 16), grid8(blocks_for(nv, 128), pad16(co) / 16);
     if (pad4(ci) == 16)
-        hipLaunchKernelGGL(conv_forward_ci<16>, grid, dim3(256), 0, (hipStream_t)stream, x, n, d, h, wd, packed,
+        hipLaunchKernelGGL(conv_forward_ci<16>, grid8, dim3(512), 0, (hipStream_t)stream, x, n, d, h, wd, packed,
                            co, bias, relu, mask, y);
     else if (pad4(ci) == 4)
-        hipLaunchKernelGGL(conv_forward_ci<4>, grid, dim3(256), 0, (hipStream_t)stream, x, n, d, h, wd, packed,
+        hipLaunchKernelGGL(conv_forward_ci<4>, grid8, dim3(512), 0, (hipStream_t)stream, x, n, d, h, wd, packed,
                            co, bias, relu, mask, y);
     else
         hipLaunchKernelGGL(conv_forward_kernel, grid, dim3(256), 0, (hipStream_t)stream, x, n, d, h, wd, ci,
