@@ -601,12 +601,30 @@ __device__ __forceinline__ void coarse_to_fine(const CoarseView<C> &v, const C (
         const int dx = k & 1, dy = (k >> 1) & 1, dz = k >> 2;
         const C w = (dx ? fx : C(1) - fx) * (dy ? fy : C(1) - fy) * (dz ? fz : C(1) - fz);
         const int64_t cc = ((int64_t)(z0 + dz) * v.ny + (y0 + dy)) * v.nx + (x0 + dx);
-        static_for<0, Q>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            C s = load_dev<T>(v.s0, i * v.pitch + cc, shift[i], SH);
-            if (v.w1 != C(0)) s += v.w1 * (load_dev<T>(v.s1, i * v.pitch + cc, shift[i], SH) - s);
-            d[i] += w * s;
-        });
+        // the time-interpolation test outside the population loop (all loads
+        // of a corner in flight together)
+        C s0[Q];
+        if (v.w1 != C(0)) {
+            C s1[Q];
+            static_for<0, Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                s0[i] = load_dev<T>(v.s0, i * v.pitch + cc, shift[i], SH);
+                s1[i] = load_dev<T>(v.s1, i * v.pitch + cc, shift[i], SH);
+            });
+            static_for<0, Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                d[i] += w * (s0[i] + v.w1 * (s1[i] - s0[i]));
+            });
+        } else {
+            static_for<0, Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                s0[i] = load_dev<T>(v.s0, i * v.pitch + cc, shift[i], SH);
+            });
+            static_for<0, Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                d[i] += w * s0[i];
+            });
+        }
     }
     const Moments<Q, C> mo = moments_of<Q>(d, rho0);
     static_for<0, Q>([&](auto ic) {
@@ -675,12 +693,31 @@ __global__ __launch_bounds__(256) void patch_ghosts_lds(const PatchArgs<C> a, co
         const int cell = threadIdx.x;
         const int lx = cell % tl.dx, ly = (cell / tl.dx) % tl.dy, lz = cell / (tl.dx * tl.dy);
         const int64_t cc = ((int64_t)(tl.oz + lz) * v.ny + (tl.oy + ly)) * v.nx + (tl.ox + lx);
-        static_for<0, Q>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            C sv = load_dev<T>(v.s0, i * v.pitch + cc, a.shift[i], SH);
-            if (v.w1 != C(0)) sv += v.w1 * (load_dev<T>(v.s1, i * v.pitch + cc, a.shift[i], SH) - sv);
-            box[i * kGhostBox + cell] = sv;
-        });
+        // the time-interpolation test outside the population loop, so that all
+        // of a cell's loads are in flight before the first is used (a test
+        // per population had made the compiler wait for each load in turn)
+        C s0[Q];
+        if (v.w1 != C(0)) {
+            C s1[Q];
+            static_for<0, Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                s0[i] = load_dev<T>(v.s0, i * v.pitch + cc, a.shift[i], SH);
+                s1[i] = load_dev<T>(v.s1, i * v.pitch + cc, a.shift[i], SH);
+            });
+            static_for<0, Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                box[i * kGhostBox + cell] = s0[i] + v.w1 * (s1[i] - s0[i]);
+            });
+        } else {
+            static_for<0, Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                s0[i] = load_dev<T>(v.s0, i * v.pitch + cc, a.shift[i], SH);
+            });
+            static_for<0, Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                box[i * kGhostBox + cell] = s0[i];
+            });
+        }
     }
     __syncthreads();
     if ((int)threadIdx.x >= tl.n) return;
