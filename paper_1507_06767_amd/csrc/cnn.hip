@@ -84,6 +84,31 @@ __global__ void pack_kernel(const float *w, int co, int ci, int flip, uint16_t *
     out[idx] = __builtin_bit_cast(uint16_t, static_cast<__bf16>(v));
 }
 
+// Bias, ReLU, mask and store of a forward output tile: lane (r, kg) holds
+// voxels v0 + 4 kg .. + 3 of output channel co0 + r.
+__device__ __forceinline__ void store_tile(const f32x4 &acc, int v0, int nv, int co0, int r, int kg, int co,
+                                           int co4, const float *bias, int relu, const float *mask, float *y) {
+    const int oc = co0 + r;
+    if (oc >= co4) return;
+    const float b = (bias && oc < co) ? bias[oc] : 0.0f;
+    // the mask values of the 4 voxels loaded together (a load inside the
+    // store loop had been waited for voxel by voxel)
+    float mv[4] = {1.0f, 1.0f, 1.0f, 1.0f};
+    if (mask) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) mv[j] = mask[(int64_t)min(v0 + 4 * kg + j, nv - 1) * co4 + oc];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int v = v0 + 4 * kg + j;
+        if (v >= nv) continue;
+        float o = acc[j] + b;
+        if (relu) o = o > 0.0f ? o : 0.0f;
+        if (mask) o = mv[j] > 0.0f ? o : 0.0f;
+        y[(int64_t)v * co4 + oc] = o;
+    }
+}
+
 // One wave: 16 voxels x 16 output channels.  Four waves per workgroup, no
 // barriers, so a wave past the last voxel simply returns.
 __global__ __launch_bounds__(256) void conv_forward_kernel(const float *x, int n, int d, int h, int w, int ci,
@@ -122,18 +147,7 @@ __global__ __launch_bounds__(256) void conv_forward_kernel(const float *x, int n
                 acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(to_bf16x4(a[q].x, a[q].y, a[q].z, a[q].w), B[q],
                                                                 acc, 0, 0, 0);
     }
-    const int oc = co0 + r;
-    if (oc >= co4) return;
-    const float b = (bias && oc < co) ? bias[oc] : 0.0f;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int v = v0 + 4 * kg + j;
-        if (v >= nv) continue;
-        float o = acc[j] + b;
-        if (relu) o = o > 0.0f ? o : 0.0f;
-        if (mask) o = mask[(int64_t)v * co4 + oc] > 0.0f ? o : 0.0f;
-        y[(int64_t)v * co4 + oc] = o;
-    }
+    store_tile(acc, v0, nv, co0, r, kg, co, co4, bias, relu, mask, y);
 }
 
 // The same convolution for 4 or 16 (padded) input channels, the
@@ -146,23 +160,6 @@ __global__ __launch_bounds__(256) void conv_forward_kernel(const float *x, int n
 // conv_forward_kernel: the same bits.
 // (Workgroup (bx, by) of the launch: voxel tiles 4 bx .. 4 bx + 3, output
 // channels 16 by ..; a body of its own so that a fused launch can run it.)
-// Bias, ReLU, mask and store of a forward output tile: lane (r, kg) holds
-// voxels v0 + 4 kg .. + 3 of output channel co0 + r.
-__device__ __forceinline__ void store_tile(const f32x4 &acc, int v0, int nv, int co0, int r, int kg, int co,
-                                           int co4, const float *bias, int relu, const float *mask, float *y) {
-    const int oc = co0 + r;
-    if (oc >= co4) return;
-    const float b = (bias && oc < co) ? bias[oc] : 0.0f;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int v = v0 + 4 * kg + j;
-        if (v >= nv) continue;
-        float o = acc[j] + b;
-        if (relu) o = o > 0.0f ? o : 0.0f;
-        if (mask) o = mask[(int64_t)v * co4 + oc] > 0.0f ? o : 0.0f;
-        y[(int64_t)v * co4 + oc] = o;
-    }
-}
 
 // WAVES waves per workgroup, one 16-voxel tile each (8 in conv_forward_ci, 4
 // in the data-gradient part of backward_layer_kernel).
